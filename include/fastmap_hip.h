@@ -1,0 +1,213 @@
+/*
+ * fastmap_hip.h - C ABI of the MI355X (gfx950) epipolar-adjustment library.
+ *
+ * The operations follow FastMap (arXiv 2505.04612), Sec. 3.3 "Epipolar
+ * Adjustment" and App. B.6:
+ *
+ *   pairs      P = {(i_n, j_n)}, i_n is the first image of pair n, j_n the second;
+ *   matches    Q_n = {(x1_nm, x2_nm)}, normalised coordinates, homogeneous
+ *              x~ = (u, v, 1); x1 lies in image i_n, x2 in image j_n;
+ *   poses      world-to-camera R_i, t_i; the rotation is parameterised by two
+ *              3-vectors (a1, a2) mapped to R = [b1 b2 b3] by Gram-Schmidt
+ *              (the 6D representation the paper uses for global rotations);
+ *   E_n        [t_hat]_x R_ij, R_ij = R_j R_i^T, t_ij = t_j - R_ij t_i,
+ *              t_hat = t_ij / |t_ij|;
+ *   residual   r_nm = x2~^T E_n x1~ (the epipolar error of eq. epipolar-objective);
+ *   Gram       W_n = sum_m omega_nm w_nm w_nm^T, w_nm = flatten(x2~ x1~^T)
+ *              (row-major: w[3a+b] = x2~[a] x1~[b]), App. B.6;
+ *   loss       L = inv_Z * sum_n e_n^T W_n e_n, e_n = flatten(E_n) row-major
+ *              (eq. epipolar-objective-l2 without the stray factor 2, which the
+ *              derivation in App. B.6 does not produce);
+ *   IRLS       omega = 1/max(|r|, delta) if |r| <= tau, else 0 (filtered),
+ *              Z = number of matches with omega > 0 (Sec. 3.3, IRLS paragraph).
+ *
+ * Compact Gram layout ("W36").  W_{(ab),(cd)} = sum omega x2[a] x2[c] x1[b] x1[d]
+ * depends on the unordered index pairs {a,c} and {b,d} only.  With the monomial
+ * vector p(x) = (u^2, u v, v^2, u, v, 1) and q(a,c) the position of x~[a] x~[c]
+ * in p (q(0,0)=0, q(0,1)=1, q(1,1)=2, q(0,2)=3, q(1,2)=4, q(2,2)=5), the pair's
+ * Gram is stored as the 6x6 matrix
+ *     W36[n][6*q2 + q1] = sum_m omega_nm p(x2_nm)[q2] p(x1_nm)[q1],
+ * so W_{(ab),(cd)} = W36[n][6*q(a,c) + q(b,d)].  Entry 35 is sum_m omega_nm.
+ *
+ * Conventions for every call:
+ *   - all array arguments are DEVICE pointers on the context's device, except
+ *     where a comment says "host";  the caller owns every buffer;
+ *   - calls are asynchronous on the given stream (NULL = the null stream);
+ *     outputs are fully overwritten, never accumulated into;
+ *   - argument validation happens on the host before any launch and returns
+ *     FM_EINVAL / FM_ESHAPE / FM_EDTYPE with a message in fm_last_error();
+ *     nothing is launched when a call returns an error;
+ *   - results are deterministic: identical inputs on the same device and
+ *     build give bit-identical outputs (fixed reduction orders, no
+ *     floating-point atomics);
+ *   - one context per host thread; a scene may be used from one stream at a
+ *     time (it owns workspace the kernels write).
+ */
+#ifndef FASTMAP_HIP_H
+#define FASTMAP_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fm_ctx fm_ctx;       /* device handle + last error message        */
+typedef struct fm_scene fm_scene;   /* pair/match structure + derived index data */
+typedef void* fm_stream;            /* a hipStream_t                             */
+
+typedef enum {
+  FM_OK = 0,
+  FM_EINVAL = -1,        /* null pointer, bad scalar argument                      */
+  FM_ESHAPE = -2,        /* inconsistent sizes, offsets or camera indices          */
+  FM_EDTYPE = -3,        /* unsupported dtype                                      */
+  FM_EHIP = -4,          /* a HIP runtime call failed                              */
+  FM_ENOMEM = -5,        /* device allocation failed                               */
+  FM_ECOOP = -6          /* cooperative launch not possible for this size         */
+} fm_status;
+
+typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2 } fm_dtype;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`. */
+fm_status fm_create(fm_ctx** out, int device);
+void fm_destroy(fm_ctx* ctx);
+/* Message of the last failed call on this context (context-owned, valid until
+ * the next call). */
+const char* fm_last_error(const fm_ctx* ctx);
+/* Library build string (host, static storage). */
+const char* fm_version(void);
+
+/* ------------------------------------------------------------------ scene */
+
+/* The problem structure of Sec. 3.3: P image pairs over N cameras and M
+ * matches sorted by pair (CSR).
+ *   pair_offsets [P+1] int64: off[0] = 0, nondecreasing, off[P] = M; the
+ *                matches of pair n are rows off[n] .. off[n+1]-1;
+ *   pair_cams    [P,2] int32: (i_n, j_n), 0 <= i_n, j_n < N, i_n != j_n;
+ *   uv           [M,4] of `dtype` (FM_F64, FM_F32 or FM_BF16), row-major
+ *                (u1, v1, u2, v2): normalised coordinates of x1 (image i_n)
+ *                and x2 (image j_n).
+ * The scene borrows these three arrays (they must outlive it and must not be
+ * modified while it exists) and allocates its own index data and workspace
+ * (work-item table, camera incidence lists, partial sums).  Creation validates
+ * the offsets and camera indices on the device and synchronises `stream`;
+ * a violation returns FM_ESHAPE.  P may be 0; M may be 0. */
+fm_status fm_scene_create(fm_ctx* ctx, int64_t num_pairs, int64_t num_matches, int32_t num_cams,
+                          const int64_t* pair_offsets, const int32_t* pair_cams,
+                          const void* uv, fm_dtype dtype, fm_stream stream, fm_scene** out);
+void fm_scene_destroy(fm_scene* scene);
+/* Number of work items (pair chunks of up to 1024 matches) the Gram build
+ * launches; host value. */
+int64_t fm_scene_work_items(const fm_scene* scene);
+
+/* ------------------------------------------------------------------ a1: Gram */
+
+/* build_pair_grams (App. B.6): W36[n] for every pair, with per-match weights
+ * `weights` [M] float32 (NULL = all ones).
+ *   W36_f64 [P,36] double  (may be NULL if W36_f32 is given)
+ *   W36_f32 [P,36] float   (may be NULL if W36_f64 is given; the float copy
+ *                           of the double result)
+ * Per-match products and their sums within a work item are float32; the
+ * work-item partials are added in float64 in work-item order.  A pair
+ * without matches gets zeros. */
+fm_status fm_build_pair_grams(fm_ctx* ctx, fm_scene* scene, const float* weights,
+                              double* W36_f64, float* W36_f32, fm_stream stream);
+
+/* ------------------------------------------------------------------ a2: IRLS */
+
+/* reweight (Sec. 3.3, IRLS and filtering): at poses `params` [N,9] float32
+ * (a1[3], a2[3], t[3] per camera) compute r = x2~^T E_n x1~ per match and
+ * omega = 1/max(|r|, delta) if |r| <= tau else 0.
+ *   weights_out [M] float (required), resid_out [M] float (NULL = not written),
+ *   num_kept    [1] int64 device scalar: number of matches with omega > 0.
+ * delta > 0 and tau > 0 are required.  A pair whose |t_ij| is 0 gives r = 0. */
+fm_status fm_reweight(fm_ctx* ctx, fm_scene* scene, const float* params, float delta, float tau,
+                      float* weights_out, float* resid_out, int64_t* num_kept, fm_stream stream);
+
+/* reweight + build_pair_grams fused in one pass over the matches (no stored
+ * weights): the Gram of the IRLS weights computed at `params`. */
+fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* scene, const float* params, float delta,
+                            float tau, double* W36_f64, float* W36_f32, int64_t* num_kept,
+                            fm_stream stream);
+
+/* ------------------------------------------------------------------ a3+a4: loss, gradient */
+
+/* epipolar_loss_grad (eq. epipolar-objective-l2 and its adjoint):
+ *   W36     [P,36] compact Grams, `wdtype` FM_F64 or FM_F32;
+ *   params  [N,9] float32;
+ *   inv_Z   1/Z (host value), used when Z_dev is NULL;
+ *   Z_dev   optional device int64 scalar Z (then inv_Z = 1/max(Z,1));
+ *   loss    [1] double device scalar (NULL = not written);
+ *   grad    [N,9] float32 dL/dparams (NULL = not written).
+ * The per-pair essential matrix and quadratic form are evaluated in float64,
+ * the Gram-Schmidt map and its adjoint in float64, the per-pair adjoint in
+ * float32; per-camera sums run over each camera's pairs in pair order. */
+fm_status fm_epipolar_loss_grad(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dtype wdtype,
+                                const float* params, double inv_Z, const int64_t* Z_dev,
+                                double* loss, float* grad, fm_stream stream);
+
+/* ------------------------------------------------------------------ a5: Adam */
+
+/* adam_step (Kingma & Ba with bias correction) over n float32 values:
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+ *   p <- p - lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps)
+ * step is 1-based (host).  lr points to device float32: one value
+ * (lr_stride = 0) or n values (lr_stride = 1). */
+fm_status fm_adam_step(fm_ctx* ctx, int64_t n, float* params, const float* grad, float* m,
+                       float* v, int64_t step, const float* lr, int lr_stride, float beta1,
+                       float beta2, float eps, fm_stream stream);
+
+/* ------------------------------------------------------------------ fused loop */
+
+typedef struct {
+  float lr_rot;          /* lr0 on (a1, a2)                                   */
+  float lr_t;            /* lr0 on t                                          */
+  float lr_final_frac;   /* lr(k) = lr0 * frac^(k / lr_total_steps)           */
+  float beta1, beta2, eps;
+  int64_t lr_step0;      /* global step index of this call's first iteration  */
+  int64_t lr_total_steps;/* length of the whole schedule (> 0)                */
+  int64_t adam_step0;    /* Adam steps already taken on m, v (0 after a reset) */
+} fm_adam_cfg;
+
+/* K iterations of {loss + gradient (as fm_epipolar_loss_grad), Adam update of
+ * params} in ONE persistent cooperative kernel; the iteration's two phases
+ * (per pair, per camera) are separated by grid-wide barriers, so no host
+ * round trip happens between iterations.  params, m, v [N,9] float32 are
+ * updated in place.  loss_trace [K] double receives L before each update
+ * (NULL = not written).  `cfg` is a host pointer. */
+fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dtype wdtype,
+                            float* params, float* m, float* v, int32_t K, const fm_adam_cfg* cfg,
+                            double inv_Z, const int64_t* Z_dev, double* loss_trace,
+                            fm_stream stream);
+
+/* ------------------------------------------------------------------ a9: learned weights */
+
+/* A 3 -> 64 -> 64 -> 1 MLP (ReLU, ReLU, sigmoid) mapping per-match features to
+ * a weight in [0, 1].  Hidden layers run on MFMA in float16 with float32
+ * accumulation.  Weights are row-major [out, in]:
+ *   W1 [64,3], b1 [64], W2 [64,64], b2 [64], W3 [1,64], b3 [1]   (float32)
+ * The forward keeps the hidden activations in `act` [M,128] float16 for the
+ * backward (NULL = not kept). */
+typedef struct {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+} fm_mlp;
+
+typedef struct {
+  float *W1, *b1, *W2, *b2, *W3, *b3;
+} fm_mlp_grad;
+
+fm_status fm_mlp_forward(fm_ctx* ctx, int64_t M, const float* feats /*[M,3]*/, const fm_mlp* w,
+                         float* out /*[M]*/, void* act /*[M,128] f16 | NULL*/, fm_stream stream);
+/* Gradients of sum_m dout[m] * out[m] with respect to all weights (fully
+ * overwritten), using the activations kept by fm_mlp_forward. */
+fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
+                          const void* act, const float* out, const float* dout,
+                          fm_mlp_grad* g, fm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTMAP_HIP_H */
