@@ -182,30 +182,6 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
                             double inv_Z, const int64_t* Z_dev, double* loss_trace,
                             fm_stream stream);
 
-/* ------------------------------------------------------------------ a9: learned weights */
-
-/* A 3 -> 64 -> 64 -> 1 MLP (ReLU, ReLU, sigmoid) mapping per-match features to
- * a weight in [0, 1].  Hidden layers run on MFMA in float16 with float32
- * accumulation.  Weights are row-major [out, in]:
- *   W1 [64,3], b1 [64], W2 [64,64], b2 [64], W3 [1,64], b3 [1]   (float32)
- * The forward keeps the hidden activations in `act` [M,128] float16 for the
- * backward (NULL = not kept). */
-typedef struct {
-  const float *W1, *b1, *W2, *b2, *W3, *b3;
-} fm_mlp;
-
-typedef struct {
-  float *W1, *b1, *W2, *b2, *W3, *b3;
-} fm_mlp_grad;
-
-fm_status fm_mlp_forward(fm_ctx* ctx, int64_t M, const float* feats /*[M,3]*/, const fm_mlp* w,
-                         float* out /*[M]*/, void* act /*[M,128] f16 | NULL*/, fm_stream stream);
-/* Gradients of sum_m dout[m] * out[m] with respect to all weights (fully
- * overwritten), using the activations kept by fm_mlp_forward. */
-fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
-                          const void* act, const float* out, const float* dout,
-                          fm_mlp_grad* g, fm_stream stream);
-
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,245 @@
+"""Torch-facing wrappers of the C ABI.
+
+PyTorch only supplies device memory and the current HIP stream; every
+computation happens in the library's kernels.  Functions take and return
+CUDA (HIP) tensors on the context's device.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FastMapError, check
+
+_DTYPES = {torch.float64: _lib.FM_F64, torch.float32: _lib.FM_F32, torch.bfloat16: _lib.FM_BF16}
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _require(t: torch.Tensor, dtype, shape, name: str, device) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.device != device:
+        raise ValueError(f"{name}: expected device {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """A library context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise FastMapError(_lib.FM_EHIP, "no HIP device available")
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = self.lib.fm_create(ctypes.byref(h), device)
+        if rc != _lib.FM_OK:
+            raise FastMapError(rc, f"fm_create({device}) failed")
+        self.handle = h
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.lib.fm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Context | None = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(torch.cuda.current_device())
+    return _default_ctx
+
+
+class Scene:
+    """Pairs, CSR offsets and match coordinates resident on the device, plus
+    the library's derived index data and workspace (fm_scene)."""
+
+    def __init__(self, ctx: Context, num_cams: int, pairs: torch.Tensor, offsets: torch.Tensor,
+                 uv: torch.Tensor):
+        self.ctx = ctx
+        dev = ctx.device
+        P = int(pairs.shape[0]) if pairs.ndim == 2 else 0
+        M = int(uv.shape[0])
+        _require(pairs, torch.int32, (P, 2), "pairs", dev)
+        _require(offsets, torch.int64, (P + 1,), "offsets", dev)
+        if uv.dtype not in _DTYPES:
+            raise TypeError(f"uv dtype {uv.dtype} not supported (float64, float32, bfloat16)")
+        _require(uv, uv.dtype, (M, 4), "uv", dev)
+        self.num_cams, self.num_pairs, self.num_matches = int(num_cams), P, M
+        self.pairs, self.offsets, self.uv = pairs, offsets, uv
+        self.dtype = uv.dtype
+        h = ctypes.c_void_p()
+        rc = ctx.lib.fm_scene_create(ctx.handle, P, M, int(num_cams), _ptr(offsets), _ptr(pairs), _ptr(uv),
+                                     _DTYPES[uv.dtype], _stream(), ctypes.byref(h))
+        check(ctx.handle, rc)
+        self.handle = h
+
+    @classmethod
+    def from_numpy(cls, ctx: Context, num_cams: int, pairs: np.ndarray, offsets: np.ndarray,
+                   uv: np.ndarray, dtype: torch.dtype = torch.float32) -> "Scene":
+        dev = ctx.device
+        uv_t = torch.from_numpy(np.ascontiguousarray(uv, dtype=np.float64)).to(dtype).to(dev)
+        return cls(ctx, num_cams,
+                   torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.int32)).to(dev),
+                   torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int64)).to(dev),
+                   uv_t.contiguous())
+
+    @property
+    def work_items(self) -> int:
+        return int(self.ctx.lib.fm_scene_work_items(self.handle))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.ctx.lib.fm_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def params_from_poses(R: torch.Tensor, t: torch.Tensor) -> torch.Tensor:
+    """Pack world-to-camera poses as the library's parameter rows
+    (a1, a2, t) = (first column of R, second column of R, t), float32."""
+    return torch.cat([R[:, :, 0], R[:, :, 1], t], dim=1).to(torch.float32).contiguous()
+
+
+# ------------------------------------------------------------------ a1
+
+def build_pair_grams(scene: Scene, weights: torch.Tensor | None = None, f64: bool = True, f32: bool = True):
+    """W36 per pair (float64 and/or float32 copies); see include/fastmap_hip.h."""
+    dev, P = scene.ctx.device, scene.num_pairs
+    if weights is not None:
+        _require(weights, torch.float32, (scene.num_matches,), "weights", dev)
+    W64 = torch.empty((P, 36), dtype=torch.float64, device=dev) if f64 else None
+    W32 = torch.empty((P, 36), dtype=torch.float32, device=dev) if f32 else None
+    check(scene.ctx.handle, scene.ctx.lib.fm_build_pair_grams(scene.ctx.handle, scene.handle, _ptr(weights),
+                                                              _ptr(W64), _ptr(W32), _stream()))
+    return W64, W32
+
+
+# ------------------------------------------------------------------ a2
+
+def reweight(scene: Scene, params: torch.Tensor, delta: float, tau: float, residuals: bool = False):
+    """IRLS weights (and residuals) at `params`; returns (weights, resid|None, kept[1] int64)."""
+    dev = scene.ctx.device
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    w = torch.empty(scene.num_matches, dtype=torch.float32, device=dev)
+    r = torch.empty(scene.num_matches, dtype=torch.float32, device=dev) if residuals else None
+    kept = torch.empty(1, dtype=torch.int64, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_reweight(scene.ctx.handle, scene.handle, _ptr(params), float(delta),
+                                                      float(tau), _ptr(w), _ptr(r), _ptr(kept), _stream()))
+    return w, r, kept
+
+
+def reweight_build(scene: Scene, params: torch.Tensor, delta: float, tau: float, f64: bool = True,
+                   f32: bool = True, out: tuple | None = None):
+    """Fused reweight + Gram build; returns (W64|None, W32|None, kept[1] int64)."""
+    dev, P = scene.ctx.device, scene.num_pairs
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    if out is not None:
+        W64, W32, kept = out
+    else:
+        W64 = torch.empty((P, 36), dtype=torch.float64, device=dev) if f64 else None
+        W32 = torch.empty((P, 36), dtype=torch.float32, device=dev) if f32 else None
+        kept = torch.empty(1, dtype=torch.int64, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_reweight_build(scene.ctx.handle, scene.handle, _ptr(params),
+                                                            float(delta), float(tau), _ptr(W64), _ptr(W32),
+                                                            _ptr(kept), _stream()))
+    return W64, W32, kept
+
+
+# ------------------------------------------------------------------ a3 + a4
+
+def _wdtype(W36: torch.Tensor) -> int:
+    if W36.dtype == torch.float64:
+        return _lib.FM_F64
+    if W36.dtype == torch.float32:
+        return _lib.FM_F32
+    raise TypeError("W36 must be float64 or float32")
+
+
+def epipolar_loss_grad(scene: Scene, W36: torch.Tensor, params: torch.Tensor, inv_Z: float | None = None,
+                       Z: torch.Tensor | None = None, want_loss: bool = True, want_grad: bool = True):
+    """(loss[1] float64 | None, grad [N,9] float32 | None) at `params`."""
+    dev = scene.ctx.device
+    _require(W36, W36.dtype, (scene.num_pairs, 36), "W36", dev)
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    if Z is not None:
+        _require(Z, torch.int64, (1,), "Z", dev)
+    elif inv_Z is None:
+        raise ValueError("give inv_Z or Z")
+    loss = torch.empty(1, dtype=torch.float64, device=dev) if want_loss else None
+    grad = torch.empty((scene.num_cams, 9), dtype=torch.float32, device=dev) if want_grad else None
+    check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_loss_grad(
+        scene.ctx.handle, scene.handle, _ptr(W36), _wdtype(W36), _ptr(params),
+        float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss), _ptr(grad), _stream()))
+    return loss, grad
+
+
+# ------------------------------------------------------------------ a5
+
+def adam_step(ctx: Context, params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+              step: int, lr: torch.Tensor, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-12) -> None:
+    """In-place Adam update of a flat float32 tensor; lr is a device tensor with
+    one value or one value per element."""
+    n = params.numel()
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        if t.dtype != torch.float32 or t.numel() != n or not t.is_contiguous() or t.device != ctx.device:
+            raise ValueError(f"{name}: contiguous float32 with {n} elements on {ctx.device} required")
+    if lr.dtype != torch.float32 or lr.numel() not in (1, n) or lr.device != ctx.device:
+        raise ValueError("lr: float32 device tensor with 1 or n elements required")
+    stride = 0 if lr.numel() == 1 else 1
+    check(ctx.handle, ctx.lib.fm_adam_step(ctx.handle, n, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                                           _ptr(lr), stride, beta1, beta2, eps, _stream()))
+
+
+# ------------------------------------------------------------------ fused loop
+
+def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                   K: int, lr_rot: float, lr_t: float, lr_final_frac: float, lr_step0: int, lr_total: int,
+                   adam_step0: int = 0, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-12,
+                   inv_Z: float | None = None, Z: torch.Tensor | None = None,
+                   loss_trace: torch.Tensor | None = None) -> None:
+    """K fused iterations (loss + adjoint + Adam) in one persistent kernel;
+    params, m, v are updated in place; loss_trace [K] float64 optional."""
+    dev = scene.ctx.device
+    _require(W36, W36.dtype, (scene.num_pairs, 36), "W36", dev)
+    for name, t in (("params", params), ("m", m), ("v", v)):
+        _require(t, torch.float32, (scene.num_cams, 9), name, dev)
+    if loss_trace is not None:
+        _require(loss_trace, torch.float64, (K,), "loss_trace", dev)
+    if Z is not None:
+        _require(Z, torch.int64, (1,), "Z", dev)
+    elif inv_Z is None:
+        raise ValueError("give inv_Z or Z")
+    cfg = _lib.AdamCfg(lr_rot, lr_t, lr_final_frac, beta1, beta2, eps, lr_step0, lr_total, adam_step0)
+    check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_solve(
+        scene.ctx.handle, scene.handle, _ptr(W36), _wdtype(W36), _ptr(params), _ptr(m), _ptr(v), int(K),
+        ctypes.byref(cfg), float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss_trace), _stream()))

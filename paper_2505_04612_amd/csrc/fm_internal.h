@@ -1,0 +1,141 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "fastmap_hip.h"
+
+// Matches per Gram work item: one wavefront of 64 lanes, 16 matches per lane.
+constexpr int kLanes = 64;
+constexpr int kPerLane = 16;
+constexpr int kChunk = kLanes * kPerLane;
+// Wavefronts per block of the Gram kernels.
+constexpr int kGramWaves = 4;
+// Threads per block of the per-pair and per-camera kernels.
+constexpr int kBlock = 256;
+
+struct fm_ctx {
+  int device = 0;
+  int num_cu = 0;
+  std::string err;
+};
+
+struct fm_scene {
+  fm_ctx* ctx = nullptr;
+  int64_t P = 0, M = 0;
+  int32_t N = 0;
+  const int64_t* offsets = nullptr;
+  const int32_t* pair_cams = nullptr;
+  const void* uv = nullptr;
+  fm_dtype dtype = FM_F32;
+  // derived index data
+  int64_t n_wi = 0;               // Gram work items
+  int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
+  int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
+  int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order
+  // workspace
+  float* partials = nullptr;      // [n_wi, 36]
+  double* ess = nullptr;          // [P, 9] essential matrices (reweight)
+  float* contrib = nullptr;       // [P, 24] per-pair gradient records
+  double* loss_part = nullptr;    // [loss_part_cap]
+  int64_t loss_part_cap = 0;
+  int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
+};
+
+// Error reporting helpers: set ctx->err and return the status.
+fm_status fm_fail(fm_ctx* ctx, fm_status st, const char* fmt, ...);
+
+#define FM_HIP_TRY(ctx, expr)                                                        \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess)                                                            \
+      return fm_fail((ctx), FM_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+#define FM_CHECK_LAUNCH(ctx)                                                         \
+  do {                                                                               \
+    hipError_t _e = hipGetLastError();                                               \
+    if (_e != hipSuccess)                                                            \
+      return fm_fail((ctx), FM_EHIP, "kernel launch failed: %s", hipGetErrorString(_e)); \
+  } while (0)
+
+static inline unsigned grid_for(int64_t n, int block) {
+  return (unsigned)((n + block - 1) / block);
+}
+
+// ------------------------------------------------------------------ device helpers
+
+// Gram-Schmidt of the 6D rotation parameters (a1, a2) into the columns
+// b1, b2, b3 of R, in float64.  Also returns |a1|, |u2| and b1.a2 for the
+// adjoint.
+struct Gs {
+  double b1[3], b2[3], b3[3];
+  double n1, n2, d12;
+};
+
+__device__ inline Gs gs_forward(const double a1[3], const double a2[3]) {
+  Gs g;
+  g.n1 = sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]);
+  double r1 = 1.0 / g.n1;
+  for (int k = 0; k < 3; ++k) g.b1[k] = a1[k] * r1;
+  g.d12 = g.b1[0] * a2[0] + g.b1[1] * a2[1] + g.b1[2] * a2[2];
+  double u2[3];
+  for (int k = 0; k < 3; ++k) u2[k] = a2[k] - g.d12 * g.b1[k];
+  g.n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  double r2 = 1.0 / g.n2;
+  for (int k = 0; k < 3; ++k) g.b2[k] = u2[k] * r2;
+  g.b3[0] = g.b1[1] * g.b2[2] - g.b1[2] * g.b2[1];
+  g.b3[1] = g.b1[2] * g.b2[0] - g.b1[0] * g.b2[2];
+  g.b3[2] = g.b1[0] * g.b2[1] - g.b1[1] * g.b2[0];
+  return g;
+}
+
+// R[r][c] = b_c[r]
+__device__ inline void gs_matrix(const Gs& g, double R[3][3]) {
+  for (int r = 0; r < 3; ++r) {
+    R[r][0] = g.b1[r];
+    R[r][1] = g.b2[r];
+    R[r][2] = g.b3[r];
+  }
+}
+
+__device__ inline void load_pose(const float* params, int c, double a1[3], double a2[3], double t[3]) {
+  const float* p = params + (int64_t)c * 9;
+  for (int k = 0; k < 3; ++k) {
+    a1[k] = (double)p[k];
+    a2[k] = (double)p[3 + k];
+    t[k] = (double)p[6 + k];
+  }
+}
+
+// Relative pose and essential matrix of pair (i, j) in float64:
+// R_ij = R_j R_i^T, s = t_j - R_ij t_i, th = s/|s|, E = [th]_x R_ij.
+// Returns |s| (0 for a degenerate pair, in which case E = 0).
+__device__ inline double pair_essential(const double Ri[3][3], const double ti[3],
+                                        const double Rj[3][3], const double tj[3],
+                                        double Rij[3][3], double th[3], double E[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      Rij[a][b] = Rj[a][0] * Ri[b][0] + Rj[a][1] * Ri[b][1] + Rj[a][2] * Ri[b][2];
+  double s[3];
+  for (int a = 0; a < 3; ++a)
+    s[a] = tj[a] - (Rij[a][0] * ti[0] + Rij[a][1] * ti[1] + Rij[a][2] * ti[2]);
+  double ns = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+  double inv = ns > 0.0 ? 1.0 / ns : 0.0;
+  for (int a = 0; a < 3; ++a) th[a] = s[a] * inv;
+  // rows of [th]_x
+  const double T[3][3] = {{0.0, -th[2], th[1]}, {th[2], 0.0, -th[0]}, {-th[1], th[0], 0.0}};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      E[a][b] = T[a][0] * Rij[0][b] + T[a][1] * Rij[1][b] + T[a][2] * Rij[2][b];
+  return ns;
+}
+
+// Symmetric monomial index q(a, c) of x~[a] x~[c] in p = (u^2, uv, v^2, u, v, 1).
+__device__ __host__ constexpr int mono_q(int a, int c) {
+  return (a == c) ? (a == 0 ? 0 : (a == 1 ? 2 : 5))
+                  : ((a + c) == 1 ? 1 : ((a + c) == 2 ? 3 : 4));
+}

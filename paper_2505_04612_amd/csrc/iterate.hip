@@ -1,0 +1,427 @@
+// Loss, hand-written adjoint and Adam for epipolar adjustment: eq.
+// (epipolar-objective-l2) evaluated per image pair from the compact Grams,
+// its gradient with respect to the 6D rotation parameters and translations,
+// and the fused persistent loop (Sec. 3.4's kernel fusion, re-designed as one
+// cooperative kernel that also applies the Adam update).
+//
+// One iteration has two phases:
+//   pair phase    one thread per image pair: E_n and W_n e_n in float64, the
+//                 pair's loss, and the adjoint back to dL/dR and dL/dt of its
+//                 two cameras (a 24-float record per pair);
+//   camera phase  one wavefront per camera: the records of the camera's pairs
+//                 are summed in a fixed order (lanes stride the camera's
+//                 incidence list, then a fixed tree), the Gram-Schmidt adjoint
+//                 gives dL/d(a1, a2), and lane 0 applies Adam.
+// The float64 quadratic form matters: near a minimum e^T W e is many orders
+// of magnitude below |W| |e|^2, so float32 would cancel most of its digits.
+#include <hip/hip_cooperative_groups.h>
+
+#include "fm_internal.h"
+
+namespace cg = cooperative_groups;
+
+template <typename WT>
+__device__ inline double load_w(const WT* p, int k) {
+  return (double)p[k];
+}
+
+// Loss term and adjoint record of pair n.  rec = [dL/dR_i (3x3 row-major),
+// dL/dt_i, dL/dR_j, dL/dt_j] as float32.
+template <typename WT>
+__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const int32_t* __restrict__ cams,
+                                           const WT* __restrict__ W36, int64_t n, double two_inv_Z,
+                                           float* __restrict__ rec) {
+  const int ci = cams[2 * n], cj = cams[2 * n + 1];
+  double a1[3], a2[3], ti[3], tj[3];
+  double Ri[3][3], Rj[3][3], Rij[3][3], th[3], E[3][3];
+  load_pose(params, ci, a1, a2, ti);
+  gs_matrix(gs_forward(a1, a2), Ri);
+  load_pose(params, cj, a1, a2, tj);
+  gs_matrix(gs_forward(a1, a2), Rj);
+  const double ns = pair_essential(Ri, ti, Rj, tj, Rij, th, E);
+  // g = W e with W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)]
+  const WT* Wn = W36 + n * 36;
+  double Wl[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) Wl[k] = load_w(Wn, k);
+  double g[3][3];
+  double loss = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc += Wl[6 * mono_q(a, c) + mono_q(b, d)] * E[c][d];
+      g[a][b] = acc;
+      loss += E[a][b] * acc;
+    }
+  if (!(ns > 0.0)) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) rec[k] = 0.0f;
+    return 0.0;
+  }
+  // G = dL/dE = (2/Z) g ; A = G R_ij^T ; dR_ij = T^T G
+  double G[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[a][b] = two_inv_Z * g[a][b];
+  const double T[3][3] = {{0.0, -th[2], th[1]}, {th[2], 0.0, -th[0]}, {-th[1], th[0], 0.0}};
+  double A[3][3], dRij[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      A[a][b] = G[a][0] * Rij[b][0] + G[a][1] * Rij[b][1] + G[a][2] * Rij[b][2];
+      dRij[a][b] = T[0][a] * G[0][b] + T[1][a] * G[1][b] + T[2][a] * G[2][b];
+    }
+  // through T = [th]_x, th = s/|s|, s = t_j - R_ij t_i
+  double gth[3] = {A[2][1] - A[1][2], A[0][2] - A[2][0], A[1][0] - A[0][1]};
+  const double dp = th[0] * gth[0] + th[1] * gth[1] + th[2] * gth[2];
+  const double rns = 1.0 / ns;
+  double gs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gs[k] = (gth[k] - dp * th[k]) * rns;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) dRij[a][b] -= gs[a] * ti[b];
+  // R_ij = R_j R_i^T: dR_j = dRij R_i, dR_i = dRij^T R_j
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      rec[12 + 3 * a + b] = (float)(dRij[a][0] * Ri[0][b] + dRij[a][1] * Ri[1][b] + dRij[a][2] * Ri[2][b]);
+      rec[3 * a + b] = (float)(dRij[0][a] * Rj[0][b] + dRij[1][a] * Rj[1][b] + dRij[2][a] * Rj[2][b]);
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    rec[21 + a] = (float)gs[a];
+    rec[9 + a] = (float)(-(Rij[0][a] * gs[0] + Rij[1][a] * gs[1] + Rij[2][a] * gs[2]));
+  }
+  return loss;
+}
+
+// Pair phase over pairs [first, P) with stride `stride`; writes the records
+// and returns this thread's loss sum (float64, in pair order).
+template <typename WT>
+__device__ inline double pair_phase(const float* params, const int32_t* cams, const WT* W36, int64_t P,
+                                    double two_inv_Z, float* contrib, int64_t first, int64_t stride) {
+  double sum = 0.0;
+  for (int64_t n = first; n < P; n += stride) {
+    float rec[24];
+    sum += pair_loss_adjoint(params, cams, W36, n, two_inv_Z, rec);
+    float4* dst = reinterpret_cast<float4*>(contrib + n * 24);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
+  }
+  return sum;
+}
+
+// Deterministic block sum of one double per thread (fixed tree).
+__device__ inline double block_sum(double v, double* lds) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+  __syncthreads();
+  return t;
+}
+
+// Gradient of camera c (executed by a whole wavefront; result valid in lane 0).
+// Returns dL/dtheta_c [9] in float64 in lane 0.
+__device__ inline void camera_gradient(const float* __restrict__ params, const int32_t* __restrict__ cam_ptr,
+                                       const int32_t* __restrict__ cam_items, const float* __restrict__ contrib,
+                                       int c, int lane, double grad[9]) {
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  const int lo = cam_ptr[c], hi = cam_ptr[c + 1];
+  for (int q = lo + lane; q < hi; q += 64) {
+    const int item = cam_items[q];
+    const float4* src = reinterpret_cast<const float4*>(contrib + (int64_t)(item >> 1) * 24 + (item & 1) * 12);
+    const float4 r0 = src[0], r1 = src[1], r2 = src[2];
+    acc[0] += r0.x; acc[1] += r0.y; acc[2] += r0.z; acc[3] += r0.w;
+    acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
+    acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += __shfl_xor(acc[k], s);
+  // Gram-Schmidt adjoint (float64).  Columns of dL/dR: g1, g2, g3.
+  double a1[3], a2[3], t[3];
+  load_pose(params, c, a1, a2, t);
+  const Gs f = gs_forward(a1, a2);
+  double g1[3], g2[3], g3[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    g1[r] = acc[3 * r + 0];
+    g2[r] = acc[3 * r + 1];
+    g3[r] = acc[3 * r + 2];
+  }
+  // b3 = b1 x b2
+  g1[0] += f.b2[1] * g3[2] - f.b2[2] * g3[1];
+  g1[1] += f.b2[2] * g3[0] - f.b2[0] * g3[2];
+  g1[2] += f.b2[0] * g3[1] - f.b2[1] * g3[0];
+  g2[0] += g3[1] * f.b1[2] - g3[2] * f.b1[1];
+  g2[1] += g3[2] * f.b1[0] - g3[0] * f.b1[2];
+  g2[2] += g3[0] * f.b1[1] - g3[1] * f.b1[0];
+  // b2 = u2/|u2|, u2 = a2 - (b1.a2) b1
+  const double b2g2 = f.b2[0] * g2[0] + f.b2[1] * g2[1] + f.b2[2] * g2[2];
+  double gu[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gu[k] = (g2[k] - b2g2 * f.b2[k]) / f.n2;
+  const double b1gu = f.b1[0] * gu[0] + f.b1[1] * gu[1] + f.b1[2] * gu[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    grad[3 + k] = gu[k] - f.b1[k] * b1gu;
+    g1[k] += -f.d12 * gu[k] - a2[k] * b1gu;
+  }
+  // b1 = a1/|a1|
+  const double b1g1 = f.b1[0] * g1[0] + f.b1[1] * g1[1] + f.b1[2] * g1[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    grad[k] = (g1[k] - b1g1 * f.b1[k]) / f.n1;
+    grad[6 + k] = acc[9 + k];
+  }
+}
+
+// ------------------------------------------------------------------ standalone loss + gradient
+
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_pair_phase(const float* __restrict__ params,
+                                                       const int32_t* __restrict__ cams, const WT* __restrict__ W36,
+                                                       int64_t P, double inv_Z, const int64_t* __restrict__ Z_dev,
+                                                       float* __restrict__ contrib, double* __restrict__ loss_part) {
+  __shared__ double lds[kBlock / 64];
+  const double iz = Z_dev ? 1.0 / (double)(*Z_dev > 0 ? *Z_dev : 1) : inv_Z;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double v = pair_phase(params, cams, W36, P, 2.0 * iz, contrib, n, P > 0 ? P : 1);
+  const double t = block_sum(v, lds);
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_camera_grad(const float* __restrict__ params,
+                                                        const int32_t* __restrict__ cam_ptr,
+                                                        const int32_t* __restrict__ cam_items,
+                                                        const float* __restrict__ contrib, int32_t N,
+                                                        const double* __restrict__ loss_part, int64_t n_part,
+                                                        double inv_Z, const int64_t* __restrict__ Z_dev,
+                                                        float* __restrict__ grad, double* __restrict__ loss) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (loss && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double iz = Z_dev ? 1.0 / (double)(*Z_dev > 0 ? *Z_dev : 1) : inv_Z;
+    double s = 0.0;
+    for (int64_t k = 0; k < n_part; ++k) s += loss_part[k];
+    *loss = s * iz;
+  }
+  if (c >= N || !grad) return;
+  double g[9];
+  camera_gradient(params, cam_ptr, cam_items, contrib, (int)c, lane, g);
+  if (lane < 9) {
+    double v = g[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) v = (lane == k) ? g[k] : v;
+    grad[c * 9 + lane] = (float)v;
+  }
+}
+
+static fm_status check_w(fm_ctx* ctx, const char* fn, const void* W36, fm_dtype wdt) {
+  if (!W36) return fm_fail(ctx, FM_EINVAL, "%s: W36 is NULL", fn);
+  if (wdt != FM_F64 && wdt != FM_F32) return fm_fail(ctx, FM_EDTYPE, "%s: W36 must be FM_F64 or FM_F32", fn);
+  return FM_OK;
+}
+
+extern "C" fm_status fm_epipolar_loss_grad(fm_ctx* ctx, fm_scene* s, const void* W36, fm_dtype wdt,
+                                           const float* params, double inv_Z, const int64_t* Z_dev, double* loss,
+                                           float* grad, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  if (!s) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: scene is NULL");
+  if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: scene belongs to another context");
+  fm_status rc = check_w(ctx, "fm_epipolar_loss_grad", W36, wdt);
+  if (rc != FM_OK) return rc;
+  if (!params) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: params is NULL");
+  if (!Z_dev && !(inv_Z >= 0.0)) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: inv_Z must be >= 0");
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned gp = grid_for(s->P > 0 ? s->P : 1, kBlock);
+  if (wdt == FM_F64)
+    hipLaunchKernelGGL(k_pair_phase<double>, dim3(gp), dim3(kBlock), 0, st, params, s->pair_cams,
+                       (const double*)W36, s->P, inv_Z, Z_dev, s->contrib, s->loss_part);
+  else
+    hipLaunchKernelGGL(k_pair_phase<float>, dim3(gp), dim3(kBlock), 0, st, params, s->pair_cams,
+                       (const float*)W36, s->P, inv_Z, Z_dev, s->contrib, s->loss_part);
+  FM_CHECK_LAUNCH(ctx);
+  const unsigned gc = grid_for((int64_t)(s->N > 0 ? s->N : 1) * 64, kBlock);
+  hipLaunchKernelGGL(k_camera_grad, dim3(gc), dim3(kBlock), 0, st, params, s->cam_ptr, s->cam_items, s->contrib,
+                     s->N, s->loss_part, (int64_t)gp, inv_Z, Z_dev, grad, loss);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
+}
+
+// ------------------------------------------------------------------ Adam
+
+__device__ inline float adam_update(float p, float g, float& m, float& v, double lr, double b1, double b2,
+                                    double eps, double bc1, double bc2) {
+  const double md = b1 * (double)m + (1.0 - b1) * (double)g;
+  const double vd = b2 * (double)v + (1.0 - b2) * (double)g * (double)g;
+  m = (float)md;
+  v = (float)vd;
+  return (float)((double)p - lr * (md / bc1) / (sqrt(vd / bc2) + eps));
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, const float* __restrict__ lr, int lr_stride, double b1, double b2,
+                       double eps, double bc1, double bc2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float mk = m[k], vk = v[k];
+  p[k] = adam_update(p[k], g[k], mk, vk, (double)lr[lr_stride ? k : 0], b1, b2, eps, bc1, bc2);
+  m[k] = mk;
+  v[k] = vk;
+}
+
+extern "C" fm_status fm_adam_step(fm_ctx* ctx, int64_t n, float* p, const float* g, float* m, float* v,
+                                  int64_t step, const float* lr, int lr_stride, float beta1, float beta2, float eps,
+                                  fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  if (n < 0) return fm_fail(ctx, FM_ESHAPE, "fm_adam_step: n < 0");
+  if (n > 0 && (!p || !g || !m || !v || !lr)) return fm_fail(ctx, FM_EINVAL, "fm_adam_step: NULL argument");
+  if (step < 1) return fm_fail(ctx, FM_EINVAL, "fm_adam_step: step is 1-based");
+  if (lr_stride != 0 && lr_stride != 1) return fm_fail(ctx, FM_EINVAL, "fm_adam_step: lr_stride must be 0 or 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return fm_fail(ctx, FM_EINVAL, "fm_adam_step: bad beta/eps");
+  if (n == 0) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const double bc1 = 1.0 - pow((double)beta1, (double)step), bc2 = 1.0 - pow((double)beta2, (double)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, n, p, g, m, v, lr,
+                     lr_stride, (double)beta1, (double)beta2, (double)eps, bc1, bc2);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
+}
+
+// ------------------------------------------------------------------ fused persistent solve
+
+struct SolveArgs {
+  float* params;
+  float* m;
+  float* v;
+  const int32_t* cams;
+  const void* W36;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  float* contrib;
+  double* loss_part;
+  double* loss_trace;
+  const int64_t* Z_dev;
+  double inv_Z;
+  int64_t P;
+  int32_t N;
+  int32_t K;
+  double lr_rot, lr_t, log_frac;
+  double b1, b2, eps;
+  int64_t lr_step0, lr_total, adam_step0;
+};
+
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
+  __shared__ double lds[kBlock / 64];
+  cg::grid_group grid = cg::this_grid();
+  const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const WT* W36 = reinterpret_cast<const WT*>(a.W36);
+  for (int k = 0; k < a.K; ++k) {
+    const double v = pair_phase(a.params, a.cams, W36, a.P, 2.0 * iz, a.contrib, gtid, gsize);
+    const double t = block_sum(v, lds);
+    if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
+    grid.sync();
+    if (a.loss_trace && gtid == 0) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += a.loss_part[b];
+      a.loss_trace[k] = s * iz;
+    }
+    const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
+    const double step = (double)(a.adam_step0 + k + 1);
+    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    for (int64_t c = gwave; c < a.N; c += nwaves) {
+      double g[9];
+      camera_gradient(a.params, a.cam_ptr, a.cam_items, a.contrib, (int)c, lane, g);
+      if (lane == 0) {
+        float* p = a.params + c * 9;
+        float* m = a.m + c * 9;
+        float* vv = a.v + c * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const double lr = (q < 6 ? a.lr_rot : a.lr_t) * frac;
+          float mq = m[q], vq = vv[q];
+          p[q] = adam_update(p[q], (float)g[q], mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+          m[q] = mq;
+          vv[q] = vq;
+        }
+      }
+    }
+    grid.sync();
+  }
+}
+
+int fm_solve_coop_blocks(fm_ctx* ctx) {
+  int per_cu64 = 0, per_cu32 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_solve<double>, kBlock, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, k_solve<float>, kBlock, 0) != hipSuccess) return 0;
+  const int per_cu = per_cu64 < per_cu32 ? per_cu64 : per_cu32;
+  return per_cu * ctx->num_cu;
+}
+
+extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36, fm_dtype wdt, float* params,
+                                       float* m, float* v, int32_t K, const fm_adam_cfg* cfg, double inv_Z,
+                                       const int64_t* Z_dev, double* loss_trace, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  if (!s) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: scene is NULL");
+  if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: scene belongs to another context");
+  fm_status rc = check_w(ctx, "fm_epipolar_solve", W36, wdt);
+  if (rc != FM_OK) return rc;
+  if (!params || !m || !v || !cfg) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: NULL argument");
+  if (K < 0) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: K < 0");
+  if (cfg->lr_total_steps <= 0 || cfg->lr_step0 < 0 || cfg->adam_step0 < 0 || !(cfg->lr_final_frac > 0.0f) ||
+      !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f && cfg->eps >= 0.0f))
+    return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: bad Adam configuration");
+  if (!Z_dev && !(inv_Z >= 0.0)) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: inv_Z must be >= 0");
+  if (K == 0) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // enough threads for one pair each or one wavefront per camera, within the
+  // co-resident limit of a cooperative launch
+  int64_t want = grid_for(s->P, kBlock);
+  const int64_t want_c = grid_for((int64_t)s->N * 64, kBlock);
+  if (want_c > want) want = want_c;
+  if (want < 1) want = 1;
+  if (want > s->coop_blocks) want = s->coop_blocks;
+  if (want > s->loss_part_cap) return fm_fail(ctx, FM_ECOOP, "fm_epipolar_solve: loss workspace too small");
+  SolveArgs a;
+  a.params = params; a.m = m; a.v = v;
+  a.cams = s->pair_cams; a.W36 = W36; a.cam_ptr = s->cam_ptr; a.cam_items = s->cam_items;
+  a.contrib = s->contrib; a.loss_part = s->loss_part; a.loss_trace = loss_trace; a.Z_dev = Z_dev;
+  a.inv_Z = inv_Z; a.P = s->P; a.N = s->N; a.K = K;
+  a.lr_rot = cfg->lr_rot; a.lr_t = cfg->lr_t; a.log_frac = log((double)cfg->lr_final_frac);
+  a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;
+  a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
+  void* args[] = {&a};
+  hipError_t e = wdt == FM_F64
+                     ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want), dim3(kBlock),
+                                                  args, 0, (hipStream_t)stream)
+                     : hipLaunchCooperativeKernel((const void*)k_solve<float>, dim3((unsigned)want), dim3(kBlock),
+                                                  args, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+  return FM_OK;
+}

@@ -1,0 +1,260 @@
+// Context, error handling and scene set-up: validation of the pair/match
+// structure, the Gram work-item table and the per-camera incidence lists.
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+
+#include "fm_internal.h"
+
+fm_status fm_fail(fm_ctx* ctx, fm_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+extern "C" const char* fm_version(void) { return "fastmap_hip 0.1 gfx950"; }
+
+extern "C" fm_status fm_create(fm_ctx** out, int device) {
+  if (!out) return FM_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FM_EINVAL;
+  fm_ctx* ctx = new (std::nothrow) fm_ctx();
+  if (!ctx) return FM_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    delete ctx;
+    return FM_EHIP;
+  }
+  *out = ctx;
+  return FM_OK;
+}
+
+extern "C" void fm_destroy(fm_ctx* ctx) { delete ctx; }
+
+extern "C" const char* fm_last_error(const fm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// ------------------------------------------------------------------ kernels
+
+// Bit 0: offsets not a valid CSR; bit 1: camera index out of range or i == j.
+__global__ void k_validate(const int64_t* off, const int32_t* cams, int64_t P, int64_t M, int32_t N,
+                           int* flag) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n > P) return;
+  int bad = 0;
+  int64_t a = off[n];
+  if (n == 0 && a != 0) bad |= 1;
+  if (n == P && a != M) bad |= 1;
+  if (n < P) {
+    int64_t b = off[n + 1];
+    if (b < a || a < 0 || b > M) bad |= 1;
+    int32_t i = cams[2 * n], j = cams[2 * n + 1];
+    if (i < 0 || j < 0 || i >= N || j >= N || i == j) bad |= 2;
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+// Work items per pair (chunks of kChunk matches), written shifted by one so
+// that an inclusive scan yields the exclusive offsets wi_off[0..P].
+__global__ void k_wi_count(const int64_t* off, int64_t P, int64_t* wi_off) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 0) wi_off[0] = 0;
+  if (n < P) {
+    int64_t len = off[n + 1] - off[n];
+    wi_off[n + 1] = (len + kChunk - 1) / kChunk;
+  }
+}
+
+// In-place inclusive scan of x[0..n) by one block of 1024 threads: each
+// thread scans a contiguous range serially, the range totals are scanned in
+// LDS, and the ranges are offset.  Used only at scene set-up.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_inclusive(T* x, int64_t n) {
+  __shared__ T tot[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = tid * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  T s = 0;
+  for (int64_t k = lo; k < hi; ++k) {
+    s += x[k];
+    x[k] = s;
+  }
+  tot[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    T v = tid >= d ? tot[tid - d] : 0;
+    __syncthreads();
+    tot[tid] += v;
+    __syncthreads();
+  }
+  const T base = tid > 0 ? tot[tid - 1] : 0;
+  for (int64_t k = lo; k < hi; ++k) x[k] += base;
+}
+
+__global__ void k_cam_degree(const int32_t* cams, int64_t P, int32_t* cam_ptr) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < P) {
+    atomicAdd(&cam_ptr[cams[2 * n] + 1], 1);
+    atomicAdd(&cam_ptr[cams[2 * n + 1] + 1], 1);
+  }
+}
+
+__global__ void k_cam_scatter(const int32_t* cams, int64_t P, const int32_t* cam_ptr, int32_t* cursor,
+                              int32_t* items) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < P) {
+    for (int side = 0; side < 2; ++side) {
+      int c = cams[2 * n + side];
+      int pos = atomicAdd(&cursor[c], 1);
+      items[cam_ptr[c] + pos] = (int32_t)(2 * n + side);
+    }
+  }
+}
+
+// Put every camera's incidence list in ascending item order (pair order), so
+// that the per-camera gradient sums have a fixed order: each item's rank in
+// its list is the number of smaller items in the list.
+__global__ void k_cam_sort(const int32_t* cam_ptr, const int32_t* cam_of_slot, const int32_t* unsorted,
+                           int64_t total, int32_t* sorted) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  int c = cam_of_slot[k];
+  int lo = cam_ptr[c], hi = cam_ptr[c + 1];
+  int v = unsorted[k];
+  int rank = 0;
+  for (int q = lo; q < hi; ++q) rank += unsorted[q] < v;
+  sorted[lo + rank] = v;
+}
+
+__global__ void k_slot_camera(const int32_t* cam_ptr, int32_t N, int32_t* cam_of_slot) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N)
+    for (int q = cam_ptr[c]; q < cam_ptr[c + 1]; ++q) cam_of_slot[q] = c;
+}
+
+// ------------------------------------------------------------------ scene
+
+static void scene_free(fm_scene* s) {
+  if (!s) return;
+  (void)hipFree(s->wi_off);
+  (void)hipFree(s->cam_ptr);
+  (void)hipFree(s->cam_items);
+  (void)hipFree(s->partials);
+  (void)hipFree(s->ess);
+  (void)hipFree(s->contrib);
+  (void)hipFree(s->loss_part);
+  delete s;
+}
+
+extern "C" void fm_scene_destroy(fm_scene* s) { scene_free(s); }
+
+extern "C" int64_t fm_scene_work_items(const fm_scene* s) { return s ? s->n_wi : -1; }
+
+int fm_solve_coop_blocks(fm_ctx* ctx);  // iterate.hip
+
+#define SCENE_TRY(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess) {                                                               \
+      (void)hipFree(tmp_i32);                                                             \
+      (void)hipFree(flag);                                                                \
+      scene_free(s);                                                                      \
+      return fm_fail(ctx, _e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP, "%s: %s", #expr, \
+                     hipGetErrorString(_e));                                              \
+    }                                                                                     \
+  } while (0)
+
+extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t N, const int64_t* off,
+                                     const int32_t* cams, const void* uv, fm_dtype dtype,
+                                     fm_stream stream_, fm_scene** out) {
+  if (!ctx) return FM_EINVAL;
+  if (!out) return fm_fail(ctx, FM_EINVAL, "fm_scene_create: out is NULL");
+  *out = nullptr;
+  if (P < 0 || M < 0 || N < 0) return fm_fail(ctx, FM_ESHAPE, "negative size (P=%lld M=%lld N=%d)", (long long)P, (long long)M, N);
+  if (P > (int64_t)1 << 30 || N >= (1 << 30)) return fm_fail(ctx, FM_ESHAPE, "too many pairs or cameras");
+  if (!off) return fm_fail(ctx, FM_EINVAL, "pair_offsets is NULL");
+  if (P > 0 && !cams) return fm_fail(ctx, FM_EINVAL, "pair_cams is NULL");
+  if (M > 0 && !uv) return fm_fail(ctx, FM_EINVAL, "uv is NULL");
+  if (P > 0 && N < 2) return fm_fail(ctx, FM_ESHAPE, "pairs need at least two cameras");
+  if (dtype != FM_F64 && dtype != FM_F32 && dtype != FM_BF16)
+    return fm_fail(ctx, FM_EDTYPE, "unsupported coordinate dtype %d", (int)dtype);
+  hipStream_t st = (hipStream_t)stream_;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  fm_scene* s = new (std::nothrow) fm_scene();
+  if (!s) return fm_fail(ctx, FM_ENOMEM, "host allocation failed");
+  s->ctx = ctx;
+  s->P = P; s->M = M; s->N = N;
+  s->offsets = off; s->pair_cams = cams; s->uv = uv; s->dtype = dtype;
+  int32_t* tmp_i32 = nullptr;
+  int* flag = nullptr;
+  SCENE_TRY(hipMalloc(&flag, sizeof(int)));
+  SCENE_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(P + 1, kBlock)), dim3(kBlock), 0, st, off, cams, P, M, N, flag);
+  SCENE_TRY(hipGetLastError());
+  int hflag = 0;
+  SCENE_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SCENE_TRY(hipStreamSynchronize(st));
+  if (hflag) {
+    (void)hipFree(flag);
+    scene_free(s);
+    return fm_fail(ctx, FM_ESHAPE, "%s%s", (hflag & 1) ? "pair_offsets is not a CSR over [0, M] " : "",
+                   (hflag & 2) ? "pair_cams has an index out of [0, N) or i == j" : "");
+  }
+  // work items
+  SCENE_TRY(hipMalloc(&s->wi_off, sizeof(int64_t) * (P + 1)));
+  hipLaunchKernelGGL(k_wi_count, dim3(grid_for(P + 1, kBlock)), dim3(kBlock), 0, st, off, P, s->wi_off);
+  SCENE_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_inclusive<int64_t>, dim3(1), dim3(1024), 0, st, s->wi_off + 1, P);
+  SCENE_TRY(hipGetLastError());
+  SCENE_TRY(hipMemcpyAsync(&s->n_wi, s->wi_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  // camera incidence lists
+  SCENE_TRY(hipMalloc(&s->cam_ptr, sizeof(int32_t) * (N + 1)));
+  SCENE_TRY(hipMalloc(&s->cam_items, sizeof(int32_t) * (2 * P + 1)));
+  SCENE_TRY(hipMalloc(&tmp_i32, sizeof(int32_t) * (N + 1 + 4 * P + 2)));
+  int32_t* cursor = tmp_i32;                 // [N+1]
+  int32_t* unsorted = tmp_i32 + N + 1;       // [2P+1]
+  int32_t* slot_cam = unsorted + 2 * P + 1;  // [2P+1]
+  SCENE_TRY(hipMemsetAsync(s->cam_ptr, 0, sizeof(int32_t) * (N + 1), st));
+  SCENE_TRY(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (N + 1), st));
+  if (P > 0) {
+    hipLaunchKernelGGL(k_cam_degree, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, cams, P, s->cam_ptr);
+    SCENE_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_inclusive<int32_t>, dim3(1), dim3(1024), 0, st, s->cam_ptr + 1, (int64_t)N);
+    SCENE_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_cam_scatter, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, cams, P, s->cam_ptr,
+                       cursor, unsorted);
+    SCENE_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_slot_camera, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, s->cam_ptr, N, slot_cam);
+    SCENE_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_cam_sort, dim3(grid_for(2 * P, kBlock)), dim3(kBlock), 0, st, s->cam_ptr, slot_cam,
+                       unsorted, 2 * P, s->cam_items);
+    SCENE_TRY(hipGetLastError());
+  }
+  SCENE_TRY(hipStreamSynchronize(st));
+  (void)hipFree(tmp_i32);
+  tmp_i32 = nullptr;
+  (void)hipFree(flag);
+  flag = nullptr;
+  // workspace
+  s->coop_blocks = fm_solve_coop_blocks(ctx);
+  if (s->coop_blocks <= 0) {
+    scene_free(s);
+    return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative solve kernel");
+  }
+  s->loss_part_cap = (int64_t)grid_for(P, kBlock);
+  if (s->loss_part_cap < s->coop_blocks) s->loss_part_cap = s->coop_blocks;
+  SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_wi > 0 ? s->n_wi : 1)));
+  SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
+  SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
+  SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
+  *out = s;
+  return FM_OK;
+}

@@ -1,0 +1,259 @@
+"""GPU <-> FP64 oracle parity through the C ABI (needs an MI355X).
+
+Tolerances (derived from the arithmetic, stated per check):
+  * Gram: per pair |dW|_F / |W|_F <= 1e-5 and per element |dW| <= 1e-5 *
+    sum_m |omega w_k w_l| (float32 products and work-item sums of at most 16
+    terms per lane plus a 6-level tree, float64 across work items); both are
+    measured against float64 Grams of the same stored coordinates;
+  * Gram bit-identical across runs (fixed reduction order);
+  * IRLS weights: kept/filtered decisions identical (both sides decide on a
+    float64 residual), weights within 1e-6 relative (float32 storage);
+  * loss within 1e-9 relative and gradient within 1e-5 of its max-norm (the
+    quadratic form runs in float64, the per-pair adjoint records are float32);
+  * final poses: relative rotation <= 0.1 deg and translation direction
+    <= 0.5 deg from the oracle (the workload's pose-parity bar).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ea
+from tests.helpers import expand36, f32, gram_errors, scene, stored
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fm():
+    from paper_2505_04612_amd import api
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU is required for the gpu-marked tests")
+    return api
+
+
+@pytest.fixture(scope="module")
+def ctx(fm):
+    return fm.default_context()
+
+
+def _scene_on_gpu(fm, ctx, sc, dtype):
+    return fm.Scene.from_numpy(ctx, sc.num_cams, sc.pairs, sc.offsets, sc.uv, dtype)
+
+
+def _ragged_scene(seed=7, sizes=(0, 1, 63, 64, 65, 1023, 1024, 1025, 2049, 5000, 0, 17), ncams=6):
+    """Synthetic structure with empty pairs and chunk-boundary sizes."""
+    rng = np.random.default_rng(seed)
+    P = len(sizes)
+    pairs = np.array([[k % ncams, (k + 1 + k // ncams) % ncams] for k in range(P)], dtype=np.int32)
+    pairs[pairs[:, 0] == pairs[:, 1], 1] = (pairs[pairs[:, 0] == pairs[:, 1], 0] + 1) % ncams
+    offs = np.zeros(P + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    uv = rng.uniform(-0.7, 0.7, size=(int(offs[-1]), 4))
+    return pairs, offs, uv, ncams
+
+
+# ------------------------------------------------------------------ a1: Gram
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_gram_ragged_parity_and_determinism(fm, ctx, dtype):
+    pairs, offs, uv, N = _ragged_scene()
+    s = fm.Scene.from_numpy(ctx, N, pairs, offs, uv, dtype)
+    W64, W32 = fm.build_pair_grams(s)
+    W64b, _ = fm.build_pair_grams(s)
+    torch.cuda.synchronize()
+    assert torch.equal(W64, W64b), "Gram build is not bit-identical across runs"
+    assert torch.equal(W32, W64.to(torch.float32))
+    x = stored(uv, dtype)
+    ref = ea.pair_grams(x, offs)
+    absg = ea.pair_grams(np.abs(x), offs)
+    rel, el = gram_errors(expand36(W64.cpu().numpy()), ref, absg)
+    assert rel <= 1e-5 and el <= 1e-5, (rel, el)
+    assert np.all(W64.cpu().numpy()[np.diff(offs) == 0] == 0.0)
+
+
+@pytest.mark.parametrize("name,dtype", [("tiny", torch.float64), ("medium", torch.float32),
+                                        ("medium", torch.bfloat16)])
+def test_gram_scene_parity(fm, ctx, name, dtype):
+    sc = scene(name)
+    s = _scene_on_gpu(fm, ctx, sc, dtype)
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.0, 50.0, sc.num_matches).astype(np.float32)
+    w[rng.random(sc.num_matches) < 0.2] = 0.0
+    wt = torch.from_numpy(w).to(ctx.device)
+    for weights in (None, wt):
+        W64, W32 = fm.build_pair_grams(s, weights)
+        W64b, _ = fm.build_pair_grams(s, weights)
+        assert torch.equal(W64, W64b)
+        x = stored(sc.uv, dtype)
+        om = None if weights is None else w.astype(np.float64)
+        ref = ea.pair_grams(x, sc.offsets, om)
+        absg = ea.pair_grams(np.abs(x), sc.offsets, om)
+        rel, el = gram_errors(expand36(W64.cpu().numpy()), ref, absg)
+        assert rel <= 1e-5 and el <= 1e-5, (name, dtype, weights is None, rel, el)
+
+
+def test_empty_scene(fm, ctx):
+    s = fm.Scene.from_numpy(ctx, 3, np.zeros((0, 2), np.int32), np.zeros(1, np.int64), np.zeros((0, 4)))
+    W64, W32 = fm.build_pair_grams(s)
+    assert W64.shape == (0, 36)
+    params = torch.zeros((3, 9), dtype=torch.float32, device=ctx.device)
+    params[:, 0] = 1
+    params[:, 4] = 1
+    loss, grad = fm.epipolar_loss_grad(s, W64, params, inv_Z=1.0)
+    assert float(loss.item()) == 0.0 and torch.count_nonzero(grad) == 0
+
+
+def test_scene_validation_errors(fm, ctx):
+    from paper_2505_04612_amd._lib import FM_ESHAPE, FastMapError
+    uv = np.zeros((10, 4))
+    with pytest.raises(FastMapError) as e:
+        fm.Scene.from_numpy(ctx, 3, np.array([[0, 1], [1, 2]], np.int32), np.array([0, 6, 5], np.int64), uv)
+    assert e.value.status == FM_ESHAPE
+    with pytest.raises(FastMapError) as e:
+        fm.Scene.from_numpy(ctx, 3, np.array([[0, 1], [1, 1]], np.int32), np.array([0, 5, 10], np.int64), uv)
+    assert e.value.status == FM_ESHAPE
+    with pytest.raises(FastMapError) as e:
+        fm.Scene.from_numpy(ctx, 3, np.array([[0, 1], [1, 3]], np.int32), np.array([0, 5, 10], np.int64), uv)
+    assert e.value.status == FM_ESHAPE
+    with pytest.raises(FastMapError) as e:
+        fm.Scene.from_numpy(ctx, 3, np.array([[0, 1], [1, 2]], np.int32), np.array([0, 5, 9], np.int64), uv)
+    assert e.value.status == FM_ESHAPE
+
+
+# ------------------------------------------------------------------ a2: IRLS
+
+def _theta(sc):
+    return ea.params_from_poses(sc.R_init, sc.t_init).astype(np.float32)
+
+
+@pytest.mark.parametrize("name,dtype", [("tiny", torch.float64), ("medium", torch.float32),
+                                        ("medium", torch.bfloat16)])
+def test_reweight_parity(fm, ctx, name, dtype):
+    sc = scene(name)
+    s = _scene_on_gpu(fm, ctx, sc, dtype)
+    th = _theta(sc)
+    delta, tau = f32(1e-4), f32(0.05)
+    w, r, kept = fm.reweight(s, torch.from_numpy(th).to(ctx.device), delta, tau, residuals=True)
+    x = stored(sc.uv, dtype)
+    r_ref = ea.residuals(th.astype(np.float64), sc.pairs, sc.offsets, x)
+    w_ref = ea.irls_weights(r_ref, delta, tau)
+    w_g, r_g = w.cpu().numpy(), r.cpu().numpy()
+    assert np.allclose(r_g, r_ref, rtol=1e-6, atol=1e-12 + 1e-7 * np.abs(r_ref).max())
+    ambiguous = np.abs(np.abs(r_ref) - tau) <= 1e-12
+    assert np.array_equal((w_g > 0)[~ambiguous], (w_ref > 0)[~ambiguous])
+    assert np.allclose(w_g, w_ref, rtol=1e-6, atol=0)
+    assert int(kept.item()) == int(np.count_nonzero(w_g))
+    # fused reweight + build equals the build of the oracle's weights
+    W64, _, kept2 = fm.reweight_build(s, torch.from_numpy(th).to(ctx.device), delta, tau)
+    assert int(kept2.item()) == int(kept.item())
+    ref = ea.pair_grams(x, sc.offsets, w_ref)
+    absg = ea.pair_grams(np.abs(x), sc.offsets, w_ref)
+    rel, el = gram_errors(expand36(W64.cpu().numpy()), ref, absg)
+    assert rel <= 1e-5 and el <= 1e-5, (rel, el)
+
+
+# ------------------------------------------------------------------ a3 + a4: loss and adjoint
+
+@pytest.mark.parametrize("wdtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_loss_grad_parity(fm, ctx, name, wdtype):
+    sc = scene(name)
+    s = _scene_on_gpu(fm, ctx, sc, torch.float32)
+    W64, W32 = fm.build_pair_grams(s)
+    th = _theta(sc)
+    rng = np.random.default_rng(1)
+    th = (th + rng.normal(0, 0.02, th.shape)).astype(np.float32)   # off the orthonormal manifold
+    inv_Z = 1.0 / sc.num_matches
+    Wg = W64 if wdtype == torch.float64 else W32
+    loss, grad = fm.epipolar_loss_grad(s, Wg, torch.from_numpy(th).to(ctx.device), inv_Z=inv_Z)
+    Wref = expand36(Wg.cpu().numpy().astype(np.float64))      # the same Gram values
+    L_ref, g_ref = ea.loss_grad(th.astype(np.float64), sc.pairs, Wref, inv_Z)
+    assert abs(float(loss.item()) - L_ref) <= 1e-9 * abs(L_ref)
+    g = grad.cpu().numpy()
+    assert np.abs(g - g_ref).max() <= 1e-5 * np.abs(g_ref).max()
+    # determinism
+    loss2, grad2 = fm.epipolar_loss_grad(s, Wg, torch.from_numpy(th).to(ctx.device), inv_Z=inv_Z)
+    assert torch.equal(loss, loss2) and torch.equal(grad, grad2)
+
+
+def test_loss_grad_device_Z(fm, ctx):
+    sc = scene("tiny")
+    s = _scene_on_gpu(fm, ctx, sc, torch.float64)
+    W64, _ = fm.build_pair_grams(s)
+    th = torch.from_numpy(_theta(sc)).to(ctx.device)
+    Z = torch.tensor([12345], dtype=torch.int64, device=ctx.device)
+    l1, g1 = fm.epipolar_loss_grad(s, W64, th, Z=Z)
+    l2, g2 = fm.epipolar_loss_grad(s, W64, th, inv_Z=1.0 / 12345)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+
+
+# ------------------------------------------------------------------ a5: Adam
+
+def test_adam_parity(fm, ctx):
+    rng = np.random.default_rng(2)
+    n = 1000
+    p = rng.normal(size=n).astype(np.float32)
+    pt = torch.from_numpy(p.copy()).to(ctx.device)
+    m = torch.zeros(n, device=ctx.device)
+    v = torch.zeros(n, device=ctx.device)
+    pr, mr, vr = p.astype(np.float64), np.zeros(n), np.zeros(n)
+    lrs = rng.uniform(1e-4, 1e-2, n).astype(np.float32)
+    lr_t = torch.from_numpy(lrs).to(ctx.device)
+    for step in range(1, 31):
+        g = (rng.normal(size=n) * 10.0 ** rng.uniform(-8, 0)).astype(np.float32)
+        fm.adam_step(ctx, pt, torch.from_numpy(g).to(ctx.device), m, v, step, lr_t, 0.9, 0.999, 1e-12)
+        pr, mr, vr = ea.adam_step(pr, g.astype(np.float64), mr, vr, step, lrs.astype(np.float64),
+                                  f32(0.9), f32(0.999), f32(1e-12))
+    assert np.allclose(pt.cpu().numpy(), pr, rtol=0, atol=1e-5)
+
+
+# ------------------------------------------------------------------ fused loop and whole solve
+
+def test_fused_solve_matches_oracle_steps(fm, ctx):
+    """K fused iterations on a fixed Gram equal K oracle Adam steps."""
+    sc = scene("tiny")
+    s = _scene_on_gpu(fm, ctx, sc, torch.float64)
+    W64, _ = fm.build_pair_grams(s)
+    th = _theta(sc)
+    p = torch.from_numpy(th.copy()).to(ctx.device)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    K = 50
+    trace = torch.empty(K, dtype=torch.float64, device=ctx.device)
+    inv_Z = 1.0 / sc.num_matches
+    fm.epipolar_solve(s, W64, p, m, v, K, 3e-3, 1e-2, 1e-3, 0, K, 0, inv_Z=inv_Z, loss_trace=trace)
+    W = expand36(W64.cpu().numpy())
+    sched = ea.Schedule(iters=K, round_len=K, lr_rot=f32(3e-3), lr_t=f32(1e-2), lr_final_frac=f32(1e-3),
+                        beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-12))
+    tr = th.astype(np.float64)
+    mr, vr = np.zeros_like(tr), np.zeros_like(tr)
+    losses = []
+    for k in range(K):
+        L, g = ea.loss_grad(tr, sc.pairs, W, inv_Z)
+        losses.append(L)
+        tr, mr, vr = ea.adam_step(tr, g, mr, vr, k + 1, ea.lr_at(sched, k), sched.beta1, sched.beta2, sched.eps)
+    assert np.allclose(trace.cpu().numpy(), losses, rtol=1e-5)
+    rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), tr, sc.pairs)
+    assert rot.max() < 1e-3 and tra.max() < 1e-2
+
+
+def _oracle_sched(s):
+    return ea.Schedule(iters=s.iters, round_len=s.round_len, lr_rot=f32(s.lr_rot), lr_t=f32(s.lr_t),
+                       lr_final_frac=f32(s.lr_final_frac), beta1=f32(s.beta1), beta2=f32(s.beta2),
+                       eps=f32(s.eps), irls=s.irls, delta=f32(s.delta), tau0=f32(s.tau0),
+                       tau_min=f32(s.tau_min), first_round_unit_weights=s.first_round_unit_weights)
+
+
+@pytest.mark.parametrize("name,dtype,iters", [("tiny", torch.float64, 500), ("medium", torch.float32, 2000)])
+def test_full_solve_pose_parity(fm, ctx, name, dtype, iters):
+    from paper_2505_04612_amd import solver
+    sc = scene(name)
+    s = _scene_on_gpu(fm, ctx, sc, dtype)
+    th0 = _theta(sc)
+    sched = solver.Schedule(iters=iters, round_len=100)
+    p, losses, Z = solver.solve(s, torch.from_numpy(th0).to(ctx.device), sched)
+    th_o, tr_o, w_o = ea.solve(th0.astype(np.float64), sc.pairs, sc.offsets, stored(sc.uv, dtype),
+                               _oracle_sched(sched))
+    rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), th_o, sc.pairs)
+    assert rot.max() <= 0.1 and tra.max() <= 0.5, (rot.max(), tra.max())
+    assert int(Z.item()) == int(np.count_nonzero(w_o)) or abs(int(Z.item()) - int(np.count_nonzero(w_o))) <= 2
