@@ -251,6 +251,7 @@ class Schedule:
     tau0: float = 0.1
     tau_min: float = 0.01
     first_round_unit_weights: bool = False
+    reset_adam: bool = True     # restart Adam (m, v, step) at every loop
 
 
 def lr_at(sched: Schedule, k: int) -> np.ndarray:
@@ -282,17 +283,23 @@ def solve(theta0: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.nda
         k_rw += 1
     trace = []
     done = 0
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    t_adam = 0
     while done < sched.iters:
         W = pair_grams(uv, offsets, weights)
         Z = M if weights is None else int(np.count_nonzero(weights))
         inv_Z = 1.0 / max(Z, 1)
-        m = np.zeros_like(theta)
-        v = np.zeros_like(theta)
+        if sched.reset_adam:
+            m = np.zeros_like(theta)
+            v = np.zeros_like(theta)
+            t_adam = 0
         K = min(sched.round_len, sched.iters - done)
         for s in range(K):
             L, g = loss_grad(theta, pairs, W, inv_Z)
             trace.append(L)
-            theta, m, v = adam_step(theta, g, m, v, s + 1, lr_at(sched, done + s),
+            t_adam += 1
+            theta, m, v = adam_step(theta, g, m, v, t_adam, lr_at(sched, done + s),
                                     sched.beta1, sched.beta2, sched.eps)
         done += K
         if sched.irls and done < sched.iters:

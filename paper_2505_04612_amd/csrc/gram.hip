@@ -292,7 +292,7 @@ extern "C" fm_status fm_build_pair_grams(fm_ctx* ctx, fm_scene* s, const float* 
                                          float* W32, fm_stream stream) {
   fm_status rc = check_scene(ctx, s, "fm_build_pair_grams");
   if (rc != FM_OK) return rc;
-  if (!W64 && !W32) return fm_fail(ctx, FM_EINVAL, "fm_build_pair_grams: both outputs are NULL");
+  if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_build_pair_grams: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
   rc = weights ? launch_partial<W_ARRAY, true, false>(s, weights, 0, 0, nullptr, nullptr, nullptr, st)
                : launch_partial<W_UNIT, true, false>(s, nullptr, 0, 0, nullptr, nullptr, nullptr, st);
@@ -325,7 +325,7 @@ extern "C" fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* s, const float* pa
   fm_status rc = check_scene(ctx, s, "fm_reweight_build");
   if (rc != FM_OK) return rc;
   if ((rc = check_irls_args(ctx, "fm_reweight_build", params, delta, tau, kept)) != FM_OK) return rc;
-  if (!W64 && !W32) return fm_fail(ctx, FM_EINVAL, "fm_reweight_build: both outputs are NULL");
+  if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight_build: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
   unsigned long long* k = reinterpret_cast<unsigned long long*>(kept);
   if ((rc = launch_essentials(s, params, k, st)) != FM_OK) return rc;

@@ -235,8 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_camera_grad(const float* __restrict_
   }
 }
 
-static fm_status check_w(fm_ctx* ctx, const char* fn, const void* W36, fm_dtype wdt) {
-  if (!W36) return fm_fail(ctx, FM_EINVAL, "%s: W36 is NULL", fn);
+static fm_status check_w(fm_ctx* ctx, const char* fn, const void* W36, fm_dtype wdt, int64_t P) {
+  if (!W36 && P > 0) return fm_fail(ctx, FM_EINVAL, "%s: W36 is NULL", fn);
   if (wdt != FM_F64 && wdt != FM_F32) return fm_fail(ctx, FM_EDTYPE, "%s: W36 must be FM_F64 or FM_F32", fn);
   return FM_OK;
 }
@@ -247,9 +247,9 @@ extern "C" fm_status fm_epipolar_loss_grad(fm_ctx* ctx, fm_scene* s, const void*
   if (!ctx) return FM_EINVAL;
   if (!s) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: scene is NULL");
   if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: scene belongs to another context");
-  fm_status rc = check_w(ctx, "fm_epipolar_loss_grad", W36, wdt);
+  fm_status rc = check_w(ctx, "fm_epipolar_loss_grad", W36, wdt, s->P);
   if (rc != FM_OK) return rc;
-  if (!params) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: params is NULL");
+  if (!params && s->N > 0) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: params is NULL");
   if (!Z_dev && !(inv_Z >= 0.0)) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_loss_grad: inv_Z must be >= 0");
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
@@ -390,9 +390,10 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   if (!ctx) return FM_EINVAL;
   if (!s) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: scene is NULL");
   if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: scene belongs to another context");
-  fm_status rc = check_w(ctx, "fm_epipolar_solve", W36, wdt);
+  fm_status rc = check_w(ctx, "fm_epipolar_solve", W36, wdt, s->P);
   if (rc != FM_OK) return rc;
-  if (!params || !m || !v || !cfg) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: NULL argument");
+  if (!cfg || (s->N > 0 && (!params || !m || !v)))
+    return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: NULL argument");
   if (K < 0) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: K < 0");
   if (cfg->lr_total_steps <= 0 || cfg->lr_step0 < 0 || cfg->adam_step0 < 0 || !(cfg->lr_final_frac > 0.0f) ||
       !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f && cfg->eps >= 0.0f))

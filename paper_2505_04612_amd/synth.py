@@ -25,7 +25,11 @@ Scene recipes (sizes follow the five workloads the hot path is measured on):
   large    5,000 street cameras in a city-block grid, facade points,
            ~250k pairs / ~200M matches, BF16, sigma 1.5 px, 30 % outliers
 Every scene is reproducible from (recipe, seed); the pose initialisation uses
-seed + 10,000.
+seed + 10,000.  Epipolar adjustment refines poses that earlier stages
+(rotation and translation averaging) already estimated, so the initial poses
+are the true ones perturbed: tiny uses 5 deg rotation noise and 0.1 centre
+noise (radius-5 rig); the other recipes use 1 deg and a centre noise of a few
+percent of the camera spacing.  `init_trans="random"` gives N(0, I) centres.
 """
 from __future__ import annotations
 
@@ -169,6 +173,7 @@ def _init_poses(R_gt, t_gt, seed, rot_deg=5.0, trans="perturbed", centre_sigma=0
 def _assemble(name, seed, R_gt, t_gt, cam_a, cam_b, uv, outl, min_matches, storage,
               sigma, frac, init_kw):
     init_kw = {k: v for k, v in init_kw.items() if v is not None}
+    init_kw.setdefault("centre_sigma", 0.1)
     """Sort matches by pair, drop pairs with fewer than `min_matches`, build CSR."""
     n = R_gt.shape[0]
     key = cam_a.astype(np.int64) * n + cam_b.astype(np.int64)
@@ -250,15 +255,16 @@ def tiny(seed: int = 0, n_cams: int = 20, n_points: int = 2000, sigma: float = 0
                      {"trans": init_trans, "centre_sigma": init_sigma})
 
 
-def _helix_scene(name, seed, n_cams, n_points, sigma, frac, storage, min_matches=30,
-                 track_mean=6.0, track_sigma=0.4, init_trans="perturbed", init_sigma=None):
+def _helix_scene(name, seed, n_cams, n_points, sigma, frac, storage, min_matches=30, extent=1.0,
+                 track_mean=6.0, track_sigma=0.4, init_trans="perturbed", init_sigma=0.02,
+                 init_rot_deg=1.0):
     rng = np.random.default_rng(seed)
     phi = 2.0 * math.pi * 3.0 * np.arange(n_cams) / n_cams
     z = np.linspace(-2.0, 2.0, n_cams)
     c = np.stack([5.0 * np.cos(phi), 5.0 * np.sin(phi), z], axis=1)
     R = _jitter(_look_at(c, np.zeros_like(c)), rng, 3.0)
     t = -np.einsum("nab,nb->na", R, c)
-    X = rng.uniform(-1.0, 1.0, size=(n_points, 3))
+    X = rng.uniform(-extent, extent, size=(n_points, 3))
     nrm = _normalize(rng.normal(size=(n_points, 3)))
     # visibility [n_points, n_cams]
     vis = np.zeros((n_points, n_cams), dtype=bool)
@@ -293,12 +299,12 @@ def _helix_scene(name, seed, n_cams, n_points, sigma, frac, storage, min_matches
     obs_b = (pix[pts, cb, 0], pix[pts, cb, 1])
     uv, outl = _make_matches(rng, R, t, ca, cb, X[pts], sigma, frac, obs_a, obs_b)
     return _assemble(name, seed, R, t, ca, cb, uv, outl, min_matches, storage, sigma, frac,
-                     {"trans": init_trans, "centre_sigma": init_sigma})
+                     {"trans": init_trans, "centre_sigma": init_sigma, "rot_deg": init_rot_deg})
 
 
 def medium(seed: int = 1, n_cams: int = 200, n_points: int = 165_000, sigma: float = 1.0,
            frac: float = 0.20, init_trans: str = "perturbed",
-         init_sigma: float | None = None) -> Scene:
+           init_sigma: float = 0.02, init_rot_deg: float = 1.0) -> Scene:
     """200 cameras on a 3-loop helix (radius 5, z in [-2, 2]) aimed at the
     origin; points in [-1, 1]^3 with random normals; each point's track is a
     contiguous run (log-normal length, mean 6, log-sd 0.4) of the cameras that
@@ -306,16 +312,16 @@ def medium(seed: int = 1, n_cams: int = 200, n_points: int = 165_000, sigma: flo
     "~4k pairs, ~3M matches"; a 50k-point cloud with mean-6 tracks yields only
     ~0.9M matches once pairs below 30 matches are dropped)."""
     return _helix_scene("medium", seed, n_cams, n_points, sigma, frac, "f32",
-                        init_trans=init_trans, init_sigma=init_sigma)
+                        init_trans=init_trans, init_sigma=init_sigma, init_rot_deg=init_rot_deg)
 
 
 def learned(seed: int = 100, n_cams: int = 300, n_points: int = 280_000, sigma: float = 1.0,
             frac: float = 0.20, init_trans: str = "perturbed",
-         init_sigma: float | None = None) -> Scene:
+            init_sigma: float = 0.02, init_rot_deg: float = 1.0) -> Scene:
     """The medium recipe with 300 cameras (~5M matches); seeds 100-163 train,
     200-215 are held out."""
     return _helix_scene("learned", seed, n_cams, n_points, sigma, frac, "f32",
-                        init_trans=init_trans, init_sigma=init_sigma)
+                        init_trans=init_trans, init_sigma=init_sigma, init_rot_deg=init_rot_deg)
 
 
 def _powerlaw_sizes(rng, n, lo, hi, alpha):
@@ -334,7 +340,7 @@ def diffprec(seed: int = 2, nx: int = 20, ny: int = 50, height: float = 1.0,
              spacing: float = 0.22, sigma: float = 1.0, frac: float = 0.25,
              alpha: float = 1.45, size_lo: int = 20, size_hi: int = 20_000,
              max_pairs: int | None = None, init_trans: str = "perturbed",
-         init_sigma: float | None = None) -> Scene:
+             init_sigma: float = 0.01, init_rot_deg: float = 1.0) -> Scene:
     """1,000 nadir cameras on a 20x50 serpentine grid at height 1 over a relief
     ground plane; every pair of cameras whose footprints overlap gets a
     power-law number of matches (density k^-1.45 on [20, 20k]) sampled from
@@ -394,13 +400,13 @@ def diffprec(seed: int = 2, nx: int = 20, ny: int = 50, height: float = 1.0,
     ca, cb, X = ca[keep], cb[keep], X[keep]
     uv, outl = _make_matches(rng, R, t, ca, cb, X, sigma, frac)
     return _assemble("diffprec", seed, R, t, ca, cb, uv, outl, 20, "bf16", sigma, frac,
-                     {"trans": init_trans, "centre_sigma": init_sigma})
+                     {"trans": init_trans, "centre_sigma": init_sigma, "rot_deg": init_rot_deg})
 
 
 def large(seed: int = 3, blocks: int = 12, block: float = 10.0, street: float = 2.0,
           n_cams: int = 5000, pairs_per_cam: int = 100, mean_matches: float = 800.0,
           sigma: float = 1.5, frac: float = 0.30, init_trans: str = "perturbed",
-          init_sigma: float | None = None, scale: float = 1.0) -> Scene:
+          init_sigma: float = 0.03, init_rot_deg: float = 1.0, scale: float = 1.0) -> Scene:
     """5,000 street-level cameras in a blocks x blocks city grid, heading along
     their street with +-15 deg yaw jitter; matches are facade points (the two
     building faces lining the street) seen by two cameras on the same street.
@@ -474,7 +480,7 @@ def large(seed: int = 3, blocks: int = 12, block: float = 10.0, street: float = 
     ca, cb, X = ca[keep], cb[keep], X[keep]
     uv, outl = _make_matches(rng, R, t, ca, cb, X, sigma, frac)
     return _assemble("large", seed, R, t, ca, cb, uv, outl, 30, "bf16", sigma, frac,
-                     {"trans": init_trans, "centre_sigma": init_sigma})
+                     {"trans": init_trans, "centre_sigma": init_sigma, "rot_deg": init_rot_deg})
 
 
 RECIPES = {"tiny": tiny, "medium": medium, "diffprec": diffprec, "learned": learned,
