@@ -182,6 +182,20 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
                             double inv_Z, const int64_t* Z_dev, double* loss_trace,
                             fm_stream stream);
 
+/* ------------------------------------------------------------------ launch timing */
+
+/* Optional device-time measurement of the library's own launches (for
+ * roofline reporting): while enabled, every launch of the kernels below is
+ * bracketed by HIP events recorded on the launch's stream.
+ *   FM_K_GRAM 0 (Gram / reweight pass over the matches), FM_K_SOLVE 1 (fused
+ *   persistent loop), FM_K_ESSENTIALS 2, FM_K_FINALIZE 3, FM_K_PAIR 4 and
+ *   FM_K_CAMERA 5 (the two kernels of fm_epipolar_loss_grad).
+ * fm_profile_enable synchronises the device and clears earlier records;
+ * fm_profile_read waits for the recorded events and returns the summed
+ * elapsed milliseconds and the launch count of one kernel (host outputs). */
+fm_status fm_profile_enable(fm_ctx* ctx, int enable);
+fm_status fm_profile_read(fm_ctx* ctx, int kernel, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

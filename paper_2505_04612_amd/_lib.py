@@ -23,7 +23,9 @@ EXPORTS = [
     "fm_scene_create", "fm_scene_destroy", "fm_scene_work_items",
     "fm_build_pair_grams", "fm_reweight", "fm_reweight_build",
     "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve",
+    "fm_profile_enable", "fm_profile_read",
 ]
+K_GRAM, K_SOLVE, K_ESSENTIALS, K_FINALIZE, K_PAIR, K_CAMERA = range(6)
 
 
 class FastMapError(RuntimeError):
@@ -69,6 +71,8 @@ _SIGNATURES = {
     "fm_epipolar_loss_grad": (_S, [_P, _P, _P, _S, _P, _D, _P, _P, _P, _P]),
     "fm_adam_step": (_S, [_P, _I64, _P, _P, _P, _P, _I64, _P, _S, _F, _F, _F, _P]),
     "fm_epipolar_solve": (_S, [_P, _P, _P, _S, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _D, _P, _P, _P]),
+    "fm_profile_enable": (_S, [_P, _S]),
+    "fm_profile_read": (_S, [_P, _S, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
 
 _lib = None

@@ -57,6 +57,16 @@ class Context:
             self.lib.fm_destroy(self.handle)
             self.handle = None
 
+    def profile(self, enable: bool) -> None:
+        """Start (clearing earlier records) or stop launch timing."""
+        check(self.handle, self.lib.fm_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self, kernel: int) -> tuple[float, int]:
+        """(summed device milliseconds, launches) of one kernel id (_lib.K_*)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(self.handle, self.lib.fm_profile_read(self.handle, kernel, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def __del__(self):
         try:
             self.close()

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "fastmap_hip.h"
 
@@ -17,10 +18,32 @@ constexpr int kGramWaves = 4;
 // Threads per block of the per-pair and per-camera kernels.
 constexpr int kBlock = 256;
 
+// Kernel identifiers of the optional launch timing (fm_profile_*).
+enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
+       FM_K_COUNT = 6 };
+
+struct fm_timing {
+  int kernel;
+  hipEvent_t start, stop;
+};
+
 struct fm_ctx {
   int device = 0;
   int num_cu = 0;
   std::string err;
+  bool profile = false;
+  std::vector<fm_timing> timings;    // recorded launches (profiling on)
+  std::vector<hipEvent_t> event_pool;
+};
+
+// Bracket a kernel launch with events on its stream when profiling is on.
+struct fm_timed {
+  fm_ctx* ctx;
+  int kernel;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  fm_timed(fm_ctx* c, int k, hipStream_t s);
+  ~fm_timed();
 };
 
 struct fm_scene {

@@ -247,6 +247,7 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
                                 float* r_out, unsigned long long* kept, hipStream_t st) {
   if (s->n_wi == 0) return FM_OK;
   const dim3 grid(grid_for(s->n_wi, kGramWaves)), block(kGramWaves * kLanes);
+  fm_timed timer(s->ctx, FM_K_GRAM, st);
   switch (s->dtype) {
     case FM_F32:
       hipLaunchKernelGGL((k_gram_partial<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
@@ -267,6 +268,7 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
 
 static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, hipStream_t st) {
   if (s->P == 0) return FM_OK;
+  fm_timed timer(s->ctx, FM_K_FINALIZE, st);
   hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(s->P * 36, kBlock)), dim3(kBlock), 0, st, s->partials,
                      s->wi_off, s->P, W64, W32);
   FM_CHECK_LAUNCH(s->ctx);
@@ -274,6 +276,7 @@ static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, hipStream
 }
 
 static fm_status launch_essentials(fm_scene* s, const float* params, unsigned long long* kept, hipStream_t st) {
+  fm_timed timer(s->ctx, FM_K_ESSENTIALS, st);
   hipLaunchKernelGGL(k_pair_essentials, dim3(grid_for(s->P > 0 ? s->P : 1, kBlock)), dim3(kBlock), 0, st, params,
                      s->pair_cams, s->P, s->ess, kept);
   FM_CHECK_LAUNCH(s->ctx);

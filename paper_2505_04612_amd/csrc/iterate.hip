@@ -254,14 +254,18 @@ extern "C" fm_status fm_epipolar_loss_grad(fm_ctx* ctx, fm_scene* s, const void*
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const unsigned gp = grid_for(s->P > 0 ? s->P : 1, kBlock);
+  {
+  fm_timed timer(ctx, FM_K_PAIR, st);
   if (wdt == FM_F64)
     hipLaunchKernelGGL(k_pair_phase<double>, dim3(gp), dim3(kBlock), 0, st, params, s->pair_cams,
                        (const double*)W36, s->P, inv_Z, Z_dev, s->contrib, s->loss_part);
   else
     hipLaunchKernelGGL(k_pair_phase<float>, dim3(gp), dim3(kBlock), 0, st, params, s->pair_cams,
                        (const float*)W36, s->P, inv_Z, Z_dev, s->contrib, s->loss_part);
+  }
   FM_CHECK_LAUNCH(ctx);
   const unsigned gc = grid_for((int64_t)(s->N > 0 ? s->N : 1) * 64, kBlock);
+  fm_timed timer(ctx, FM_K_CAMERA, st);
   hipLaunchKernelGGL(k_camera_grad, dim3(gc), dim3(kBlock), 0, st, params, s->cam_ptr, s->cam_items, s->contrib,
                      s->N, s->loss_part, (int64_t)gp, inv_Z, Z_dev, grad, loss);
   FM_CHECK_LAUNCH(ctx);
@@ -418,6 +422,7 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;
   a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
   void* args[] = {&a};
+  fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
   hipError_t e = wdt == FM_F64
                      ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want), dim3(kBlock),
                                                   args, 0, (hipStream_t)stream)

@@ -37,7 +37,79 @@ extern "C" fm_status fm_create(fm_ctx** out, int device) {
   return FM_OK;
 }
 
-extern "C" void fm_destroy(fm_ctx* ctx) { delete ctx; }
+static hipEvent_t pool_get(fm_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+fm_timed::fm_timed(fm_ctx* c, int k, hipStream_t s) : ctx(c), kernel(k), st(s) {
+  if (ctx && ctx->profile) {
+    a = pool_get(ctx);
+    b = pool_get(ctx);
+    if (a) (void)hipEventRecord(a, st);
+  }
+}
+
+fm_timed::~fm_timed() {
+  if (a && b) {
+    (void)hipEventRecord(b, st);
+    ctx->timings.push_back({kernel, a, b});
+  } else {
+    if (a) ctx->event_pool.push_back(a);
+    if (b) ctx->event_pool.push_back(b);
+  }
+}
+
+static void release_timings(fm_ctx* ctx) {
+  for (auto& t : ctx->timings) {
+    ctx->event_pool.push_back(t.start);
+    ctx->event_pool.push_back(t.stop);
+  }
+  ctx->timings.clear();
+}
+
+extern "C" fm_status fm_profile_enable(fm_ctx* ctx, int enable) {
+  if (!ctx) return FM_EINVAL;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  FM_HIP_TRY(ctx, hipDeviceSynchronize());
+  release_timings(ctx);
+  ctx->profile = enable != 0;
+  return FM_OK;
+}
+
+extern "C" fm_status fm_profile_read(fm_ctx* ctx, int kernel, double* total_ms, int64_t* launches) {
+  if (!ctx) return FM_EINVAL;
+  if (!total_ms || !launches) return fm_fail(ctx, FM_EINVAL, "fm_profile_read: NULL output");
+  if (kernel < 0 || kernel >= FM_K_COUNT) return fm_fail(ctx, FM_EINVAL, "fm_profile_read: unknown kernel %d", kernel);
+  double sum = 0.0;
+  int64_t n = 0;
+  for (auto& t : ctx->timings) {
+    if (t.kernel != kernel) continue;
+    FM_HIP_TRY(ctx, hipEventSynchronize(t.stop));
+    float ms = 0.0f;
+    FM_HIP_TRY(ctx, hipEventElapsedTime(&ms, t.start, t.stop));
+    sum += ms;
+    ++n;
+  }
+  *total_ms = sum;
+  *launches = n;
+  return FM_OK;
+}
+
+extern "C" void fm_destroy(fm_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  release_timings(ctx);
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
 
 extern "C" const char* fm_last_error(const fm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
