@@ -182,6 +182,46 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
                             double inv_Z, const int64_t* Z_dev, double* loss_trace,
                             fm_stream stream);
 
+/* ------------------------------------------------------------------ a9: learned weights */
+
+/* Learned robust weights (an addition to the paper's IRLS, Sec. 3.3): a
+ * 3 -> 64 -> 64 -> 1 MLP (ReLU, ReLU, sigmoid) maps per-match features to a
+ * weight proposal in [0, 1].
+ *
+ * fm_match_features: at poses `params` [N,9] float32, per match
+ *   feats[m] = (log max(|r|, delta), log |Q_n|, parallax angle in radians
+ *               between the bearing rays R_i^T x1~ and R_j^T x2~)   [M,3] float32
+ * (r in float64 as in fm_reweight). */
+fm_status fm_match_features(fm_ctx* ctx, fm_scene* scene, const float* params, float delta,
+                            float* feats, fm_stream stream);
+
+/* Network weights, row-major [out, in], float32 device arrays:
+ *   W1 [64,3], b1 [64], W2 [64,64], b2 [64], W3 [1,64], b3 [1];
+ *   feat_mean [3], feat_std [3]: inputs are standardised (f - mean) / std. */
+typedef struct {
+  const float *W1, *b1, *W2, *b2, *W3, *b3, *feat_mean, *feat_std;
+} fm_mlp;
+
+typedef struct {
+  float *W1, *b1, *W2, *b2, *W3, *b3;
+} fm_mlp_grad;
+
+/* out[m] = out_scale * sigmoid(z3[m]) for M matches.  The 64x64 layer runs
+ * on MFMA with float16 operands and float32 accumulation; the first and last
+ * layers in float32.  If `act` is given ([M,128] float16, device), the
+ * post-ReLU activations of both hidden layers are kept for fm_mlp_backward. */
+fm_status fm_mlp_forward(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
+                         float out_scale, float* out, void* act, fm_stream stream);
+
+/* Gradients of sum_m dout[m] * sigmoid(z3[m]) with respect to every weight
+ * (fully overwritten, float32), from the activations kept by the forward
+ * (z3 is recomputed from them).  Reductions over matches are deterministic:
+ * per-wavefront partial sums, then a sum over wavefronts in a fixed order.
+ * Uses a context-owned workspace that grows on demand (the first call with a
+ * larger M synchronises `stream` and allocates). */
+fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
+                          const void* act, const float* dout, fm_mlp_grad* g, fm_stream stream);
+
 /* ------------------------------------------------------------------ launch timing */
 
 /* Optional device-time measurement of the library's own launches (for

@@ -24,6 +24,7 @@ EXPORTS = [
     "fm_build_pair_grams", "fm_reweight", "fm_reweight_build",
     "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve",
     "fm_profile_enable", "fm_profile_read",
+    "fm_match_features", "fm_mlp_forward", "fm_mlp_backward",
 ]
 K_GRAM, K_SOLVE, K_ESSENTIALS, K_FINALIZE, K_PAIR, K_CAMERA = range(6)
 
@@ -43,7 +44,7 @@ class AdamCfg(ctypes.Structure):
 
 
 class Mlp(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("W1", "b1", "W2", "b2", "W3", "b3", "feat_mean", "feat_std")]
 
 
 class MlpGrad(ctypes.Structure):
@@ -72,6 +73,9 @@ _SIGNATURES = {
     "fm_adam_step": (_S, [_P, _I64, _P, _P, _P, _P, _I64, _P, _S, _F, _F, _F, _P]),
     "fm_epipolar_solve": (_S, [_P, _P, _P, _S, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _D, _P, _P, _P]),
     "fm_profile_enable": (_S, [_P, _S]),
+    "fm_match_features": (_S, [_P, _P, _P, _F, _P, _P]),
+    "fm_mlp_forward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _F, _P, _P, _P]),
+    "fm_mlp_backward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(MlpGrad), _P]),
     "fm_profile_read": (_S, [_P, _S, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
 

@@ -253,3 +253,79 @@ def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: tor
     check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_solve(
         scene.ctx.handle, scene.handle, _ptr(W36), _wdtype(W36), _ptr(params), _ptr(m), _ptr(v), int(K),
         ctypes.byref(cfg), float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss_trace), _stream()))
+
+
+# ------------------------------------------------------------------ a9: learned weights
+
+MLP_SHAPES = {"W1": (64, 3), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (1, 64), "b3": (1,)}
+
+
+class MlpWeights:
+    """The MLP's float32 weights as views into one flat device tensor (so one
+    fm_adam_step updates them all), plus the feature standardisation."""
+
+    def __init__(self, device, flat: torch.Tensor | None = None, mean=None, std=None):
+        n = sum(int(np.prod(s)) for s in MLP_SHAPES.values())
+        self.flat = torch.zeros(n, dtype=torch.float32, device=device) if flat is None else flat
+        assert self.flat.numel() == n and self.flat.dtype == torch.float32
+        self.views = {}
+        o = 0
+        for k, s in MLP_SHAPES.items():
+            c = int(np.prod(s))
+            self.views[k] = self.flat[o:o + c].view(*s)
+            o += c
+        self.mean = torch.zeros(3, dtype=torch.float32, device=device) if mean is None else mean
+        self.std = torch.ones(3, dtype=torch.float32, device=device) if std is None else std
+
+    def struct(self):
+        v = self.views
+        return _lib.Mlp(*(_ptr(v[k]) for k in MLP_SHAPES), _ptr(self.mean), _ptr(self.std))
+
+    def grad_struct(self, g: "MlpWeights"):
+        return _lib.MlpGrad(*(_ptr(g.views[k]) for k in MLP_SHAPES))
+
+    def load_numpy(self, params: dict, mean, std) -> None:
+        for k in MLP_SHAPES:
+            self.views[k].copy_(torch.as_tensor(np.asarray(params[k], dtype=np.float32)))
+        self.mean.copy_(torch.as_tensor(np.asarray(mean, dtype=np.float32)))
+        self.std.copy_(torch.as_tensor(np.asarray(std, dtype=np.float32)))
+
+    def to_numpy(self) -> dict:
+        return {k: v.detach().cpu().numpy().astype(np.float64) for k, v in self.views.items()}
+
+
+def match_features(scene: Scene, params: torch.Tensor, delta: float) -> torch.Tensor:
+    """[M,3] float32 features (log max(|r|, delta), log |Q_n|, parallax)."""
+    dev = scene.ctx.device
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    f = torch.empty((scene.num_matches, 3), dtype=torch.float32, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_match_features(scene.ctx.handle, scene.handle, _ptr(params),
+                                                            float(delta), _ptr(f), _stream()))
+    return f
+
+
+def mlp_forward(ctx: Context, w: MlpWeights, feats: torch.Tensor, out_scale: float = 1.0,
+                keep_act: bool = False):
+    """(out [M] float32, act [M,128] float16 | None)."""
+    M = int(feats.shape[0])
+    _require(feats, torch.float32, (M, 3), "feats", ctx.device)
+    out = torch.empty(M, dtype=torch.float32, device=ctx.device)
+    act = torch.empty((M, 128), dtype=torch.float16, device=ctx.device) if keep_act else None
+    st = w.struct()
+    check(ctx.handle, ctx.lib.fm_mlp_forward(ctx.handle, M, _ptr(feats), ctypes.byref(st), float(out_scale),
+                                             _ptr(out), _ptr(act), _stream()))
+    return out, act
+
+
+def mlp_backward(ctx: Context, w: MlpWeights, feats: torch.Tensor, act: torch.Tensor, dout: torch.Tensor,
+                 grad: MlpWeights | None = None) -> MlpWeights:
+    """Gradients of sum(dout * out) into `grad` (allocated if None)."""
+    M = int(feats.shape[0])
+    _require(feats, torch.float32, (M, 3), "feats", ctx.device)
+    _require(act, torch.float16, (M, 128), "act", ctx.device)
+    _require(dout, torch.float32, (M,), "dout", ctx.device)
+    g = grad if grad is not None else MlpWeights(ctx.device)
+    st, gs = w.struct(), w.grad_struct(g)
+    check(ctx.handle, ctx.lib.fm_mlp_backward(ctx.handle, M, _ptr(feats), ctypes.byref(st), _ptr(act),
+                                              _ptr(dout), ctypes.byref(gs), _stream()))
+    return g

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastmap_hip.so")
-SOURCES = ["scene.hip", "gram.hip", "iterate.hip"]
+SOURCES = ["scene.hip", "gram.hip", "iterate.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 

@@ -34,6 +34,8 @@ struct fm_ctx {
   bool profile = false;
   std::vector<fm_timing> timings;    // recorded launches (profiling on)
   std::vector<hipEvent_t> event_pool;
+  void* ws = nullptr;                // grow-only workspace (MLP gradient slots)
+  size_t ws_bytes = 0;
 };
 
 // Bracket a kernel launch with events on its stream when profiling is on.

@@ -283,6 +283,10 @@ static fm_status launch_essentials(fm_scene* s, const float* params, unsigned lo
   return FM_OK;
 }
 
+fm_status fm_launch_essentials(fm_scene* s, const float* params, unsigned long long* kept, hipStream_t st) {
+  return launch_essentials(s, params, kept, st);
+}
+
 static fm_status check_scene(fm_ctx* ctx, fm_scene* s, const char* fn) {
   if (!ctx) return FM_EINVAL;
   if (!s) return fm_fail(ctx, FM_EINVAL, "%s: scene is NULL", fn);

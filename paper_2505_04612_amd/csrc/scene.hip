@@ -108,6 +108,7 @@ extern "C" void fm_destroy(fm_ctx* ctx) {
   (void)hipDeviceSynchronize();
   release_timings(ctx);
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  (void)hipFree(ctx->ws);
   delete ctx;
 }
 

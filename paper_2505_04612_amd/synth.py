@@ -337,7 +337,7 @@ def _relief(x, y):
 
 
 def diffprec(seed: int = 2, nx: int = 20, ny: int = 50, height: float = 1.0,
-             spacing: float = 0.22, sigma: float = 1.0, frac: float = 0.25,
+             spacing: float = 0.17, sigma: float = 1.0, frac: float = 0.25,
              alpha: float = 1.45, size_lo: int = 20, size_hi: int = 20_000,
              max_pairs: int | None = None, init_trans: str = "perturbed",
              init_sigma: float = 0.01, init_rot_deg: float = 1.0) -> Scene:

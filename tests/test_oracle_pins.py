@@ -388,3 +388,67 @@ def test_pins_catch_planted_mistakes(tiny_clean, monkeypatch):
     brute = float(np.sum(np.einsum("ma,ab,mb->m", x2, E, x1) ** 2))
     assert not math.isclose(float(E.reshape(9) @ W_bad[0] @ E.reshape(9)), brute, rel_tol=1e-6)
     assert np.linalg.norm(good) > 0
+
+
+# ----------------------------------------------------------- learned-weight MLP
+
+def test_mlp_backward_matches_central_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(21)
+    p = mlp.init_params(3)
+    for k in p:
+        p[k] = p[k] + rng.normal(0, 0.05, p[k].shape)
+    feats = rng.normal(size=(40, 3)) * [2.0, 1.0, 0.1] + [-6.0, 5.0, 0.2]
+    mean, std = np.array([-6.0, 5.0, 0.2]), np.array([2.0, 1.0, 0.1])
+    dout = rng.normal(size=40)
+    g = mlp.backward(p, feats, mean, std, dout)
+    h = 1e-6
+    for k, shape in mlp.SHAPES.items():
+        for _ in range(4):
+            idx = tuple(rng.integers(0, s) for s in shape)
+            pp = {q: v.copy() for q, v in p.items()}
+            pm = {q: v.copy() for q, v in p.items()}
+            pp[k][idx] += h
+            pm[k][idx] -= h
+            fd = (np.sum(dout * mlp.forward(pp, feats, mean, std)[0])
+                  - np.sum(dout * mlp.forward(pm, feats, mean, std)[0])) / (2 * h)
+            assert abs(fd - g[k][idx]) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, g[k][idx])
+
+
+def test_mlp_closed_forms():
+    """Zero weights give sigmoid(b3); a single active path gives the product
+    of its weights."""
+    from oracle import mlp
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES.items()}
+    p["b3"][0] = 0.3
+    f = np.random.default_rng(0).normal(size=(5, 3))
+    out, _ = mlp.forward(p, f, np.zeros(3), np.ones(3))
+    assert np.allclose(out, 1.0 / (1.0 + np.exp(-0.3)))
+    p["W1"][7, 2] = 2.0
+    p["W2"][11, 7] = 0.5
+    p["W3"][0, 11] = 3.0
+    f = np.array([[0.0, 0.0, 1.5], [0.0, 0.0, -1.0]])
+    out, _ = mlp.forward(p, f, np.zeros(3), np.ones(3))
+    z = np.array([0.3 + 3.0 * 0.5 * 2.0 * 1.5, 0.3])
+    assert np.allclose(out, 1.0 / (1.0 + np.exp(-z)))
+
+
+def test_match_features_closed_form():
+    """Two cameras looking down +z, the second shifted by b along x: a point
+    at depth D straight ahead of camera 1 has parallax atan(b/D), zero
+    residual at the true poses, and f1 = log(#matches)."""
+    from oracle import mlp
+    b, D = 0.5, 4.0
+    R = np.stack([np.eye(3), np.eye(3)])
+    t = np.array([[0.0, 0.0, 0.0], [-b, 0.0, 0.0]])
+    th = ea.params_from_poses(R, t)
+    X = np.array([[0.0, 0.0, D], [0.3, -0.2, 2.0 * D]])
+    uv = np.stack([X[:, 0] / X[:, 2], X[:, 1] / X[:, 2], (X[:, 0] - b) / X[:, 2], X[:, 1] / X[:, 2]], axis=1)
+    f = mlp.features(th, np.array([[0, 1]]), np.array([0, 2]), uv, 1e-4)
+    assert np.allclose(f[:, 0], np.log(1e-4))
+    assert np.allclose(f[:, 1], np.log(2.0))
+    assert np.isclose(f[0, 2], np.arctan2(b, D), atol=1e-12)
+    c2 = np.array([b, 0.0, 0.0])
+    a1, a2 = X[1], X[1] - c2
+    ang = np.arccos(a1 @ a2 / np.linalg.norm(a1) / np.linalg.norm(a2))
+    assert np.isclose(f[1, 2], ang, atol=1e-9)
