@@ -6,7 +6,9 @@ CUDA (HIP) tensors on the context's device.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
 import torch
@@ -75,6 +77,7 @@ class Context:
 
 
 _default_ctx: Context | None = None
+_live_scenes: "weakref.WeakSet[Scene]" = weakref.WeakSet()
 
 
 def default_context() -> Context:
@@ -82,6 +85,21 @@ def default_context() -> Context:
     if _default_ctx is None:
         _default_ctx = Context(torch.cuda.current_device())
     return _default_ctx
+
+
+@atexit.register
+def _shutdown() -> None:
+    """Release scenes and the default context while the HIP runtime is still
+    up (interpreter teardown order is otherwise unspecified)."""
+    global _default_ctx
+    try:
+        for s in list(_live_scenes):
+            s.close()
+        if _default_ctx is not None:
+            _default_ctx.close()
+            _default_ctx = None
+    except Exception:
+        pass
 
 
 class Scene:
@@ -107,6 +125,7 @@ class Scene:
                                      _DTYPES[uv.dtype], _stream(), ctypes.byref(h))
         check(ctx.handle, rc)
         self.handle = h
+        _live_scenes.add(self)
 
     @classmethod
     def from_numpy(cls, ctx: Context, num_cams: int, pairs: np.ndarray, offsets: np.ndarray,

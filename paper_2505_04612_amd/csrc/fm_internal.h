@@ -59,6 +59,7 @@ struct fm_scene {
   // derived index data
   int64_t n_wi = 0;               // Gram work items
   int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
+  int32_t* wi_pair = nullptr;     // [n_wi] pair of each work item
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order
   // workspace

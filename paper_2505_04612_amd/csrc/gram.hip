@@ -14,98 +14,63 @@
 
 enum { W_UNIT = 0, W_ARRAY = 1, W_IRLS = 2 };
 
-template <int DT>
-__device__ inline float4 load_match(const void* uv, int64_t m) {
-  if constexpr (DT == FM_F32) {
-    return reinterpret_cast<const float4*>(uv)[m];
-  } else if constexpr (DT == FM_BF16) {
-    // four bf16 values: the float32 with the same upper 16 bits
-    uint2 q = reinterpret_cast<const uint2*>(uv)[m];
-    return make_float4(__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xffff0000u),
-                       __uint_as_float(q.y << 16), __uint_as_float(q.y & 0xffff0000u));
-  } else {
-    const double2* d = reinterpret_cast<const double2*>(uv) + 2 * m;
-    double2 a = d[0], b = d[1];
-    return make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+// Lane exchange partners for the reduce-scatter.  Stages over lane bits 3,
+// 2, 1, 0 use DPP within 16-lane rows (row_mirror pairs l with 15-l,
+// row_half_mirror pairs l with 7-l inside each half row, quad_perm swaps
+// neighbours 2 and 1 apart); bits 4 and 5 cross rows and use a lane
+// permute.  Each pairing is an involution whose partner has the opposite
+// value of the stage's bit and the same value of every bit already reduced,
+// which is all a reduce-scatter needs.
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppRowMirror = 0x140, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+
+template <int S, int BIT>
+__device__ inline float partner(float v) {
+  if constexpr (BIT == 3) return dpp_mov<kDppRowMirror>(v);
+  else if constexpr (BIT == 2) return dpp_mov<kDppHalfMirror>(v);
+  else if constexpr (BIT == 1) return dpp_mov<kDppXor2>(v);
+  else if constexpr (BIT == 0) return dpp_mov<kDppXor1>(v);
+  else return __shfl_xor(v, 1 << BIT);
+}
+
+// One stage: keep the lower (bit clear) or upper (bit set) half of S values,
+// padded to an even count, and add the partner's copy of that half.
+template <int S, int BIT>
+__device__ inline void rs_stage(const float (&in)[S], float (&out)[(S + 1) / 2], int lane) {
+  constexpr int H = (S + 1) / 2;
+  const bool up = (lane >> BIT) & 1;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float lo = in[k];
+    const float hi = (k + H < S) ? in[k + H] : 0.0f;
+    out[k] = (up ? hi : lo) + partner<S, BIT>(up ? lo : hi);
   }
 }
 
-// The exact float64 value of the stored coordinates (used for the residual).
-template <int DT>
-__device__ inline void load_match_f64(const void* uv, int64_t m, float4 f, double x[4]) {
-  if constexpr (DT == FM_F64) {
-    const double2* d = reinterpret_cast<const double2*>(uv) + 2 * m;
-    double2 a = d[0], b = d[1];
-    x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
-  } else {
-    x[0] = f.x; x[1] = f.y; x[2] = f.z; x[3] = f.w;
-  }
-}
-
-// Reduce-scatter of 36 per-lane values over the 64 lanes of a wavefront.
-// Stage k exchanges half of the current values with the lane whose index
-// differs in bit (5 - k) and keeps the other half (padded to an even count);
-// after six stages each lane holds the wave total of at most one entry.
-// Returns that total; `slot` receives the entry index or -1.
+// Reduce-scatter of 36 per-lane values over the 64 lanes of a wavefront
+// (36 -> 18 -> 9 -> 5 -> 3 -> 2 -> 1 values per lane over lane bits 3, 2, 1,
+// 0, 4, 5); afterwards 36 of the 64 lanes each hold the wave total of one
+// entry.  Returns that total; `slot` receives the entry index or -1.
 __device__ inline float wave_reduce_scatter36(const float (&a)[36], int lane, int& slot) {
-  float b[18], c[9], d[5], e[3], f[2];
-  bool up = (lane & 32) != 0;
-#pragma unroll
-  for (int k = 0; k < 18; ++k) {
-    float send = up ? a[k] : a[k + 18];
-    float keep = up ? a[k + 18] : a[k];
-    b[k] = keep + __shfl_xor(send, 32);
-  }
-  up = (lane & 16) != 0;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    float send = up ? b[k] : b[k + 9];
-    float keep = up ? b[k + 9] : b[k];
-    c[k] = keep + __shfl_xor(send, 16);
-  }
-  up = (lane & 8) != 0;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    float hi = (k + 5 < 9) ? c[k + 5] : 0.0f;
-    float send = up ? c[k] : hi;
-    float keep = up ? hi : c[k];
-    d[k] = keep + __shfl_xor(send, 8);
-  }
-  up = (lane & 4) != 0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    float hi = (k + 3 < 5) ? d[k + 3] : 0.0f;
-    float send = up ? d[k] : hi;
-    float keep = up ? hi : d[k];
-    e[k] = keep + __shfl_xor(send, 4);
-  }
-  up = (lane & 2) != 0;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    float hi = (k + 2 < 3) ? e[k + 2] : 0.0f;
-    float send = up ? e[k] : hi;
-    float keep = up ? hi : e[k];
-    f[k] = keep + __shfl_xor(send, 2);
-  }
-  up = (lane & 1) != 0;
-  float g = (up ? f[1] : f[0]) + __shfl_xor(up ? f[0] : f[1], 1);
-  // entry index held by this lane (see the stage sizes 36, 18, 9, 5, 3, 2)
-  int x = lane & 1;
-  int y = x + 2 * ((lane >> 1) & 1);
-  int z = y + 3 * ((lane >> 2) & 1);
-  int w = z + 5 * ((lane >> 3) & 1);
-  slot = (y < 3 && z < 5 && w < 9) ? w + 9 * ((lane >> 4) & 1) + 18 * ((lane >> 5) & 1) : -1;
-  return g;
-}
-
-__device__ inline int64_t find_pair(const int64_t* wi_off, int64_t P, int64_t w) {
-  // largest n with wi_off[n] <= w; wi_off[0] = 0 <= w < wi_off[P]
-  int64_t lo = 0, hi = P;
-  while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
-    if (wi_off[mid] <= w) lo = mid; else hi = mid;
-  }
-  return lo;
+  float b[18], c[9], d[5], e[3], f[2], g[1];
+  rs_stage<36, 3>(a, b, lane);
+  rs_stage<18, 2>(b, c, lane);
+  rs_stage<9, 1>(c, d, lane);
+  rs_stage<5, 0>(d, e, lane);
+  rs_stage<3, 4>(e, f, lane);
+  rs_stage<2, 5>(f, g, lane);
+  // position of the kept value, walking the stages backwards
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  const int b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+  const int x = b5;               // in the 2 values of stage 5
+  const int y = x + 2 * b4;       // in the 3 values of stage 4
+  const int z = y + 3 * b0;       // in the 5 values of stage 3
+  const int w = z + 5 * b1;       // in the 9 values of stage 2
+  slot = (y < 3 && z < 5 && w < 9) ? w + 9 * b2 + 18 * b3 : -1;
+  return g[0];
 }
 
 __device__ inline void accumulate36(float (&acc)[36], float4 x, float om) {
@@ -120,78 +85,119 @@ __device__ inline void accumulate36(float (&acc)[36], float4 x, float om) {
   }
 }
 
-// One wavefront per work item.  WMODE: W_UNIT (omega = 1), W_ARRAY (omega from
-// `weights`) or W_IRLS (omega from the residual at E_n).  BUILD: accumulate the
-// Gram partials.  WRITE: store omega (and r if r_out) per match.
+// Raw storage of one match row per lane.
+template <int DT> struct RawMatch;
+template <> struct RawMatch<FM_F32> { using T = float4; };
+template <> struct RawMatch<FM_BF16> { using T = uint2; };
+template <> struct RawMatch<FM_F64> { using T = double4; };
+
+template <int DT>
+__device__ inline typename RawMatch<DT>::T load_raw(const void* uv, int64_t m) {
+  if constexpr (DT == FM_F32) {
+    return reinterpret_cast<const float4*>(uv)[m];
+  } else if constexpr (DT == FM_BF16) {
+    return reinterpret_cast<const uint2*>(uv)[m];
+  } else {
+    const double2* d = reinterpret_cast<const double2*>(uv) + 2 * m;
+    const double2 a = d[0], b = d[1];
+    return double4{a.x, a.y, b.x, b.y};
+  }
+}
+
+template <int DT>
+__device__ inline void unpack(const typename RawMatch<DT>::T& r, float4& f, double x[4]) {
+  if constexpr (DT == FM_F32) {
+    f = r;
+  } else if constexpr (DT == FM_BF16) {
+    // bf16 -> the float32 with the same upper 16 bits
+    f = make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                    __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+  } else {
+    f = make_float4((float)r.x, (float)r.y, (float)r.z, (float)r.w);
+  }
+  if constexpr (DT == FM_F64) {
+    x[0] = r.x; x[1] = r.y; x[2] = r.z; x[3] = r.w;
+  } else {
+    x[0] = f.x; x[1] = f.y; x[2] = f.z; x[3] = f.w;
+  }
+}
+
+// One wavefront per work item (<= 1024 matches of one pair).  All rows of
+// the chunk are loaded before any is used, so a wavefront has its whole
+// chunk in flight (16 KB for float32 rows).  WMODE: W_UNIT (omega = 1),
+// W_ARRAY (omega from `weights`) or W_IRLS (omega from the float64 residual
+// at E_n).  BUILD: accumulate the Gram partials.  WRITE: store omega (and r
+// if r_out) per match.
 template <int DT, int WMODE, bool BUILD, bool WRITE>
 __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int64_t* __restrict__ wi_off,
-    int64_t P, int64_t n_wi, const float* __restrict__ weights, const double* __restrict__ ess,
-    double delta, double tau, float* __restrict__ partials, float* __restrict__ w_out,
-    float* __restrict__ r_out, unsigned long long* __restrict__ kept) {
+    const int32_t* __restrict__ wi_pair, int64_t n_wi, const float* __restrict__ weights,
+    const double* __restrict__ ess, double delta, double tau, float* __restrict__ partials,
+    float* __restrict__ w_out, float* __restrict__ r_out, unsigned long long* __restrict__ kept) {
+  constexpr int kRows = kPerLane;                     // rows of 64 matches per work item
+  constexpr int kBatch = (DT == FM_F64) ? 4 : kRows;  // rows loaded together
   const int lane = threadIdx.x & (kLanes - 1);
   const int64_t w = (int64_t)blockIdx.x * kGramWaves + (threadIdx.x >> 6);
   if (w >= n_wi) return;  // whole wavefront
-  const int64_t n = find_pair(wi_off, P, w);
+  const int64_t n = wi_pair[w];
   const int64_t start = off[n] + (w - wi_off[n]) * kChunk;
-  const int64_t stop = min(off[n + 1], start + kChunk);
-  const int count = (int)(stop - start);
+  const int count = (int)min(off[n + 1] - start, (int64_t)kChunk);
+  const int nrows = (count + kLanes - 1) / kLanes;
   double E[9];
   if constexpr (WMODE == W_IRLS) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) E[k] = ess[n * 9 + k];
   }
+  const float fdelta = (float)delta;
   float acc[36];
 #pragma unroll
   for (int k = 0; k < 36; ++k) acc[k] = 0.0f;
   unsigned nkept = 0;
-  // groups of 4 matches per lane; the group loop exits uniformly
 #pragma unroll
-  for (int g = 0; g < kPerLane / 4; ++g) {
-    if (g * 4 * kLanes >= count) break;
-    // lanes past the end of the chunk load the chunk's first match (always
-    // in bounds) and get weight 0
-    float4 xs[4];
-    bool ok[4];
-    int64_t mi[4];
+  for (int r0 = 0; r0 < kRows; r0 += kBatch) {
+    if (r0 >= nrows) break;
+    typename RawMatch<DT>::T raw[kBatch];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = (g * 4 + r) * kLanes + lane;
-      ok[r] = i < count;
-      mi[r] = ok[r] ? start + i : start;
-      xs[r] = load_match<DT>(uv, mi[r]);
+    for (int r = 0; r < kBatch; ++r) {
+      if (r0 + r < nrows) {
+        // lanes past the end of the chunk load its first match (in bounds)
+        const int i = (r0 + r) * kLanes + lane;
+        raw[r] = load_raw<DT>(uv, i < count ? start + i : start);
+      }
     }
-    float oms[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t m = mi[r];
-      float om = ok[r] ? 1.0f : 0.0f;
+    for (int r = 0; r < kBatch; ++r) {
+      if (r0 + r < nrows) {
+      const int i = (r0 + r) * kLanes + lane;
+      const bool ok = i < count;
+      const int64_t m = ok ? start + i : start;
+      float4 xf;
+      double x[4];
+      unpack<DT>(raw[r], xf, x);
+      float om = ok ? 1.0f : 0.0f;
       if constexpr (WMODE == W_ARRAY) {
         const float wm = weights[m];
-        om = ok[r] ? wm : 0.0f;
+        om = ok ? wm : 0.0f;
       } else if constexpr (WMODE == W_IRLS) {
-        // r = x2~^T E x1~ in float64 from the stored coordinates
-        double x[4];
-        load_match_f64<DT>(uv, m, xs[r], x);
+        // r = x2~^T E x1~ in float64 from the stored coordinates; the
+        // keep/filter decision is taken on that value
         const double e0 = E[0] * x[0] + E[1] * x[1] + E[2];
         const double e1 = E[3] * x[0] + E[4] * x[1] + E[5];
         const double e2 = E[6] * x[0] + E[7] * x[1] + E[8];
         const double res = x[2] * e0 + x[3] * e1 + e2;
         const double a = fabs(res);
-        om = (ok[r] && a <= tau) ? (float)(1.0 / (a > delta ? a : delta)) : 0.0f;
+        const float af = fmaxf((float)a, fdelta);
+        om = (ok && a <= tau) ? __builtin_amdgcn_rcpf(af) : 0.0f;
         nkept += (om > 0.0f) ? 1u : 0u;
         if constexpr (WRITE) {
-          if (ok[r] && r_out) r_out[m] = (float)res;
+          if (ok && r_out) r_out[m] = (float)res;
         }
       }
       if constexpr (WRITE) {
-        if (ok[r]) w_out[m] = om;
+        if (ok) w_out[m] = om;
       }
-      oms[r] = om;
-    }
-    if constexpr (BUILD) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) accumulate36(acc, xs[r], oms[r]);
+      if constexpr (BUILD) accumulate36(acc, xf, om);
+      }
     }
   }
   if constexpr (BUILD) {
@@ -251,15 +257,15 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
   switch (s->dtype) {
     case FM_F32:
       hipLaunchKernelGGL((k_gram_partial<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->P, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
       break;
     case FM_BF16:
       hipLaunchKernelGGL((k_gram_partial<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->P, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
       break;
     default:
       hipLaunchKernelGGL((k_gram_partial<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->P, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
       break;
   }
   FM_CHECK_LAUNCH(s->ctx);

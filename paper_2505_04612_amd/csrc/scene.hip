@@ -172,6 +172,12 @@ __global__ __launch_bounds__(1024) void k_scan_inclusive(T* x, int64_t n) {
   for (int64_t k = lo; k < hi; ++k) x[k] += base;
 }
 
+__global__ void k_wi_fill(const int64_t* wi_off, int64_t P, int32_t* wi_pair) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < P)
+    for (int64_t w = wi_off[n]; w < wi_off[n + 1]; ++w) wi_pair[w] = (int32_t)n;
+}
+
 __global__ void k_cam_degree(const int32_t* cams, int64_t P, int32_t* cam_ptr) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < P) {
@@ -218,6 +224,7 @@ __global__ void k_slot_camera(const int32_t* cam_ptr, int32_t N, int32_t* cam_of
 static void scene_free(fm_scene* s) {
   if (!s) return;
   (void)hipFree(s->wi_off);
+  (void)hipFree(s->wi_pair);
   (void)hipFree(s->cam_ptr);
   (void)hipFree(s->cam_items);
   (void)hipFree(s->partials);
@@ -288,6 +295,12 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   hipLaunchKernelGGL(k_scan_inclusive<int64_t>, dim3(1), dim3(1024), 0, st, s->wi_off + 1, P);
   SCENE_TRY(hipGetLastError());
   SCENE_TRY(hipMemcpyAsync(&s->n_wi, s->wi_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SCENE_TRY(hipStreamSynchronize(st));
+  SCENE_TRY(hipMalloc(&s->wi_pair, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
+  if (P > 0) {
+    hipLaunchKernelGGL(k_wi_fill, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, s->wi_pair);
+    SCENE_TRY(hipGetLastError());
+  }
   // camera incidence lists
   SCENE_TRY(hipMalloc(&s->cam_ptr, sizeof(int32_t) * (N + 1)));
   SCENE_TRY(hipMalloc(&s->cam_items, sizeof(int32_t) * (2 * P + 1)));

@@ -403,16 +403,55 @@ def diffprec(seed: int = 2, nx: int = 20, ny: int = 50, height: float = 1.0,
                      {"trans": init_trans, "centre_sigma": init_sigma, "rot_deg": init_rot_deg})
 
 
+def _street_matches(args):
+    """Facade matches for a block of pairs of the street scene (worker)."""
+    (seed, chunk, ii, jj, k, R, t, c, horiz, line, street, heading, sigma, frac) = args
+    rng = np.random.default_rng([seed, 1, chunk])
+    ca = np.repeat(ii, k); cb = np.repeat(jj, k)
+    X = np.zeros((ca.size, 3))
+    todo = np.arange(ca.size)
+    for _ in range(40):
+        if todo.size == 0:
+            break
+        a, b = ca[todo], cb[todo]
+        # a random facade point ahead of the leading camera of the pair, on
+        # one of the two building faces lining the street
+        hz = horiz[a]
+        al_a = np.where(hz, c[a, 0], c[a, 1])
+        al_b = np.where(hz, c[b, 0], c[b, 1])
+        sg = heading[a]
+        front = np.where(sg > 0, np.maximum(al_a, al_b), np.minimum(al_a, al_b))
+        along_p = front + sg * rng.uniform(1.0, 40.0, todo.size)
+        side = line[a] + np.where(rng.random(todo.size) < 0.5, 0.5, -0.5) * street
+        hgt = rng.uniform(0.0, 8.0, todo.size)
+        P = np.stack([np.where(hz, along_p, side), np.where(hz, side, along_p), hgt], axis=1)
+        pa_, qa_, za = _project_px(R[a], t[a], P)
+        pb_, qb_, zb = _project_px(R[b], t[b], P)
+        ok = _in_frame(pa_, qa_, za) & _in_frame(pb_, qb_, zb)
+        X[todo[ok]] = P[ok]
+        todo = todo[~ok]
+    keep = np.ones(ca.size, dtype=bool)
+    keep[todo] = False
+    ca, cb, X = ca[keep], cb[keep], X[keep]
+    uv, outl = _make_matches(rng, R, t, ca, cb, X, sigma, frac)
+    counts = np.bincount(np.repeat(np.arange(ii.size), k)[keep], minlength=ii.size)
+    return uv.astype(np.float32), outl, counts
+
+
 def large(seed: int = 3, blocks: int = 12, block: float = 10.0, street: float = 2.0,
           n_cams: int = 5000, pairs_per_cam: int = 100, mean_matches: float = 800.0,
           sigma: float = 1.5, frac: float = 0.30, init_trans: str = "perturbed",
-          init_sigma: float = 0.03, init_rot_deg: float = 1.0, scale: float = 1.0) -> Scene:
-    """5,000 street-level cameras in a blocks x blocks city grid, heading along
-    their street with +-15 deg yaw jitter; matches are facade points (the two
+          init_sigma: float = 0.03, init_rot_deg: float = 1.0, scale: float = 1.0,
+          workers: int = 1, pairs_per_chunk: int = 2000) -> Scene:
+    """5,000 street-level cameras in a blocks x blocks city grid, all cameras
+    of a street heading the same way along it, with +-15 deg yaw jitter; matches are facade points (the two
     building faces lining the street) seen by two cameras on the same street.
     Each camera is paired with up to ~100 neighbours along its street, pair
-    sizes follow a power law with mean ~800 matches.  `scale` < 1 shrinks the
-    camera and match counts for quick runs."""
+    sizes follow a power law with mean ~800 matches (~250k pairs, ~200M
+    matches).  Matches are generated per block of pairs with a generator
+    seeded by (seed, block), so `workers` processes give the same scene; the
+    coordinates are kept as float32 (the workload stores them as bf16).
+    `scale` < 1 shrinks the camera count (and so pairs and matches)."""
     rng = np.random.default_rng(seed)
     n_cams = max(8, int(n_cams * scale))
     pitch = block + street
@@ -426,7 +465,8 @@ def large(seed: int = 3, blocks: int = 12, block: float = 10.0, street: float = 
     lateral = rng.uniform(-0.3, 0.3, n_cams) * street
     order = np.lexsort((along, st))
     st, horiz, line, along, lateral = st[order], horiz[order], line[order], along[order], lateral[order]
-    sign = np.where(rng.random(n_cams) < 0.5, 1.0, -1.0)
+    street_sign = np.where(rng.random(n_streets) < 0.5, 1.0, -1.0)   # one heading per street
+    sign = street_sign[st]
     cx = np.where(horiz, along, line + lateral)
     cy = np.where(horiz, line + lateral, along)
     cz = np.full(n_cams, 1.6) + rng.normal(0, 0.05, n_cams)
@@ -439,48 +479,47 @@ def large(seed: int = 3, blocks: int = 12, block: float = 10.0, street: float = 
     half = pairs_per_cam // 2
     ii, jj = [], []
     bounds = np.searchsorted(st, np.arange(n_streets + 1))
-    for s in range(n_streets):
-        lo, hi = bounds[s], bounds[s + 1]
+    for s_ in range(n_streets):
+        lo, hi = bounds[s_], bounds[s_ + 1]
         m = hi - lo
         if m < 2:
             continue
         for d in range(1, min(half, m - 1) + 1):
-            a = np.arange(lo, hi - d)
-            ii.append(a); jj.append(a + d)
+            a_ = np.arange(lo, hi - d)
+            ii.append(a_); jj.append(a_ + d)
     ii = np.concatenate(ii); jj = np.concatenate(jj)
+    o = np.lexsort((jj, ii))
+    ii, jj = ii[o], jj[o]
     k = _powerlaw_sizes(rng, ii.size, 20, 20_000, 1.45)
     k = np.maximum(20, np.round(k * (mean_matches / max(k.mean(), 1.0)))).astype(np.int64)
     k = np.minimum(k, 20_000)
-    ca = np.repeat(ii, k); cb = np.repeat(jj, k)
-    X = np.zeros((ca.size, 3))
-    todo = np.arange(ca.size)
-    for _ in range(60):
-        if todo.size == 0:
-            break
-        a, b = ca[todo], cb[todo]
-        # a random facade point: ray from camera a through a random pixel hits
-        # one of the two building faces lining the street
-        px = rng.uniform(0, WIDTH, todo.size); py = rng.uniform(0, HEIGHT, todo.size)
-        d_cam = np.stack([(px - CX) / FOCAL, (py - CY) / FOCAL, np.ones(todo.size)], 1)
-        d = np.einsum("nba,nb->na", R[a], d_cam)
-        hz = horiz[a]
-        lat = np.where(hz, d[:, 1], d[:, 0])
-        pos = np.where(hz, c[a, 1], c[a, 0])
-        face = np.where(lat > 0, line[a] + street / 2, line[a] - street / 2)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            s_ = (face - pos) / lat
-        P = c[a] + s_[:, None] * d
-        good = np.isfinite(s_) & (s_ > 0.2) & (s_ < 60.0) & (P[:, 2] > 0) & (P[:, 2] < 12.0)
-        pb_, qb_, zb = _project_px(R[b], t[b], P)
-        ok = good & _in_frame(pb_, qb_, zb)
-        X[todo[ok]] = P[ok]
-        todo = todo[~ok]
-    keep = np.ones(ca.size, dtype=bool)
-    keep[todo] = False
-    ca, cb, X = ca[keep], cb[keep], X[keep]
-    uv, outl = _make_matches(rng, R, t, ca, cb, X, sigma, frac)
-    return _assemble("large", seed, R, t, ca, cb, uv, outl, 30, "bf16", sigma, frac,
-                     {"trans": init_trans, "centre_sigma": init_sigma, "rot_deg": init_rot_deg})
+    jobs = []
+    for ch, lo in enumerate(range(0, ii.size, pairs_per_chunk)):
+        sl = slice(lo, lo + pairs_per_chunk)
+        jobs.append((seed, ch, ii[sl], jj[sl], k[sl], R, t, c, horiz, line, street, sign, sigma, frac))
+    if workers > 1:
+        import concurrent.futures
+        import multiprocessing
+        with concurrent.futures.ProcessPoolExecutor(
+                max_workers=workers, mp_context=multiprocessing.get_context("spawn")) as ex:
+            parts = list(ex.map(_street_matches, jobs))
+    else:
+        parts = [_street_matches(j) for j in jobs]
+    counts = np.concatenate([p[2] for p in parts])
+    uv = np.concatenate([p[0] for p in parts])
+    outl = np.concatenate([p[1] for p in parts])
+    del parts
+    keep_pair = counts >= 30
+    if not np.all(keep_pair):
+        sel = np.repeat(keep_pair, counts)
+        uv, outl = uv[sel], outl[sel]
+        ii, jj, counts = ii[keep_pair], jj[keep_pair], counts[keep_pair]
+    offsets = np.zeros(counts.size + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    R_init, t_init = _init_poses(R, t, seed, rot_deg=init_rot_deg, trans=init_trans,
+                                 centre_sigma=init_sigma)
+    return Scene("large", seed, R, t, R_init, t_init, np.stack([ii, jj], 1).astype(np.int32), offsets,
+                 uv, outl, "bf16", sigma, frac)
 
 
 RECIPES = {"tiny": tiny, "medium": medium, "diffprec": diffprec, "learned": learned,
