@@ -169,6 +169,8 @@ typedef struct {
   int64_t lr_step0;      /* global step index of this call's first iteration  */
   int64_t lr_total_steps;/* length of the whole schedule (> 0)                */
   int64_t adam_step0;    /* Adam steps already taken on m, v (0 after a reset) */
+  int32_t blocks;        /* workgroups of the persistent kernel (0 = automatic;
+                            capped at the co-resident limit)                  */
 } fm_adam_cfg;
 
 /* K iterations of {loss + gradient (as fm_epipolar_loss_grad), Adam update of

@@ -40,6 +40,7 @@ class AdamCfg(ctypes.Structure):
         ("lr_rot", ctypes.c_float), ("lr_t", ctypes.c_float), ("lr_final_frac", ctypes.c_float),
         ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
         ("lr_step0", ctypes.c_int64), ("lr_total_steps", ctypes.c_int64), ("adam_step0", ctypes.c_int64),
+        ("blocks", ctypes.c_int32),
     ]
 
 

@@ -255,7 +255,7 @@ def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: tor
                    K: int, lr_rot: float, lr_t: float, lr_final_frac: float, lr_step0: int, lr_total: int,
                    adam_step0: int = 0, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-12,
                    inv_Z: float | None = None, Z: torch.Tensor | None = None,
-                   loss_trace: torch.Tensor | None = None) -> None:
+                   loss_trace: torch.Tensor | None = None, blocks: int = 0) -> None:
     """K fused iterations (loss + adjoint + Adam) in one persistent kernel;
     params, m, v are updated in place; loss_trace [K] float64 optional."""
     dev = scene.ctx.device
@@ -268,7 +268,7 @@ def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: tor
         _require(Z, torch.int64, (1,), "Z", dev)
     elif inv_Z is None:
         raise ValueError("give inv_Z or Z")
-    cfg = _lib.AdamCfg(lr_rot, lr_t, lr_final_frac, beta1, beta2, eps, lr_step0, lr_total, adam_step0)
+    cfg = _lib.AdamCfg(lr_rot, lr_t, lr_final_frac, beta1, beta2, eps, lr_step0, lr_total, adam_step0, blocks)
     check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_solve(
         scene.ctx.handle, scene.handle, _ptr(W36), _wdtype(W36), _ptr(params), _ptr(m), _ptr(v), int(K),
         ctypes.byref(cfg), float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss_trace), _stream()))

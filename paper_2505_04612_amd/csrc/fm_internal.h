@@ -60,6 +60,7 @@ struct fm_scene {
   int64_t n_wi = 0;               // Gram work items
   int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
   int32_t* wi_pair = nullptr;     // [n_wi] pair of each work item
+  int32_t* wi_kept = nullptr;     // [n_wi] kept matches of each work item (IRLS passes)
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order
   // workspace
@@ -67,6 +68,7 @@ struct fm_scene {
   double* ess = nullptr;          // [P, 9] essential matrices (reweight)
   float* contrib = nullptr;       // [P, 24] per-pair gradient records
   double* loss_part = nullptr;    // [loss_part_cap]
+  double* rot = nullptr;          // [N, 9] rotations of the current poses (fused solve)
   int64_t loss_part_cap = 0;
   int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
 };

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int64_t* __restrict__ wi_off,
     const int32_t* __restrict__ wi_pair, int64_t n_wi, const float* __restrict__ weights,
     const double* __restrict__ ess, double delta, double tau, float* __restrict__ partials,
-    float* __restrict__ w_out, float* __restrict__ r_out, unsigned long long* __restrict__ kept) {
+    float* __restrict__ w_out, float* __restrict__ r_out, int32_t* __restrict__ wi_kept) {
   constexpr int kRows = kPerLane;                     // rows of 64 matches per work item
   constexpr int kBatch = (DT == FM_F64) ? 4 : kRows;  // rows loaded together
   const int lane = threadIdx.x & (kLanes - 1);
@@ -206,16 +206,43 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
     if (slot >= 0) partials[w * 36 + slot] = v;
   }
   if constexpr (WMODE == W_IRLS) {
-    // integer wave sum, one atomic per wavefront (exact, order-free)
+    // per-work-item count; the counts are summed by a later kernel (one
+    // atomic per wavefront on a single address would serialise the pass)
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) nkept += __shfl_xor(nkept, s);
-    if (lane == 0 && nkept) atomicAdd(kept, (unsigned long long)nkept);
+    if (lane == 0) wi_kept[w] = (int32_t)nkept;
   }
 }
 
-// Sum each pair's work-item partials in float64, in work-item order.
-__global__ void k_gram_finalize(const float* __restrict__ partials, const int64_t* __restrict__ wi_off,
-                                int64_t P, double* __restrict__ W64, float* __restrict__ W32) {
+// Deterministic sum of the per-work-item kept counts by one block.
+__device__ inline void sum_kept(const int32_t* __restrict__ wi_kept, int64_t n_wi, int64_t* __restrict__ kept) {
+  __shared__ long long part[kBlock / 64];
+  long long s = 0;
+  for (int64_t w = threadIdx.x; w < n_wi; w += blockDim.x) s += wi_kept[w];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
+    *kept = t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_kept(const int32_t* __restrict__ wi_kept, int64_t n_wi,
+                                                       int64_t* __restrict__ kept) {
+  sum_kept(wi_kept, n_wi, kept);
+}
+
+// Sum each pair's work-item partials in float64, in work-item order; block 0
+// also totals the kept counts of an IRLS pass (kept != NULL).
+__global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restrict__ partials,
+                                                          const int64_t* __restrict__ wi_off, int64_t P,
+                                                          double* __restrict__ W64, float* __restrict__ W32,
+                                                          const int32_t* __restrict__ wi_kept, int64_t n_wi,
+                                                          int64_t* __restrict__ kept) {
+  if (kept && blockIdx.x == 0) sum_kept(wi_kept, n_wi, kept);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P * 36) return;
   const int64_t n = t / 36;
@@ -226,12 +253,10 @@ __global__ void k_gram_finalize(const float* __restrict__ partials, const int64_
   if (W32) W32[t] = (float)s;
 }
 
-// E_n for every pair at the given poses (float64), for the residual pass;
-// thread 0 also clears the kept-match counter.
+// E_n for every pair at the given poses (float64), for the residual pass.
 __global__ void k_pair_essentials(const float* __restrict__ params, const int32_t* __restrict__ cams,
-                                  int64_t P, double* __restrict__ ess, unsigned long long* kept) {
+                                  int64_t P, double* __restrict__ ess) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n == 0 && kept) *kept = 0ull;
   if (n >= P) return;
   double a1[3], a2[3], ti[3], tj[3];
   double Ri[3][3], Rj[3][3], Rij[3][3], th[3], E[3][3];
@@ -250,47 +275,48 @@ __global__ void k_pair_essentials(const float* __restrict__ params, const int32_
 
 template <int WMODE, bool BUILD, bool WRITE>
 static fm_status launch_partial(fm_scene* s, const float* weights, double delta, double tau, float* w_out,
-                                float* r_out, unsigned long long* kept, hipStream_t st) {
+                                float* r_out, hipStream_t st) {
   if (s->n_wi == 0) return FM_OK;
   const dim3 grid(grid_for(s->n_wi, kGramWaves)), block(kGramWaves * kLanes);
   fm_timed timer(s->ctx, FM_K_GRAM, st);
   switch (s->dtype) {
     case FM_F32:
       hipLaunchKernelGGL((k_gram_partial<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->wi_kept);
       break;
     case FM_BF16:
       hipLaunchKernelGGL((k_gram_partial<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->wi_kept);
       break;
     default:
       hipLaunchKernelGGL((k_gram_partial<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->wi_kept);
       break;
   }
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
 
-static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, hipStream_t st) {
-  if (s->P == 0) return FM_OK;
+static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* kept, hipStream_t st) {
+  if (s->P == 0 && !kept) return FM_OK;
   fm_timed timer(s->ctx, FM_K_FINALIZE, st);
-  hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(s->P * 36, kBlock)), dim3(kBlock), 0, st, s->partials,
-                     s->wi_off, s->P, W64, W32);
+  const int64_t nthreads = s->P * 36 > 0 ? s->P * 36 : 1;
+  hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, s->partials,
+                     s->wi_off, s->P, W64, W32, s->wi_kept, s->n_wi, kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
 
-static fm_status launch_essentials(fm_scene* s, const float* params, unsigned long long* kept, hipStream_t st) {
+static fm_status launch_essentials(fm_scene* s, const float* params, hipStream_t st) {
   fm_timed timer(s->ctx, FM_K_ESSENTIALS, st);
   hipLaunchKernelGGL(k_pair_essentials, dim3(grid_for(s->P > 0 ? s->P : 1, kBlock)), dim3(kBlock), 0, st, params,
-                     s->pair_cams, s->P, s->ess, kept);
+                     s->pair_cams, s->P, s->ess);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
 
-fm_status fm_launch_essentials(fm_scene* s, const float* params, unsigned long long* kept, hipStream_t st) {
-  return launch_essentials(s, params, kept, st);
+fm_status fm_launch_essentials(fm_scene* s, const float* params, hipStream_t st) {
+  return launch_essentials(s, params, st);
 }
 
 static fm_status check_scene(fm_ctx* ctx, fm_scene* s, const char* fn) {
@@ -307,10 +333,10 @@ extern "C" fm_status fm_build_pair_grams(fm_ctx* ctx, fm_scene* s, const float* 
   if (rc != FM_OK) return rc;
   if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_build_pair_grams: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
-  rc = weights ? launch_partial<W_ARRAY, true, false>(s, weights, 0, 0, nullptr, nullptr, nullptr, st)
-               : launch_partial<W_UNIT, true, false>(s, nullptr, 0, 0, nullptr, nullptr, nullptr, st);
+  rc = weights ? launch_partial<W_ARRAY, true, false>(s, weights, 0, 0, nullptr, nullptr, st)
+               : launch_partial<W_UNIT, true, false>(s, nullptr, 0, 0, nullptr, nullptr, st);
   if (rc != FM_OK) return rc;
-  return launch_finalize(s, W64, W32, st);
+  return launch_finalize(s, W64, W32, nullptr, st);
 }
 
 static fm_status check_irls_args(fm_ctx* ctx, const char* fn, const float* params, float delta, float tau,
@@ -328,9 +354,11 @@ extern "C" fm_status fm_reweight(fm_ctx* ctx, fm_scene* s, const float* params, 
   if ((rc = check_irls_args(ctx, "fm_reweight", params, delta, tau, kept)) != FM_OK) return rc;
   if (!w_out && s->M > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight: weights_out is NULL");
   hipStream_t st = (hipStream_t)stream;
-  unsigned long long* k = reinterpret_cast<unsigned long long*>(kept);
-  if ((rc = launch_essentials(s, params, k, st)) != FM_OK) return rc;
-  return launch_partial<W_IRLS, false, true>(s, nullptr, delta, tau, w_out, r_out, k, st);
+  if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
+  if ((rc = launch_partial<W_IRLS, false, true>(s, nullptr, delta, tau, w_out, r_out, st)) != FM_OK) return rc;
+  hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(kBlock), 0, st, s->wi_kept, s->n_wi, kept);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
 }
 
 extern "C" fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* s, const float* params, float delta, float tau,
@@ -340,9 +368,8 @@ extern "C" fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* s, const float* pa
   if ((rc = check_irls_args(ctx, "fm_reweight_build", params, delta, tau, kept)) != FM_OK) return rc;
   if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight_build: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
-  unsigned long long* k = reinterpret_cast<unsigned long long*>(kept);
-  if ((rc = launch_essentials(s, params, k, st)) != FM_OK) return rc;
-  if ((rc = launch_partial<W_IRLS, true, false>(s, nullptr, delta, tau, nullptr, nullptr, k, st)) != FM_OK)
+  if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
+  if ((rc = launch_partial<W_IRLS, true, false>(s, nullptr, delta, tau, nullptr, nullptr, st)) != FM_OK)
     return rc;
-  return launch_finalize(s, W64, W32, st);
+  return launch_finalize(s, W64, W32, kept, st);
 }

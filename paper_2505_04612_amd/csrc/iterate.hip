@@ -27,17 +27,29 @@ __device__ inline double load_w(const WT* p, int k) {
 
 // Loss term and adjoint record of pair n.  rec = [dL/dR_i (3x3 row-major),
 // dL/dt_i, dL/dR_j, dL/dt_j] as float32.
+// `rot` (optional) holds each camera's rotation from Gram-Schmidt of the
+// current parameters, so pairs need not repeat it.
 template <typename WT>
-__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const int32_t* __restrict__ cams,
-                                           const WT* __restrict__ W36, int64_t n, double two_inv_Z,
-                                           float* __restrict__ rec) {
+__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot,
+                                           const int32_t* __restrict__ cams, const WT* __restrict__ W36,
+                                           int64_t n, double two_inv_Z, float* __restrict__ rec) {
   const int ci = cams[2 * n], cj = cams[2 * n + 1];
   double a1[3], a2[3], ti[3], tj[3];
   double Ri[3][3], Rj[3][3], Rij[3][3], th[3], E[3][3];
   load_pose(params, ci, a1, a2, ti);
-  gs_matrix(gs_forward(a1, a2), Ri);
   load_pose(params, cj, a1, a2, tj);
-  gs_matrix(gs_forward(a1, a2), Rj);
+  if (rot) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      Ri[k / 3][k % 3] = rot[(int64_t)ci * 9 + k];
+      Rj[k / 3][k % 3] = rot[(int64_t)cj * 9 + k];
+    }
+  } else {
+    load_pose(params, ci, a1, a2, ti);
+    gs_matrix(gs_forward(a1, a2), Ri);
+    load_pose(params, cj, a1, a2, tj);
+    gs_matrix(gs_forward(a1, a2), Rj);
+  }
   const double ns = pair_essential(Ri, ti, Rj, tj, Rij, th, E);
   // g = W e with W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)]
   const WT* Wn = W36 + n * 36;
@@ -108,12 +120,12 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
 // Pair phase over pairs [first, P) with stride `stride`; writes the records
 // and returns this thread's loss sum (float64, in pair order).
 template <typename WT>
-__device__ inline double pair_phase(const float* params, const int32_t* cams, const WT* W36, int64_t P,
-                                    double two_inv_Z, float* contrib, int64_t first, int64_t stride) {
+__device__ inline double pair_phase(const float* params, const double* rot, const int32_t* cams, const WT* W36,
+                                    int64_t P, double two_inv_Z, float* contrib, int64_t first, int64_t stride) {
   double sum = 0.0;
   for (int64_t n = first; n < P; n += stride) {
     float rec[24];
-    sum += pair_loss_adjoint(params, cams, W36, n, two_inv_Z, rec);
+    sum += pair_loss_adjoint(params, rot, cams, W36, n, two_inv_Z, rec);
     float4* dst = reinterpret_cast<float4*>(contrib + n * 24);
 #pragma unroll
     for (int k = 0; k < 6; ++k) dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
@@ -204,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_phase(const float* __restrict__
   __shared__ double lds[kBlock / 64];
   const double iz = Z_dev ? 1.0 / (double)(*Z_dev > 0 ? *Z_dev : 1) : inv_Z;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double v = pair_phase(params, cams, W36, P, 2.0 * iz, contrib, n, P > 0 ? P : 1);
+  const double v = pair_phase(params, (const double*)nullptr, cams, W36, P, 2.0 * iz, contrib, n, P > 0 ? P : 1);
   const double t = block_sum(v, lds);
   if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
 }
@@ -325,6 +337,7 @@ struct SolveArgs {
   const int32_t* cam_items;
   float* contrib;
   double* loss_part;
+  double* rot;
   double* loss_trace;
   const int64_t* Z_dev;
   double inv_Z;
@@ -347,7 +360,10 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
   const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
   const WT* W36 = reinterpret_cast<const WT*>(a.W36);
   for (int k = 0; k < a.K; ++k) {
-    const double v = pair_phase(a.params, a.cams, W36, a.P, 2.0 * iz, a.contrib, gtid, gsize);
+    // iteration 0 runs Gram-Schmidt per pair; later iterations read the
+    // rotations the camera phase stored with the updated parameters
+    const double v = pair_phase(a.params, k > 0 ? a.rot : nullptr, a.cams, W36, a.P, 2.0 * iz, a.contrib, gtid,
+                                gsize);
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
     grid.sync();
@@ -374,6 +390,11 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
           m[q] = mq;
           vv[q] = vq;
         }
+        double n1[3], n2[3], nt[3], R[3][3];
+        load_pose(a.params, (int)c, n1, n2, nt);
+        gs_matrix(gs_forward(n1, n2), R);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) a.rot[c * 9 + q] = R[q / 3][q % 3];
       }
     }
     grid.sync();
@@ -411,12 +432,13 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   const int64_t want_c = grid_for((int64_t)s->N * 64, kBlock);
   if (want_c > want) want = want_c;
   if (want < 1) want = 1;
+  if (cfg->blocks > 0) want = cfg->blocks;
   if (want > s->coop_blocks) want = s->coop_blocks;
   if (want > s->loss_part_cap) return fm_fail(ctx, FM_ECOOP, "fm_epipolar_solve: loss workspace too small");
   SolveArgs a;
   a.params = params; a.m = m; a.v = v;
   a.cams = s->pair_cams; a.W36 = W36; a.cam_ptr = s->cam_ptr; a.cam_items = s->cam_items;
-  a.contrib = s->contrib; a.loss_part = s->loss_part; a.loss_trace = loss_trace; a.Z_dev = Z_dev;
+  a.contrib = s->contrib; a.loss_part = s->loss_part; a.rot = s->rot; a.loss_trace = loss_trace; a.Z_dev = Z_dev;
   a.inv_Z = inv_Z; a.P = s->P; a.N = s->N; a.K = K;
   a.lr_rot = cfg->lr_rot; a.lr_t = cfg->lr_t; a.log_frac = log((double)cfg->lr_final_frac);
   a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;

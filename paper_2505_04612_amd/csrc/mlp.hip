@@ -400,7 +400,7 @@ extern "C" fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats,
   return FM_OK;
 }
 
-fm_status fm_launch_essentials(fm_scene* s, const float* params, unsigned long long* kept, hipStream_t st);
+fm_status fm_launch_essentials(fm_scene* s, const float* params, hipStream_t st);
 
 extern "C" fm_status fm_match_features(fm_ctx* ctx, fm_scene* s, const float* params, float delta, float* feats,
                                        fm_stream stream) {
@@ -410,7 +410,7 @@ extern "C" fm_status fm_match_features(fm_ctx* ctx, fm_scene* s, const float* pa
   if (!(delta > 0.0f)) return fm_fail(ctx, FM_EINVAL, "fm_match_features: delta must be > 0");
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  fm_status rc = fm_launch_essentials(s, params, nullptr, st);
+  fm_status rc = fm_launch_essentials(s, params, st);
   if (rc != FM_OK || s->n_wi == 0) return rc;
   const dim3 grid(grid_for(s->n_wi, 4)), block(256);
   switch (s->dtype) {

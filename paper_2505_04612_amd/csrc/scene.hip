@@ -225,12 +225,14 @@ static void scene_free(fm_scene* s) {
   if (!s) return;
   (void)hipFree(s->wi_off);
   (void)hipFree(s->wi_pair);
+  (void)hipFree(s->wi_kept);
   (void)hipFree(s->cam_ptr);
   (void)hipFree(s->cam_items);
   (void)hipFree(s->partials);
   (void)hipFree(s->ess);
   (void)hipFree(s->contrib);
   (void)hipFree(s->loss_part);
+  (void)hipFree(s->rot);
   delete s;
 }
 
@@ -297,6 +299,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMemcpyAsync(&s->n_wi, s->wi_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SCENE_TRY(hipStreamSynchronize(st));
   SCENE_TRY(hipMalloc(&s->wi_pair, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
+  SCENE_TRY(hipMalloc(&s->wi_kept, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
   if (P > 0) {
     hipLaunchKernelGGL(k_wi_fill, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, s->wi_pair);
     SCENE_TRY(hipGetLastError());
@@ -341,6 +344,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
+  SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * (N > 0 ? N : 1)));
   *out = s;
   return FM_OK;
 }

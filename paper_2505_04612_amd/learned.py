@@ -140,10 +140,13 @@ def learned_solve(scene: api.Scene, params0: torch.Tensor, w: api.MlpWeights, ls
     v = torch.zeros_like(p)
     api.epipolar_solve(scene, W64, p, m, v, ls.iters, ls.lr_rot, ls.lr_t, ls.lr_final_frac, 0, ls.iters,
                        inv_Z=1.0 / max(scene.num_matches, 1))
-    # one plain IRLS loop from the learned solution decides the fallback
+    # one plain IRLS loop from the learned solution decides the fallback; its
+    # learning rate starts at the geometric middle of the plain schedule's
+    # range, so a solution away from the IRLS optimum does move
     tau = solver.tau_at(fallback, max(fallback.iters // fallback.round_len - 1, 0))
-    chk = dataclasses.replace(fallback, iters=fallback.round_len, tau0=tau, lr_rot=ls.lr_rot * ls.lr_final_frac,
-                              lr_t=ls.lr_t * ls.lr_final_frac)
+    half = math.sqrt(fallback.lr_final_frac)
+    chk = dataclasses.replace(fallback, iters=fallback.round_len, tau0=tau, lr_rot=fallback.lr_rot * half,
+                              lr_t=fallback.lr_t * half, lr_final_frac=half)
     p_chk, _, _ = solver.solve(scene, p, chk, trace=False)
     d_rot, d_t = _relative_pose_change(p.cpu().numpy(), p_chk.cpu().numpy(), scene.pairs.cpu().numpy())
     info = {"check_rot_deg": d_rot, "check_t_deg": d_t, "fallback": False}

@@ -257,3 +257,52 @@ def test_full_solve_pose_parity(fm, ctx, name, dtype, iters):
     rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), th_o, sc.pairs)
     assert rot.max() <= 0.1 and tra.max() <= 0.5, (rot.max(), tra.max())
     assert int(Z.item()) == int(np.count_nonzero(w_o)) or abs(int(Z.item()) - int(np.count_nonzero(w_o))) <= 2
+
+
+# ------------------------------------------------------------------ precision form at larger sizes
+
+def test_gram_diffprec_bf16_full(fm, ctx):
+    """The diffprec workload (~34k pairs, ~25M BF16 matches, pair sizes 20..20k)
+    in full: unit-weight and IRLS-weighted Grams against the oracle on the same
+    stored BF16 values."""
+    sc = scene("diffprec")
+    s = _scene_on_gpu(fm, ctx, sc, torch.bfloat16)
+    x = stored(sc.uv, torch.bfloat16)
+    W64, _ = fm.build_pair_grams(s, f32=False)
+    ref = ea.pair_grams(x, sc.offsets)
+    absg = ea.pair_grams(np.abs(x), sc.offsets)
+    rel, el = gram_errors(expand36(W64.cpu().numpy()), ref, absg)
+    assert rel <= 1e-5 and el <= 1e-5, (rel, el)
+    th = _theta(sc)
+    delta, tau = f32(1e-4), f32(0.1)
+    W64w, _, kept = fm.reweight_build(s, torch.from_numpy(th).to(ctx.device), delta, tau, f32=False)
+    w_ref = ea.irls_weights(ea.residuals(th.astype(np.float64), sc.pairs, sc.offsets, x), delta, tau)
+    assert abs(int(kept.item()) - int(np.count_nonzero(w_ref))) <= 2
+    ref = ea.pair_grams(x, sc.offsets, w_ref)
+    absg = ea.pair_grams(np.abs(x), sc.offsets, w_ref)
+    rel, el = gram_errors(expand36(W64w.cpu().numpy()), ref, absg)
+    assert rel <= 1e-5 and el <= 1e-5, (rel, el)
+
+
+def test_gram_large_street_sampled(fm, ctx):
+    """The street workload at 1/5 of its camera count (1,000 cameras, ~15M BF16
+    matches): Grams of 64 sampled pairs, each computed by the oracle alone."""
+    from paper_2505_04612_amd import synth
+    sc = synth.large(scale=0.2, workers=4)
+    uv = torch.from_numpy(sc.uv).to(ctx.device).to(torch.bfloat16).contiguous()
+    s = fm.Scene(ctx, sc.num_cams, torch.from_numpy(sc.pairs).to(ctx.device),
+                 torch.from_numpy(sc.offsets).to(ctx.device), uv)
+    th = _theta(sc)
+    delta, tau = f32(1e-4), f32(0.1)
+    W64, _, kept = fm.reweight_build(s, torch.from_numpy(th).to(ctx.device), delta, tau, f32=False)
+    W = W64.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for n in rng.choice(sc.num_pairs, size=64, replace=False):
+        lo, hi = int(sc.offsets[n]), int(sc.offsets[n + 1])
+        x = uv[lo:hi].to(torch.float32).cpu().numpy().astype(np.float64)
+        off = np.array([0, hi - lo])
+        w = ea.irls_weights(ea.residuals(th.astype(np.float64), sc.pairs[n:n + 1], off, x), delta, tau)
+        ref = ea.pair_grams(x, off, w)
+        absg = ea.pair_grams(np.abs(x), off, w)
+        rel, el = gram_errors(expand36(W[n:n + 1]), ref, absg)
+        assert rel <= 1e-5 and el <= 1e-5, (n, rel, el)
