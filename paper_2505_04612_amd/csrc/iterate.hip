@@ -147,8 +147,39 @@ __device__ inline double block_sum(double v, double* lds) {
   return t;
 }
 
-// Gradient of camera c (executed by a whole wavefront; result valid in lane 0).
-// Returns dL/dtheta_c [9] in float64 in lane 0.
+template <int CTRL>
+__device__ inline double dpp_mov_d(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Reduce-scatter stage over lane bit BIT (see the Gram pass for the partner
+// rules): keep the lower or upper half of S values and add the partner's.
+template <int S, int BIT>
+__device__ inline void rs_stage_d(const double (&in)[S], double (&out)[(S + 1) / 2], int lane) {
+  constexpr int H = (S + 1) / 2;
+  const bool up = (lane >> BIT) & 1;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const double lo = in[k];
+    const double hi = (k + H < S) ? in[k + H] : 0.0;
+    const double send = up ? lo : hi;
+    double recv;
+    if constexpr (BIT == 3) recv = dpp_mov_d<0x140>(send);        // row_mirror
+    else if constexpr (BIT == 2) recv = dpp_mov_d<0x141>(send);   // row_half_mirror
+    else if constexpr (BIT == 1) recv = dpp_mov_d<0x4E>(send);    // quad_perm xor 2
+    else recv = dpp_mov_d<0xB1>(send);                            // quad_perm xor 1
+    out[k] = (up ? hi : lo) + recv;
+  }
+}
+
+// Gradient of camera c, computed by a whole wavefront; every lane returns
+// dL/dtheta_c [9] (float64).  Lanes stride the camera's incidence list (pair
+// order), then the 12 sums (dL/dR 3x3, dL/dt) are reduce-scattered over lane
+// bits 3..0 (12 -> 6 -> 3 -> 2 -> 1, DPP), added across the four rows, and
+// gathered back to every lane.
 __device__ inline void camera_gradient(const float* __restrict__ params, const int32_t* __restrict__ cam_ptr,
                                        const int32_t* __restrict__ cam_items, const float* __restrict__ contrib,
                                        int c, int lane, double grad[9]) {
@@ -164,10 +195,17 @@ __device__ inline void camera_gradient(const float* __restrict__ params, const i
     acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
     acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
   }
+  double b6[6], b3[3], b2[2], b1[1];
+  rs_stage_d<12, 3>(acc, b6, lane);
+  rs_stage_d<6, 2>(b6, b3, lane);
+  rs_stage_d<3, 1>(b3, b2, lane);
+  rs_stage_d<2, 0>(b2, b1, lane);
+  double v = b1[0];
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  // entry s now sits in lane s + s / 3 of every row
 #pragma unroll
-  for (int s = 32; s >= 1; s >>= 1)
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] += __shfl_xor(acc[k], s);
+  for (int k = 0; k < 12; ++k) acc[k] = __shfl(v, k + k / 3);
   // Gram-Schmidt adjoint (float64).  Columns of dL/dR: g1, g2, g3.
   double a1[3], a2[3], t[3];
   load_pose(params, c, a1, a2, t);
@@ -206,6 +244,14 @@ __device__ inline void camera_gradient(const float* __restrict__ params, const i
   }
 }
 
+// The element q of a per-lane array held identically by all lanes.
+__device__ inline double pick9(const double g[9], int q) {
+  double v = g[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) v = (q == k) ? g[k] : v;
+  return v;
+}
+
 // ------------------------------------------------------------------ standalone loss + gradient
 
 template <typename WT>
@@ -239,12 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_camera_grad(const float* __restrict_
   if (c >= N || !grad) return;
   double g[9];
   camera_gradient(params, cam_ptr, cam_items, contrib, (int)c, lane, g);
-  if (lane < 9) {
-    double v = g[0];
-#pragma unroll
-    for (int k = 1; k < 9; ++k) v = (lane == k) ? g[k] : v;
-    grad[c * 9 + lane] = (float)v;
-  }
+  if (lane < 9) grad[c * 9 + lane] = (float)pick9(g, lane);
 }
 
 static fm_status check_w(fm_ctx* ctx, const char* fn, const void* W36, fm_dtype wdt, int64_t P) {
@@ -378,23 +419,29 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
     for (int64_t c = gwave; c < a.N; c += nwaves) {
       double g[9];
       camera_gradient(a.params, a.cam_ptr, a.cam_items, a.contrib, (int)c, lane, g);
-      if (lane == 0) {
-        float* p = a.params + c * 9;
-        float* m = a.m + c * 9;
-        float* vv = a.v + c * 9;
+      // lanes 0..8 update one parameter each
+      float pq = 0.0f;
+      if (lane < 9) {
+        const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
+        float mq = a.m[c * 9 + lane], vq = a.v[c * 9 + lane];
+        pq = adam_update(a.params[c * 9 + lane], (float)pick9(g, lane), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+        a.params[c * 9 + lane] = pq;
+        a.m[c * 9 + lane] = mq;
+        a.v[c * 9 + lane] = vq;
+      }
+      // rotation of the updated parameters for the next pair phase
+      double n1[3], n2[3], R[3][3];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const double lr = (q < 6 ? a.lr_rot : a.lr_t) * frac;
-          float mq = m[q], vq = vv[q];
-          p[q] = adam_update(p[q], (float)g[q], mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
-          m[q] = mq;
-          vv[q] = vq;
-        }
-        double n1[3], n2[3], nt[3], R[3][3];
-        load_pose(a.params, (int)c, n1, n2, nt);
-        gs_matrix(gs_forward(n1, n2), R);
+      for (int j = 0; j < 3; ++j) {
+        n1[j] = (double)__shfl(pq, j);
+        n2[j] = (double)__shfl(pq, 3 + j);
+      }
+      gs_matrix(gs_forward(n1, n2), R);
+      if (lane < 9) {
+        double rv = R[0][0];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) a.rot[c * 9 + q] = R[q / 3][q % 3];
+        for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
+        a.rot[c * 9 + lane] = rv;
       }
     }
     grid.sync();

@@ -11,8 +11,9 @@ kernels and its Adam kernel.
 
 Fallback: after the learned solve, one plain IRLS loop is run from its
 result; if that loop moves any pair's relative rotation by more than 0.1 deg
-or its translation direction by more than 0.5 deg, plain IRLS continues for
-the full schedule from there, so plain IRLS stays the judge of pose accuracy.
+or its translation direction by more than 0.5 deg, the full plain IRLS
+schedule is run from the initial poses instead, so plain IRLS stays the
+judge of pose accuracy.
 
     python -m paper_2505_04612_amd.learned --train 64 --test 16 --out results.json
 """
@@ -151,8 +152,10 @@ def learned_solve(scene: api.Scene, params0: torch.Tensor, w: api.MlpWeights, ls
     d_rot, d_t = _relative_pose_change(p.cpu().numpy(), p_chk.cpu().numpy(), scene.pairs.cpu().numpy())
     info = {"check_rot_deg": d_rot, "check_t_deg": d_t, "fallback": False}
     if d_rot > ls.check_rot_deg or d_t > ls.check_t_deg:
+        # the learned weights missed the IRLS optimum: plain IRLS from the
+        # initial poses decides the result
         info["fallback"] = True
-        p_chk, _, _ = solver.solve(scene, p_chk, fallback, trace=False)
+        p_chk, _, _ = solver.solve(scene, params0, fallback, trace=False)
     return p_chk, info
 
 
