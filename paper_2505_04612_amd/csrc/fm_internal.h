@@ -17,6 +17,9 @@ constexpr int kChunk = kLanes * kPerLane;
 constexpr int kGramWaves = 4;
 // Threads per block of the per-pair and per-camera kernels.
 constexpr int kBlock = 256;
+// Integer counters the IRLS pass spreads its kept-match counts over (one
+// 128-byte line each, so concurrent atomics rarely meet on one address).
+constexpr int kKeptSlots = 256;
 
 // Kernel identifiers of the optional launch timing (fm_profile_*).
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
@@ -60,7 +63,7 @@ struct fm_scene {
   int64_t n_wi = 0;               // Gram work items
   int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
   int32_t* wi_pair = nullptr;     // [n_wi] pair of each work item
-  int32_t* wi_kept = nullptr;     // [n_wi] kept matches of each work item (IRLS passes)
+  unsigned long long* kept_slots = nullptr;  // [kKeptSlots * 16] kept-match counters, one per 128-B line
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order
   // workspace

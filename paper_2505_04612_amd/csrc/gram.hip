@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int64_t* __restrict__ wi_off,
     const int32_t* __restrict__ wi_pair, int64_t n_wi, const float* __restrict__ weights,
     const double* __restrict__ ess, double delta, double tau, float* __restrict__ partials,
-    float* __restrict__ w_out, float* __restrict__ r_out, int32_t* __restrict__ wi_kept) {
+    float* __restrict__ w_out, float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
   constexpr int kRows = kPerLane;                     // rows of 64 matches per work item
   constexpr int kBatch = (DT == FM_F64) ? 4 : kRows;  // rows loaded together
   const int lane = threadIdx.x & (kLanes - 1);
@@ -206,33 +206,37 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
     if (slot >= 0) partials[w * 36 + slot] = v;
   }
   if constexpr (WMODE == W_IRLS) {
-    // per-work-item count; the counts are summed by a later kernel (one
-    // atomic per wavefront on a single address would serialise the pass)
+    // integer count, spread over kKeptSlots counters (a single address would
+    // serialise one atomic per wavefront); exact and order-free
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) nkept += __shfl_xor(nkept, s);
-    if (lane == 0) wi_kept[w] = (int32_t)nkept;
+    if (lane == 0 && nkept) atomicAdd(&kept_slots[(w % kKeptSlots) * 16], (unsigned long long)nkept);
   }
 }
 
-// Deterministic sum of the per-work-item kept counts by one block.
-__device__ inline void sum_kept(const int32_t* __restrict__ wi_kept, int64_t n_wi, int64_t* __restrict__ kept) {
-  __shared__ long long part[kBlock / 64];
-  long long s = 0;
-  for (int64_t w = threadIdx.x; w < n_wi; w += blockDim.x) s += wi_kept[w];
+// Total of the kept-match counters by one block of kKeptSlots threads; the
+// counters are cleared for the next pass.
+__device__ inline void sum_kept(unsigned long long* __restrict__ kept_slots, int64_t* __restrict__ kept) {
+  __shared__ unsigned long long part[kKeptSlots / 64];
+  unsigned long long s = 0;
+  if (threadIdx.x < kKeptSlots) {
+    s = kept_slots[threadIdx.x * 16];
+    kept_slots[threadIdx.x * 16] = 0ull;
+  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  if ((threadIdx.x & 63) == 0 && threadIdx.x < kKeptSlots) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long t = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += part[k];
-    *kept = t;
+    unsigned long long t = 0;
+    for (int k = 0; k < kKeptSlots / 64; ++k) t += part[k];
+    *kept = (int64_t)t;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_kept(const int32_t* __restrict__ wi_kept, int64_t n_wi,
+__global__ __launch_bounds__(kBlock) void k_count_kept(unsigned long long* __restrict__ kept_slots,
                                                        int64_t* __restrict__ kept) {
-  sum_kept(wi_kept, n_wi, kept);
+  sum_kept(kept_slots, kept);
 }
 
 // Sum each pair's work-item partials in float64, in work-item order; block 0
@@ -240,9 +244,9 @@ __global__ __launch_bounds__(kBlock) void k_count_kept(const int32_t* __restrict
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restrict__ partials,
                                                           const int64_t* __restrict__ wi_off, int64_t P,
                                                           double* __restrict__ W64, float* __restrict__ W32,
-                                                          const int32_t* __restrict__ wi_kept, int64_t n_wi,
+                                                          unsigned long long* __restrict__ kept_slots,
                                                           int64_t* __restrict__ kept) {
-  if (kept && blockIdx.x == 0) sum_kept(wi_kept, n_wi, kept);
+  if (kept && blockIdx.x == 0) sum_kept(kept_slots, kept);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= P * 36) return;
   const int64_t n = t / 36;
@@ -282,15 +286,15 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
   switch (s->dtype) {
     case FM_F32:
       hipLaunchKernelGGL((k_gram_partial<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->wi_kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->kept_slots);
       break;
     case FM_BF16:
       hipLaunchKernelGGL((k_gram_partial<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->wi_kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->kept_slots);
       break;
     default:
       hipLaunchKernelGGL((k_gram_partial<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->wi_kept);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->kept_slots);
       break;
   }
   FM_CHECK_LAUNCH(s->ctx);
@@ -302,7 +306,7 @@ static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* 
   fm_timed timer(s->ctx, FM_K_FINALIZE, st);
   const int64_t nthreads = s->P * 36 > 0 ? s->P * 36 : 1;
   hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, s->partials,
-                     s->wi_off, s->P, W64, W32, s->wi_kept, s->n_wi, kept);
+                     s->wi_off, s->P, W64, W32, s->kept_slots, kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
@@ -356,7 +360,7 @@ extern "C" fm_status fm_reweight(fm_ctx* ctx, fm_scene* s, const float* params, 
   hipStream_t st = (hipStream_t)stream;
   if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
   if ((rc = launch_partial<W_IRLS, false, true>(s, nullptr, delta, tau, w_out, r_out, st)) != FM_OK) return rc;
-  hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(kBlock), 0, st, s->wi_kept, s->n_wi, kept);
+  hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(kBlock), 0, st, s->kept_slots, kept);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
 }

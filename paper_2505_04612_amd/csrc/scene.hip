@@ -225,7 +225,7 @@ static void scene_free(fm_scene* s) {
   if (!s) return;
   (void)hipFree(s->wi_off);
   (void)hipFree(s->wi_pair);
-  (void)hipFree(s->wi_kept);
+  (void)hipFree(s->kept_slots);
   (void)hipFree(s->cam_ptr);
   (void)hipFree(s->cam_items);
   (void)hipFree(s->partials);
@@ -299,7 +299,8 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMemcpyAsync(&s->n_wi, s->wi_off + P, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SCENE_TRY(hipStreamSynchronize(st));
   SCENE_TRY(hipMalloc(&s->wi_pair, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
-  SCENE_TRY(hipMalloc(&s->wi_kept, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
+  SCENE_TRY(hipMalloc(&s->kept_slots, sizeof(unsigned long long) * 16 * kKeptSlots));
+  SCENE_TRY(hipMemsetAsync(s->kept_slots, 0, sizeof(unsigned long long) * 16 * kKeptSlots, st));
   if (P > 0) {
     hipLaunchKernelGGL(k_wi_fill, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, s->wi_pair);
     SCENE_TRY(hipGetLastError());

@@ -256,7 +256,9 @@ def test_full_solve_pose_parity(fm, ctx, name, dtype, iters):
                                _oracle_sched(sched))
     rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), th_o, sc.pairs)
     assert rot.max() <= 0.1 and tra.max() <= 0.5, (rot.max(), tra.max())
-    assert int(Z.item()) == int(np.count_nonzero(w_o)) or abs(int(Z.item()) - int(np.count_nonzero(w_o))) <= 2
+    # the last reweighting runs at poses that agree to the bar above, so only
+    # matches whose residual sits within that perturbation of tau may flip
+    assert abs(int(Z.item()) - int(np.count_nonzero(w_o))) <= max(2, int(1e-5 * sc.num_matches))
 
 
 # ------------------------------------------------------------------ precision form at larger sizes
