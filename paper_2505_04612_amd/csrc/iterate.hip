@@ -51,25 +51,32 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
     gs_matrix(gs_forward(a1, a2), Rj);
   }
   const double ns = pair_essential(Ri, ti, Rj, tj, Rij, th, E);
-  // g = W e with W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)]
+  // g = W e with W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)]: walk the index
+  // pairs (a, c) and read only the 6-entry row q(a,c) of the compact Gram
+  // for each, so few Gram values are live at once
   const WT* Wn = W36 + n * 36;
-  double Wl[36];
-#pragma unroll
-  for (int k = 0; k < 36; ++k) Wl[k] = load_w(Wn, k);
   double g[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) g[a][b] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double row[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) row[k] = load_w(Wn, 6 * mono_q(a, c) + k);
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[a][b] = fma(row[mono_q(b, d)], E[c][d], g[a][b]);
+    }
   double loss = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) acc += Wl[6 * mono_q(a, c) + mono_q(b, d)] * E[c][d];
-      g[a][b] = acc;
-      loss += E[a][b] * acc;
-    }
+    for (int b = 0; b < 3; ++b) loss = fma(E[a][b], g[a][b], loss);
   if (!(ns > 0.0)) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) rec[k] = 0.0f;
@@ -175,28 +182,20 @@ __device__ inline void rs_stage_d(const double (&in)[S], double (&out)[(S + 1) /
   }
 }
 
-// Gradient of camera c, computed by a whole wavefront; every lane returns
-// dL/dtheta_c [9] (float64).  Lanes stride the camera's incidence list (pair
-// order), then the 12 sums (dL/dR 3x3, dL/dt) are reduce-scattered over lane
-// bits 3..0 (12 -> 6 -> 3 -> 2 -> 1, DPP), added across the four rows, and
-// gathered back to every lane.
-__device__ inline void camera_gradient(const float* __restrict__ params, const int32_t* __restrict__ cam_ptr,
-                                       const int32_t* __restrict__ cam_items, const float* __restrict__ contrib,
-                                       int c, int lane, double grad[9]) {
-  double acc[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-  const int lo = cam_ptr[c], hi = cam_ptr[c + 1];
-  for (int q = lo + lane; q < hi; q += 64) {
-    const int item = cam_items[q];
-    const float4* src = reinterpret_cast<const float4*>(contrib + (int64_t)(item >> 1) * 24 + (item & 1) * 12);
-    const float4 r0 = src[0], r1 = src[1], r2 = src[2];
-    acc[0] += r0.x; acc[1] += r0.y; acc[2] += r0.z; acc[3] += r0.w;
-    acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
-    acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
-  }
+__device__ inline void add_record(const float* __restrict__ contrib, int item, double acc[12]) {
+  const float4* src = reinterpret_cast<const float4*>(contrib + (int64_t)(item >> 1) * 24 + (item & 1) * 12);
+  const float4 r0 = src[0], r1 = src[1], r2 = src[2];
+  acc[0] += r0.x; acc[1] += r0.y; acc[2] += r0.z; acc[3] += r0.w;
+  acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
+  acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
+}
+
+// Wave-wide total of the 12 per-lane sums (dL/dR 3x3, dL/dt), returned in
+// every lane: reduce-scatter over lane bits 3..0 (12 -> 6 -> 3 -> 2 -> 1,
+// DPP), add across the four rows, gather back.  Fixed order: deterministic.
+__device__ inline void wave_sum12(double acc[12], int lane) {
   double b6[6], b3[3], b2[2], b1[1];
-  rs_stage_d<12, 3>(acc, b6, lane);
+  rs_stage_d<12, 3>(*reinterpret_cast<double(*)[12]>(acc), b6, lane);
   rs_stage_d<6, 2>(b6, b3, lane);
   rs_stage_d<3, 1>(b3, b2, lane);
   rs_stage_d<2, 0>(b2, b1, lane);
@@ -206,9 +205,11 @@ __device__ inline void camera_gradient(const float* __restrict__ params, const i
   // entry s now sits in lane s + s / 3 of every row
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = __shfl(v, k + k / 3);
-  // Gram-Schmidt adjoint (float64).  Columns of dL/dR: g1, g2, g3.
-  double a1[3], a2[3], t[3];
-  load_pose(params, c, a1, a2, t);
+}
+
+// dL/dtheta [9] of one camera from its summed dL/dR (columns g1, g2, g3 in
+// acc[3r + col]) and dL/dt (acc[9..11]): the Gram-Schmidt adjoint in float64.
+__device__ inline void gs_adjoint(const double acc[12], const double a1[3], const double a2[3], double grad[9]) {
   const Gs f = gs_forward(a1, a2);
   double g1[3], g2[3], g3[3];
 #pragma unroll
@@ -242,6 +243,23 @@ __device__ inline void camera_gradient(const float* __restrict__ params, const i
     grad[k] = (g1[k] - b1g1 * f.b1[k]) / f.n1;
     grad[6 + k] = acc[9 + k];
   }
+}
+
+// Gradient of camera c, computed by a whole wavefront; every lane returns
+// dL/dtheta_c [9] (float64).  Lanes stride the camera's incidence list (pair
+// order) and the 12 sums are combined by wave_sum12.
+__device__ inline void camera_gradient(const float* __restrict__ params, const int32_t* __restrict__ cam_ptr,
+                                       const int32_t* __restrict__ cam_items, const float* __restrict__ contrib,
+                                       int c, int lane, double grad[9]) {
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  const int lo = cam_ptr[c], hi = cam_ptr[c + 1];
+  for (int q = lo + lane; q < hi; q += 64) add_record(contrib, cam_items[q], acc);
+  wave_sum12(acc, lane);
+  double a1[3], a2[3], t[3];
+  load_pose(params, c, a1, a2, t);
+  gs_adjoint(acc, a1, a2, grad);
 }
 
 // The element q of a per-lane array held identically by all lanes.
@@ -475,11 +493,16 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
   // enough threads for one pair each or one wavefront per camera, within the
   // co-resident limit of a cooperative launch
+  // about one pair per thread or one wavefront per camera, capped at 32
+  // workgroups below 32k pairs (measured: more workgroups make the two grid
+  // barriers per iteration dearer than the work they share) and at the
+  // co-resident limit
   int64_t want = grid_for(s->P, kBlock);
   const int64_t want_c = grid_for((int64_t)s->N * 64, kBlock);
   if (want_c > want) want = want_c;
-  if (want < 1) want = 1;
+  if (s->P < 32768 && want > 32) want = 32;
   if (cfg->blocks > 0) want = cfg->blocks;
+  if (want < 1) want = 1;
   if (want > s->coop_blocks) want = s->coop_blocks;
   if (want > s->loss_part_cap) return fm_fail(ctx, FM_ECOOP, "fm_epipolar_solve: loss workspace too small");
   SolveArgs a;
