@@ -63,6 +63,9 @@ struct fm_scene {
   int64_t n_wi = 0;               // Gram work items
   int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
   int32_t* wi_pair = nullptr;     // [n_wi] pair of each work item
+  int64_t n_multi = 0;            // pairs spanning more than one work item
+  int64_t n_empty = 0;            // pairs without matches
+  int32_t* multi = nullptr;       // [n_multi + n_empty]: those pairs, then the empty ones
   unsigned long long* kept_slots = nullptr;  // [kKeptSlots * 16] kept-match counters, one per 128-B line
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order

@@ -133,9 +133,10 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int64_t* __restrict__ wi_off,
     const int32_t* __restrict__ wi_pair, int64_t n_wi, const float* __restrict__ weights,
     const double* __restrict__ ess, double delta, double tau, float* __restrict__ partials,
+    double* __restrict__ W64, float* __restrict__ W32,
     float* __restrict__ w_out, float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
   constexpr int kRows = kPerLane;                     // rows of 64 matches per work item
-  constexpr int kBatch = (DT == FM_F64) ? 4 : kRows;  // rows loaded together
+  constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 8 : kRows);  // rows loaded together
   const int lane = threadIdx.x & (kLanes - 1);
   const int64_t w = (int64_t)blockIdx.x * kGramWaves + (threadIdx.x >> 6);
   if (w >= n_wi) return;  // whole wavefront
@@ -203,7 +204,15 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
   if constexpr (BUILD) {
     int slot;
     const float v = wave_reduce_scatter36(acc, lane, slot);
-    if (slot >= 0) partials[w * 36 + slot] = v;
+    if (slot >= 0) {
+      if (wi_off[n + 1] - wi_off[n] == 1) {
+        // the pair's only work item: this is its Gram
+        if (W64) W64[n * 36 + slot] = (double)v;
+        if (W32) W32[n * 36 + slot] = v;
+      } else {
+        partials[w * 36 + slot] = v;
+      }
+    }
   }
   if constexpr (WMODE == W_IRLS) {
     // integer count, spread over kKeptSlots counters (a single address would
@@ -239,18 +248,30 @@ __global__ __launch_bounds__(kBlock) void k_count_kept(unsigned long long* __res
   sum_kept(kept_slots, kept);
 }
 
-// Sum each pair's work-item partials in float64, in work-item order; block 0
-// also totals the kept counts of an IRLS pass (kept != NULL).
+// Gram of every pair that spans several work items: the sum of its partials
+// in float64, in work-item order (pairs with one work item were written by
+// the partial kernel, pairs without matches are zeroed here).  Block 0 also
+// totals the kept counts of an IRLS pass (kept != NULL).
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restrict__ partials,
-                                                          const int64_t* __restrict__ wi_off, int64_t P,
+                                                          const int64_t* __restrict__ wi_off,
+                                                          const int32_t* __restrict__ multi, int64_t n_multi,
+                                                          const int32_t* __restrict__ empty, int64_t n_empty,
                                                           double* __restrict__ W64, float* __restrict__ W32,
                                                           unsigned long long* __restrict__ kept_slots,
                                                           int64_t* __restrict__ kept) {
   if (kept && blockIdx.x == 0) sum_kept(kept_slots, kept);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= P * 36) return;
-  const int64_t n = t / 36;
-  const int k = (int)(t - n * 36);
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (n_multi + n_empty) * 36) return;
+  if (t >= n_multi * 36) {
+    t -= n_multi * 36;
+    const int64_t e = empty[t / 36] * (int64_t)36 + t % 36;
+    if (W64) W64[e] = 0.0;
+    if (W32) W32[e] = 0.0f;
+    return;
+  }
+  const int64_t n = multi[t / 36];
+  const int k = (int)(t % 36);
+  t = n * 36 + k;
   double s = 0.0;
   for (int64_t w = wi_off[n]; w < wi_off[n + 1]; ++w) s += (double)partials[w * 36 + k];
   if (W64) W64[t] = s;
@@ -278,7 +299,8 @@ __global__ void k_pair_essentials(const float* __restrict__ params, const int32_
 // ------------------------------------------------------------------ host side
 
 template <int WMODE, bool BUILD, bool WRITE>
-static fm_status launch_partial(fm_scene* s, const float* weights, double delta, double tau, float* w_out,
+static fm_status launch_partial(fm_scene* s, const float* weights, double delta, double tau, double* W64,
+                                float* W32, float* w_out,
                                 float* r_out, hipStream_t st) {
   if (s->n_wi == 0) return FM_OK;
   const dim3 grid(grid_for(s->n_wi, kGramWaves)), block(kGramWaves * kLanes);
@@ -286,15 +308,18 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
   switch (s->dtype) {
     case FM_F32:
       hipLaunchKernelGGL((k_gram_partial<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->kept_slots);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, W64, W32, w_out, r_out,
+                         s->kept_slots);
       break;
     case FM_BF16:
       hipLaunchKernelGGL((k_gram_partial<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->kept_slots);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, W64, W32, w_out, r_out,
+                         s->kept_slots);
       break;
     default:
       hipLaunchKernelGGL((k_gram_partial<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, w_out, r_out, s->kept_slots);
+                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, W64, W32, w_out, r_out,
+                         s->kept_slots);
       break;
   }
   FM_CHECK_LAUNCH(s->ctx);
@@ -302,11 +327,12 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
 }
 
 static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* kept, hipStream_t st) {
-  if (s->P == 0 && !kept) return FM_OK;
+  if (s->n_multi + s->n_empty == 0 && !kept) return FM_OK;
   fm_timed timer(s->ctx, FM_K_FINALIZE, st);
-  const int64_t nthreads = s->P * 36 > 0 ? s->P * 36 : 1;
+  const int64_t nthreads = (s->n_multi + s->n_empty) * 36 > 0 ? (s->n_multi + s->n_empty) * 36 : 1;
   hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, s->partials,
-                     s->wi_off, s->P, W64, W32, s->kept_slots, kept);
+                     s->wi_off, s->multi, s->n_multi, s->multi + s->n_multi, s->n_empty, W64, W32, s->kept_slots,
+                     kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
@@ -337,8 +363,8 @@ extern "C" fm_status fm_build_pair_grams(fm_ctx* ctx, fm_scene* s, const float* 
   if (rc != FM_OK) return rc;
   if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_build_pair_grams: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
-  rc = weights ? launch_partial<W_ARRAY, true, false>(s, weights, 0, 0, nullptr, nullptr, st)
-               : launch_partial<W_UNIT, true, false>(s, nullptr, 0, 0, nullptr, nullptr, st);
+  rc = weights ? launch_partial<W_ARRAY, true, false>(s, weights, 0, 0, W64, W32, nullptr, nullptr, st)
+               : launch_partial<W_UNIT, true, false>(s, nullptr, 0, 0, W64, W32, nullptr, nullptr, st);
   if (rc != FM_OK) return rc;
   return launch_finalize(s, W64, W32, nullptr, st);
 }
@@ -359,7 +385,9 @@ extern "C" fm_status fm_reweight(fm_ctx* ctx, fm_scene* s, const float* params, 
   if (!w_out && s->M > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight: weights_out is NULL");
   hipStream_t st = (hipStream_t)stream;
   if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
-  if ((rc = launch_partial<W_IRLS, false, true>(s, nullptr, delta, tau, w_out, r_out, st)) != FM_OK) return rc;
+  if ((rc = launch_partial<W_IRLS, false, true>(s, nullptr, delta, tau, nullptr, nullptr, w_out, r_out, st)) !=
+      FM_OK)
+    return rc;
   hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(kBlock), 0, st, s->kept_slots, kept);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
@@ -373,7 +401,7 @@ extern "C" fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* s, const float* pa
   if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight_build: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
   if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
-  if ((rc = launch_partial<W_IRLS, true, false>(s, nullptr, delta, tau, nullptr, nullptr, st)) != FM_OK)
+  if ((rc = launch_partial<W_IRLS, true, false>(s, nullptr, delta, tau, W64, W32, nullptr, nullptr, st)) != FM_OK)
     return rc;
   return launch_finalize(s, W64, W32, kept, st);
 }

@@ -178,6 +178,28 @@ __global__ void k_wi_fill(const int64_t* wi_off, int64_t P, int32_t* wi_pair) {
     for (int64_t w = wi_off[n]; w < wi_off[n + 1]; ++w) wi_pair[w] = (int32_t)n;
 }
 
+// Flags of pairs with more than one work item (multi) and without any
+// (empty); inclusive scans of the flags give each listed pair its position.
+__global__ void k_multi_flags(const int64_t* wi_off, int64_t P, int32_t* fm, int32_t* fe) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < P) {
+    const int64_t c = wi_off[n + 1] - wi_off[n];
+    fm[n] = c > 1 ? 1 : 0;
+    fe[n] = c == 0 ? 1 : 0;
+  }
+}
+
+// List: the multi pairs, then the empty pairs, each in pair order.
+__global__ void k_multi_scatter(const int64_t* wi_off, int64_t P, const int32_t* sm, const int32_t* se,
+                                int32_t* multi) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < P) {
+    const int64_t c = wi_off[n + 1] - wi_off[n];
+    if (c > 1) multi[sm[n] - 1] = (int32_t)n;
+    if (c == 0) multi[sm[P - 1] + se[n] - 1] = (int32_t)n;
+  }
+}
+
 __global__ void k_cam_degree(const int32_t* cams, int64_t P, int32_t* cam_ptr) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < P) {
@@ -225,6 +247,7 @@ static void scene_free(fm_scene* s) {
   if (!s) return;
   (void)hipFree(s->wi_off);
   (void)hipFree(s->wi_pair);
+  (void)hipFree(s->multi);
   (void)hipFree(s->kept_slots);
   (void)hipFree(s->cam_ptr);
   (void)hipFree(s->cam_items);
@@ -301,9 +324,30 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMalloc(&s->wi_pair, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
   SCENE_TRY(hipMalloc(&s->kept_slots, sizeof(unsigned long long) * 16 * kKeptSlots));
   SCENE_TRY(hipMemsetAsync(s->kept_slots, 0, sizeof(unsigned long long) * 16 * kKeptSlots, st));
+  SCENE_TRY(hipMalloc(&s->multi, sizeof(int32_t) * (P > 0 ? P : 1)));
   if (P > 0) {
     hipLaunchKernelGGL(k_wi_fill, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, s->wi_pair);
     SCENE_TRY(hipGetLastError());
+    int32_t* flags = nullptr;
+    SCENE_TRY(hipMalloc(&flags, sizeof(int32_t) * 2 * P));
+    int32_t *fm = flags, *fe = flags + P;
+    hipLaunchKernelGGL(k_multi_flags, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, fm, fe);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_scan_inclusive<int32_t>, dim3(1), dim3(1024), 0, st, fm, P);
+      hipLaunchKernelGGL(k_scan_inclusive<int32_t>, dim3(1), dim3(1024), 0, st, fe, P);
+      hipLaunchKernelGGL(k_multi_scatter, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, fm, fe,
+                         s->multi);
+      e = hipGetLastError();
+    }
+    int32_t hcount[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&hcount[0], fm + P - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hcount[1], fe + P - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(flags);
+    SCENE_TRY(e);
+    s->n_multi = hcount[0];
+    s->n_empty = hcount[1];
   }
   // camera incidence lists
   SCENE_TRY(hipMalloc(&s->cam_ptr, sizeof(int32_t) * (N + 1)));
