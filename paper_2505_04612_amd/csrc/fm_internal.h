@@ -13,6 +13,8 @@
 constexpr int kLanes = 64;
 constexpr int kPerLane = 16;
 constexpr int kChunk = kLanes * kPerLane;
+// Pairs with at most kSmall matches share a wavefront (16 lanes x 16 rows).
+constexpr int kSmall = 16 * kPerLane;
 // Wavefronts per block of the Gram kernels.
 constexpr int kGramWaves = 4;
 // Threads per block of the per-pair and per-camera kernels.
@@ -63,14 +65,21 @@ struct fm_scene {
   int64_t n_wi = 0;               // Gram work items
   int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
   int32_t* wi_pair = nullptr;     // [n_wi] pair of each work item
-  int64_t n_multi = 0;            // pairs spanning more than one work item
+  // Gram pass plan (built at set-up)
+  int64_t n_big = 0;              // chunk work items of pairs with more than kSmall matches
+  int32_t* big_pair = nullptr;    // [n_big] pair of each chunk
+  int32_t* big_chunk = nullptr;   // [n_big] chunk index within its pair
+  int64_t n_groups = 0;           // wavefronts of four pairs with 1..kSmall matches
+  int32_t* groups = nullptr;      // [4 n_groups] pair ids (-1: none)
+  int64_t n_multi = 0;            // pairs spanning more than one chunk
   int64_t n_empty = 0;            // pairs without matches
   int32_t* multi = nullptr;       // [n_multi + n_empty]: those pairs, then the empty ones
+  int64_t* multi_first = nullptr; // [n_multi] first chunk work item of each multi pair
   unsigned long long* kept_slots = nullptr;  // [kKeptSlots * 16] kept-match counters, one per 128-B line
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order
   // workspace
-  float* partials = nullptr;      // [n_wi, 36]
+  float* partials = nullptr;      // [n_big, 36]
   double* ess = nullptr;          // [P, 9] essential matrices (reweight)
   float* contrib = nullptr;       // [P, 24] per-pair gradient records
   double* loss_part = nullptr;    // [loss_part_cap]

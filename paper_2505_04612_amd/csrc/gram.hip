@@ -122,95 +122,161 @@ __device__ inline void unpack(const typename RawMatch<DT>::T& r, float4& f, doub
   }
 }
 
-// One wavefront per work item (<= 1024 matches of one pair).  All rows of
-// the chunk are loaded before any is used, so a wavefront has its whole
-// chunk in flight (16 KB for float32 rows).  WMODE: W_UNIT (omega = 1),
-// W_ARRAY (omega from `weights`) or W_IRLS (omega from the float64 residual
-// at E_n).  BUILD: accumulate the Gram partials.  WRITE: store omega (and r
-// if r_out) per match.
+// Weight of one match and its contribution to the accumulators.  WMODE:
+// W_UNIT (omega = 1), W_ARRAY (omega from `weights`) or W_IRLS (omega from
+// the float64 residual at E_n).  BUILD: accumulate the Gram sums.  WRITE:
+// store omega (and r if r_out).
 template <int DT, int WMODE, bool BUILD, bool WRITE>
-__global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_partial(
-    const void* __restrict__ uv, const int64_t* __restrict__ off, const int64_t* __restrict__ wi_off,
-    const int32_t* __restrict__ wi_pair, int64_t n_wi, const float* __restrict__ weights,
-    const double* __restrict__ ess, double delta, double tau, float* __restrict__ partials,
-    double* __restrict__ W64, float* __restrict__ W32,
-    float* __restrict__ w_out, float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
-  constexpr int kRows = kPerLane;                     // rows of 64 matches per work item
-  constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 8 : kRows);  // rows loaded together
+__device__ inline void process_match(const typename RawMatch<DT>::T& raw, bool ok, int64_t m, const double E[9],
+                                     float fdelta, double tau, const float* __restrict__ weights,
+                                     float* __restrict__ w_out, float* __restrict__ r_out, float (&acc)[36],
+                                     unsigned& nkept) {
+  float4 xf;
+  double x[4];
+  unpack<DT>(raw, xf, x);
+  float om = ok ? 1.0f : 0.0f;
+  if constexpr (WMODE == W_ARRAY) {
+    const float wm = weights[m];
+    om = ok ? wm : 0.0f;
+  } else if constexpr (WMODE == W_IRLS) {
+    // r = x2~^T E x1~ in float64 from the stored coordinates; the
+    // keep/filter decision is taken on that value
+    const double e0 = E[0] * x[0] + E[1] * x[1] + E[2];
+    const double e1 = E[3] * x[0] + E[4] * x[1] + E[5];
+    const double e2 = E[6] * x[0] + E[7] * x[1] + E[8];
+    const double res = x[2] * e0 + x[3] * e1 + e2;
+    const double a = fabs(res);
+    const float af = fmaxf((float)a, fdelta);
+    om = (ok && a <= tau) ? __builtin_amdgcn_rcpf(af) : 0.0f;
+    nkept += (om > 0.0f) ? 1u : 0u;
+    if constexpr (WRITE) {
+      if (ok && r_out) r_out[m] = (float)res;
+    }
+  }
+  if constexpr (WRITE) {
+    if (ok) w_out[m] = om;
+  }
+  if constexpr (BUILD) accumulate36(acc, xf, om);
+}
+
+// Stream up to 16 rows of STRIDE matches: this lane takes matches
+// start + lid + STRIDE r, r < nrows (nrows is the same in every lane of the
+// wavefront); rows are loaded BATCH at a time before any is used.  Lanes
+// past `count` load the first match (in bounds) with weight 0.
+template <int DT, int WMODE, bool BUILD, bool WRITE, int STRIDE, int BATCH>
+__device__ inline void stream_rows(const void* __restrict__ uv, int64_t start, int count, int lid, int nrows,
+                                   const double E[9], float fdelta, double tau, const float* __restrict__ weights,
+                                   float* __restrict__ w_out, float* __restrict__ r_out, float (&acc)[36],
+                                   unsigned& nkept) {
+#pragma unroll
+  for (int r0 = 0; r0 < kPerLane; r0 += BATCH) {
+    if (r0 >= nrows) break;
+    typename RawMatch<DT>::T raw[BATCH];
+#pragma unroll
+    for (int r = 0; r < BATCH; ++r) {
+      if (r0 + r < nrows) {
+        const int i = (r0 + r) * STRIDE + lid;
+        raw[r] = load_raw<DT>(uv, i < count ? start + i : start);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < BATCH; ++r) {
+      if (r0 + r < nrows) {
+        const int i = (r0 + r) * STRIDE + lid;
+        const bool ok = i < count;
+        process_match<DT, WMODE, BUILD, WRITE>(raw[r], ok, ok ? start + i : start, E, fdelta, tau, weights, w_out,
+                                                r_out, acc, nkept);
+      }
+    }
+  }
+}
+
+// Reduce-scatter of 36 values over one 16-lane row (lane bits 3..0, DPP):
+// each lane keeps 3 of the row's totals; value k of lane l is entry
+// z + 5 b1 + 9 b2 + 18 b3 with z = k + 3 b0, valid if z < 5 and z + 5 b1 < 9.
+__device__ inline void row_reduce_scatter36(const float (&a)[36], int lane, float (&out)[3]) {
+  float b[18], c[9], d[5];
+  rs_stage<36, 3>(a, b, lane);
+  rs_stage<18, 2>(b, c, lane);
+  rs_stage<9, 1>(c, d, lane);
+  rs_stage<5, 0>(d, out, lane);
+}
+
+// The Gram pass.  Work item w < n_big: one wavefront on chunk big_chunk[w]
+// (<= 1024 matches, 16 per lane, lanes strided so each load instruction
+// reads one contiguous span) of a pair with more than kSmall matches.  Work
+// item w >= n_big: one wavefront on four pairs of at most kSmall matches,
+// 16 lanes each (groups of pairs with equal row counts, built at set-up).
+// Each pair's sums are reduced over its lanes in a fixed order; a pair whose
+// matches one wavefront covered stores its Gram directly (float64 of the
+// float32 sum), the others leave per-chunk partials for k_gram_finalize.
+template <int DT, int WMODE, bool BUILD, bool WRITE>
+__global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
+    const void* __restrict__ uv, const int64_t* __restrict__ off, const int32_t* __restrict__ big_pair,
+    const int32_t* __restrict__ big_chunk, int64_t n_big, const int32_t* __restrict__ groups, int64_t n_groups,
+    const float* __restrict__ weights, const double* __restrict__ ess, double delta, double tau,
+    float* __restrict__ partials, double* __restrict__ W64, float* __restrict__ W32, float* __restrict__ w_out,
+    float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
+  constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 8 : kPerLane);
   const int lane = threadIdx.x & (kLanes - 1);
   const int64_t w = (int64_t)blockIdx.x * kGramWaves + (threadIdx.x >> 6);
-  if (w >= n_wi) return;  // whole wavefront
-  const int64_t n = wi_pair[w];
-  const int64_t start = off[n] + (w - wi_off[n]) * kChunk;
-  const int count = (int)min(off[n + 1] - start, (int64_t)kChunk);
-  const int nrows = (count + kLanes - 1) / kLanes;
-  double E[9];
-  if constexpr (WMODE == W_IRLS) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) E[k] = ess[n * 9 + k];
-  }
+  if (w >= n_big + n_groups) return;  // whole wavefront
   const float fdelta = (float)delta;
   float acc[36];
 #pragma unroll
   for (int k = 0; k < 36; ++k) acc[k] = 0.0f;
   unsigned nkept = 0;
+  double E[9];
+  if (w < n_big) {
+    const int64_t n = big_pair[w];
+    const int64_t total = off[n + 1] - off[n];
+    const int64_t start = off[n] + (int64_t)big_chunk[w] * kChunk;
+    const int count = (int)min(off[n + 1] - start, (int64_t)kChunk);
+    if constexpr (WMODE == W_IRLS) {
 #pragma unroll
-  for (int r0 = 0; r0 < kRows; r0 += kBatch) {
-    if (r0 >= nrows) break;
-    typename RawMatch<DT>::T raw[kBatch];
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      if (r0 + r < nrows) {
-        // lanes past the end of the chunk load its first match (in bounds)
-        const int i = (r0 + r) * kLanes + lane;
-        raw[r] = load_raw<DT>(uv, i < count ? start + i : start);
-      }
+      for (int k = 0; k < 9; ++k) E[k] = ess[n * 9 + k];
     }
-#pragma unroll
-    for (int r = 0; r < kBatch; ++r) {
-      if (r0 + r < nrows) {
-      const int i = (r0 + r) * kLanes + lane;
-      const bool ok = i < count;
-      const int64_t m = ok ? start + i : start;
-      float4 xf;
-      double x[4];
-      unpack<DT>(raw[r], xf, x);
-      float om = ok ? 1.0f : 0.0f;
-      if constexpr (WMODE == W_ARRAY) {
-        const float wm = weights[m];
-        om = ok ? wm : 0.0f;
-      } else if constexpr (WMODE == W_IRLS) {
-        // r = x2~^T E x1~ in float64 from the stored coordinates; the
-        // keep/filter decision is taken on that value
-        const double e0 = E[0] * x[0] + E[1] * x[1] + E[2];
-        const double e1 = E[3] * x[0] + E[4] * x[1] + E[5];
-        const double e2 = E[6] * x[0] + E[7] * x[1] + E[8];
-        const double res = x[2] * e0 + x[3] * e1 + e2;
-        const double a = fabs(res);
-        const float af = fmaxf((float)a, fdelta);
-        om = (ok && a <= tau) ? __builtin_amdgcn_rcpf(af) : 0.0f;
-        nkept += (om > 0.0f) ? 1u : 0u;
-        if constexpr (WRITE) {
-          if (ok && r_out) r_out[m] = (float)res;
+    stream_rows<DT, WMODE, BUILD, WRITE, kLanes, kBatch>(uv, start, count, lane, (count + kLanes - 1) / kLanes, E,
+                                                         fdelta, tau, weights, w_out, r_out, acc, nkept);
+    if constexpr (BUILD) {
+      int slot;
+      const float v = wave_reduce_scatter36(acc, lane, slot);
+      if (slot >= 0) {
+        if (total <= kChunk) {
+          if (W64) W64[n * 36 + slot] = (double)v;
+          if (W32) W32[n * 36 + slot] = v;
+        } else {
+          partials[w * 36 + slot] = v;
         }
       }
-      if constexpr (WRITE) {
-        if (ok) w_out[m] = om;
-      }
-      if constexpr (BUILD) accumulate36(acc, xf, om);
-      }
     }
-  }
-  if constexpr (BUILD) {
-    int slot;
-    const float v = wave_reduce_scatter36(acc, lane, slot);
-    if (slot >= 0) {
-      if (wi_off[n + 1] - wi_off[n] == 1) {
-        // the pair's only work item: this is its Gram
-        if (W64) W64[n * 36 + slot] = (double)v;
-        if (W32) W32[n * 36 + slot] = v;
-      } else {
-        partials[w * 36 + slot] = v;
+  } else {
+    const int l16 = lane & 15;
+    const int64_t n = groups[(w - n_big) * 4 + (lane >> 4)];
+    const bool have = n >= 0;
+    const int64_t start = have ? off[n] : 0;
+    const int count = have ? (int)(off[n + 1] - start) : 0;
+    int nrows = (count + 15) >> 4;
+    nrows = max(nrows, __shfl_xor(nrows, 16));
+    nrows = max(nrows, __shfl_xor(nrows, 32));
+    if constexpr (WMODE == W_IRLS) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) E[k] = have ? ess[n * 9 + k] : 0.0;
+    }
+    stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch>(uv, start, count, l16, nrows, E, fdelta, tau, weights, w_out,
+                                                     r_out, acc, nkept);
+    if constexpr (BUILD) {
+      float v[3];
+      row_reduce_scatter36(acc, lane, v);
+      const int b0 = l16 & 1, b1 = (l16 >> 1) & 1, b2 = (l16 >> 2) & 1, b3 = (l16 >> 3) & 1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int z = k + 3 * b0;
+        if (have && z < 5 && z + 5 * b1 < 9) {
+          const int slot = z + 5 * b1 + 9 * b2 + 18 * b3;
+          if (W64) W64[n * 36 + slot] = (double)v[k];
+          if (W32) W32[n * 36 + slot] = v[k];
+        }
       }
     }
   }
@@ -248,13 +314,14 @@ __global__ __launch_bounds__(kBlock) void k_count_kept(unsigned long long* __res
   sum_kept(kept_slots, kept);
 }
 
-// Gram of every pair that spans several work items: the sum of its partials
-// in float64, in work-item order (pairs with one work item were written by
-// the partial kernel, pairs without matches are zeroed here).  Block 0 also
-// totals the kept counts of an IRLS pass (kept != NULL).
+// Gram of every pair that spans several work items: the sum of its chunk
+// partials in float64, in chunk order (the other pairs with matches were
+// written by the pass itself, pairs without matches are zeroed here).
+// Block 0 also totals the kept counts of an IRLS pass (kept != NULL).
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restrict__ partials,
-                                                          const int64_t* __restrict__ wi_off,
-                                                          const int32_t* __restrict__ multi, int64_t n_multi,
+                                                          const int64_t* __restrict__ off,
+                                                          const int32_t* __restrict__ multi,
+                                                          const int64_t* __restrict__ multi_first, int64_t n_multi,
                                                           const int32_t* __restrict__ empty, int64_t n_empty,
                                                           double* __restrict__ W64, float* __restrict__ W32,
                                                           unsigned long long* __restrict__ kept_slots,
@@ -269,13 +336,14 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restric
     if (W32) W32[e] = 0.0f;
     return;
   }
-  const int64_t n = multi[t / 36];
+  const int64_t i = t / 36;
+  const int64_t n = multi[i];
   const int k = (int)(t % 36);
-  t = n * 36 + k;
+  const int64_t chunks = (off[n + 1] - off[n] + kChunk - 1) / kChunk;
   double s = 0.0;
-  for (int64_t w = wi_off[n]; w < wi_off[n + 1]; ++w) s += (double)partials[w * 36 + k];
-  if (W64) W64[t] = s;
-  if (W32) W32[t] = (float)s;
+  for (int64_t j = 0; j < chunks; ++j) s += (double)partials[(multi_first[i] + j) * 36 + k];
+  if (W64) W64[n * 36 + k] = s;
+  if (W32) W32[n * 36 + k] = (float)s;
 }
 
 // E_n for every pair at the given poses (float64), for the residual pass.
@@ -300,28 +368,26 @@ __global__ void k_pair_essentials(const float* __restrict__ params, const int32_
 
 template <int WMODE, bool BUILD, bool WRITE>
 static fm_status launch_partial(fm_scene* s, const float* weights, double delta, double tau, double* W64,
-                                float* W32, float* w_out,
-                                float* r_out, hipStream_t st) {
-  if (s->n_wi == 0) return FM_OK;
-  const dim3 grid(grid_for(s->n_wi, kGramWaves)), block(kGramWaves * kLanes);
+                                float* W32, float* w_out, float* r_out, hipStream_t st) {
+  const int64_t items = s->n_big + s->n_groups;
+  if (items == 0) return FM_OK;
+  const dim3 grid(grid_for(items, kGramWaves)), block(kGramWaves * kLanes);
   fm_timed timer(s->ctx, FM_K_GRAM, st);
+#define FM_GRAM_ARGS                                                                                          \
+  s->uv, s->offsets, s->big_pair, s->big_chunk, s->n_big, s->groups, s->n_groups, weights, s->ess, delta, tau, \
+      s->partials, W64, W32, w_out, r_out, s->kept_slots
   switch (s->dtype) {
     case FM_F32:
-      hipLaunchKernelGGL((k_gram_partial<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, W64, W32, w_out, r_out,
-                         s->kept_slots);
+      hipLaunchKernelGGL((k_gram_pass<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, FM_GRAM_ARGS);
       break;
     case FM_BF16:
-      hipLaunchKernelGGL((k_gram_partial<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, W64, W32, w_out, r_out,
-                         s->kept_slots);
+      hipLaunchKernelGGL((k_gram_pass<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, FM_GRAM_ARGS);
       break;
     default:
-      hipLaunchKernelGGL((k_gram_partial<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, s->uv, s->offsets,
-                         s->wi_off, s->wi_pair, s->n_wi, weights, s->ess, delta, tau, s->partials, W64, W32, w_out, r_out,
-                         s->kept_slots);
+      hipLaunchKernelGGL((k_gram_pass<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, FM_GRAM_ARGS);
       break;
   }
+#undef FM_GRAM_ARGS
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
@@ -331,8 +397,8 @@ static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* 
   fm_timed timer(s->ctx, FM_K_FINALIZE, st);
   const int64_t nthreads = (s->n_multi + s->n_empty) * 36 > 0 ? (s->n_multi + s->n_empty) * 36 : 1;
   hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, s->partials,
-                     s->wi_off, s->multi, s->n_multi, s->multi + s->n_multi, s->n_empty, W64, W32, s->kept_slots,
-                     kept);
+                     s->offsets, s->multi, s->multi_first, s->n_multi, s->multi + s->n_multi, s->n_empty, W64, W32,
+                     s->kept_slots, kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }

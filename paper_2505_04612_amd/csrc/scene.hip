@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <new>
+#include <vector>
 
 #include "fm_internal.h"
 
@@ -178,28 +179,6 @@ __global__ void k_wi_fill(const int64_t* wi_off, int64_t P, int32_t* wi_pair) {
     for (int64_t w = wi_off[n]; w < wi_off[n + 1]; ++w) wi_pair[w] = (int32_t)n;
 }
 
-// Flags of pairs with more than one work item (multi) and without any
-// (empty); inclusive scans of the flags give each listed pair its position.
-__global__ void k_multi_flags(const int64_t* wi_off, int64_t P, int32_t* fm, int32_t* fe) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < P) {
-    const int64_t c = wi_off[n + 1] - wi_off[n];
-    fm[n] = c > 1 ? 1 : 0;
-    fe[n] = c == 0 ? 1 : 0;
-  }
-}
-
-// List: the multi pairs, then the empty pairs, each in pair order.
-__global__ void k_multi_scatter(const int64_t* wi_off, int64_t P, const int32_t* sm, const int32_t* se,
-                                int32_t* multi) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < P) {
-    const int64_t c = wi_off[n + 1] - wi_off[n];
-    if (c > 1) multi[sm[n] - 1] = (int32_t)n;
-    if (c == 0) multi[sm[P - 1] + se[n] - 1] = (int32_t)n;
-  }
-}
-
 __global__ void k_cam_degree(const int32_t* cams, int64_t P, int32_t* cam_ptr) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < P) {
@@ -248,6 +227,10 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->wi_off);
   (void)hipFree(s->wi_pair);
   (void)hipFree(s->multi);
+  (void)hipFree(s->multi_first);
+  (void)hipFree(s->big_pair);
+  (void)hipFree(s->big_chunk);
+  (void)hipFree(s->groups);
   (void)hipFree(s->kept_slots);
   (void)hipFree(s->cam_ptr);
   (void)hipFree(s->cam_items);
@@ -261,9 +244,67 @@ static void scene_free(fm_scene* s) {
 
 extern "C" void fm_scene_destroy(fm_scene* s) { scene_free(s); }
 
-extern "C" int64_t fm_scene_work_items(const fm_scene* s) { return s ? s->n_wi : -1; }
+extern "C" int64_t fm_scene_work_items(const fm_scene* s) { return s ? s->n_big + s->n_groups : -1; }
 
 int fm_solve_coop_blocks(fm_ctx* ctx);  // iterate.hip
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
+  hipError_t e = hipMalloc(dst, sizeof(T) * (v.empty() ? 1 : v.size()));
+  if (e == hipSuccess && !v.empty()) e = hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+  return e;
+}
+
+// Work decomposition of the Gram pass, from the pair offsets (set-up only,
+// on the host): pairs with more than kSmall matches are cut into chunks of
+// kChunk (one wavefront each); pairs with 1..kSmall matches are bucketed by
+// their number of 16-match rows and packed four to a wavefront; the lists of
+// multi-chunk and empty pairs drive the finalize kernel.  Which wavefront
+// handles a pair does not change its result (each pair's sums use a fixed
+// lane/row assignment and reduction order).
+static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
+  fm_ctx* ctx = s->ctx;
+  const int64_t P = s->P;
+  std::vector<int64_t> off(P + 1);
+  hipError_t e = hipMemcpyAsync(off.data(), s->offsets, sizeof(int64_t) * (P + 1), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fm_fail(ctx, FM_EHIP, "gram plan: %s", hipGetErrorString(e));
+  std::vector<int32_t> big_pair, big_chunk, groups, multi, empty;
+  std::vector<int64_t> multi_first;
+  std::vector<std::vector<int32_t>> bucket(kPerLane + 1);
+  for (int64_t n = 0; n < P; ++n) {
+    const int64_t c = off[n + 1] - off[n];
+    if (c == 0) {
+      empty.push_back((int32_t)n);
+    } else if (c <= kSmall) {
+      bucket[(c + 15) / 16].push_back((int32_t)n);
+    } else {
+      const int64_t chunks = (c + kChunk - 1) / kChunk;
+      if (chunks > 1) {
+        multi.push_back((int32_t)n);
+        multi_first.push_back((int64_t)big_pair.size());
+      }
+      for (int64_t j = 0; j < chunks; ++j) {
+        big_pair.push_back((int32_t)n);
+        big_chunk.push_back((int32_t)j);
+      }
+    }
+  }
+  for (auto& b : bucket) {
+    for (size_t k = 0; k < b.size(); ++k) groups.push_back(b[k]);
+    while (groups.size() % 4) groups.push_back(-1);
+  }
+  s->n_big = (int64_t)big_pair.size();
+  s->n_groups = (int64_t)groups.size() / 4;
+  s->n_multi = (int64_t)multi.size();
+  s->n_empty = (int64_t)empty.size();
+  multi.insert(multi.end(), empty.begin(), empty.end());
+  if ((e = upload(&s->big_pair, big_pair, st)) != hipSuccess || (e = upload(&s->big_chunk, big_chunk, st)) != hipSuccess ||
+      (e = upload(&s->groups, groups, st)) != hipSuccess || (e = upload(&s->multi, multi, st)) != hipSuccess ||
+      (e = upload(&s->multi_first, multi_first, st)) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess)
+    return fm_fail(ctx, e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP, "gram plan: %s", hipGetErrorString(e));
+  return FM_OK;
+}
 
 #define SCENE_TRY(expr)                                                                   \
   do {                                                                                    \
@@ -324,30 +365,18 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMalloc(&s->wi_pair, sizeof(int32_t) * (s->n_wi > 0 ? s->n_wi : 1)));
   SCENE_TRY(hipMalloc(&s->kept_slots, sizeof(unsigned long long) * 16 * kKeptSlots));
   SCENE_TRY(hipMemsetAsync(s->kept_slots, 0, sizeof(unsigned long long) * 16 * kKeptSlots, st));
-  SCENE_TRY(hipMalloc(&s->multi, sizeof(int32_t) * (P > 0 ? P : 1)));
   if (P > 0) {
     hipLaunchKernelGGL(k_wi_fill, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, s->wi_pair);
     SCENE_TRY(hipGetLastError());
-    int32_t* flags = nullptr;
-    SCENE_TRY(hipMalloc(&flags, sizeof(int32_t) * 2 * P));
-    int32_t *fm = flags, *fe = flags + P;
-    hipLaunchKernelGGL(k_multi_flags, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, fm, fe);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_scan_inclusive<int32_t>, dim3(1), dim3(1024), 0, st, fm, P);
-      hipLaunchKernelGGL(k_scan_inclusive<int32_t>, dim3(1), dim3(1024), 0, st, fe, P);
-      hipLaunchKernelGGL(k_multi_scatter, dim3(grid_for(P, kBlock)), dim3(kBlock), 0, st, s->wi_off, P, fm, fe,
-                         s->multi);
-      e = hipGetLastError();
+  }
+  {
+    fm_status prc = build_gram_plan(s, st);
+    if (prc != FM_OK) {
+      (void)hipFree(tmp_i32);
+      (void)hipFree(flag);
+      scene_free(s);
+      return prc;
     }
-    int32_t hcount[2] = {0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(&hcount[0], fm + P - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&hcount[1], fe + P - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(flags);
-    SCENE_TRY(e);
-    s->n_multi = hcount[0];
-    s->n_empty = hcount[1];
   }
   // camera incidence lists
   SCENE_TRY(hipMalloc(&s->cam_ptr, sizeof(int32_t) * (N + 1)));
@@ -385,7 +414,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   }
   s->loss_part_cap = (int64_t)grid_for(P, kBlock);
   if (s->loss_part_cap < s->coop_blocks) s->loss_part_cap = s->coop_blocks;
-  SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_wi > 0 ? s->n_wi : 1)));
+  SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_big > 0 ? s->n_big : 1)));
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
