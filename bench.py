@@ -38,6 +38,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "medium_oracle.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "gram_medium_traffic.json")
 GRAM_SRC = os.path.join(ROOT, "paper_2505_04612_amd", "csrc", "gram.hip")
 HBM_PEAK_GBPS = 8000.0
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12     # lane-instructions per second, non-packed
+VALU_PER_MATCH_BF16 = 65                       # IRLS Gram pass, BF16 coordinates
 
 
 def log(msg: str) -> None:
@@ -140,6 +142,8 @@ def main() -> int:
                     help="medium (default, the metric's workload) or large (5,000 cameras, ~200M BF16 "
                          "matches: Gram-pass and iteration throughput with sampled Gram parity)")
     ap.add_argument("--scale", type=float, default=1.0, help="camera-count scale of the large workload")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="processes generating the large workload (default: up to 16; 1 = no child processes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the hot path runs on a single MI355X and this build "
@@ -227,7 +231,7 @@ def main() -> int:
         "pose_check": {"passed": passed, "rot_max_deg": float(rot.max()), "rot_median_deg": float(np.median(rot)),
                        "t_max_deg": float(tra.max()), "t_median_deg": float(np.median(tra)),
                        "kept_gpu": int(Z.item()), "kept_oracle": golden["kept"]},
-        "roofline": {"bound": "hbm", "kernel": "k_gram_partial (fused IRLS reweight + Gram, float32 coords)",
+        "roofline": {"bound": "hbm", "kernel": "k_gram_pass (fused IRLS reweight + Gram, float32 coords)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes},
@@ -249,7 +253,7 @@ def bench_large(args) -> int:
 
     from paper_2505_04612_amd import _lib, api, solver, synth
     t_gen = time.perf_counter()
-    workers = max(1, min(16, (os.cpu_count() or 1)))
+    workers = args.workers if args.workers > 0 else max(1, min(16, (os.cpu_count() or 1)))
     sc = synth.large(scale=args.scale, workers=workers)   # before any GPU call
     log(f"[bench] large scene {sc.stats()} generated in {time.perf_counter() - t_gen:.1f}s")
     ctx = api.default_context()
@@ -326,9 +330,16 @@ def bench_large(args) -> int:
         "gram_pass_us": gram_s * 1e6,
         "gram_aux_us": {"essentials": ess_ms * 1e3 / max(n_gram, 1), "finalize": fin_ms * 1e3 / max(n_gram, 1)},
         "sampled_gram_parity": {"pairs": int(len(sample)), "max_rel_fro": worst_rel, "max_elem_rel": worst_el},
-        "roofline": {"bound": "hbm", "kernel": "k_gram_partial (fused IRLS reweight + Gram, bf16 coords)",
+        "roofline": {"bound": "hbm", "kernel": "k_gram_pass (fused IRLS reweight + Gram, bf16 coords)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "alg_bytes_per_launch": alg_bytes},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "alg_bytes_per_launch": alg_bytes,
+                     # with 8 B per match the pass issues more VALU work than HBM time:
+                     # VALU instructions per match (gfx950 assembly of the kernel) against
+                     # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+                     "valu": {"instr_per_match": VALU_PER_MATCH_BF16,
+                              "achieved_T_lane_instr_per_s": VALU_PER_MATCH_BF16 * M / gram_s / 1e12,
+                              "peak_T_lane_instr_per_s": VALU_PEAK_T,
+                              "frac": VALU_PER_MATCH_BF16 * M / gram_s / 1e12 / VALU_PEAK_T}},
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -74,9 +74,10 @@ __device__ inline float wave_reduce_scatter36(const float (&a)[36], int lane, in
 }
 
 __device__ inline void accumulate36(float (&acc)[36], float4 x, float om) {
-  // p1 = monomials of x1 = (u1, v1), p2 of x2 = (u2, v2)
+  // p1 = monomials of x1 = (u1, v1); w2 = omega times the monomials of x2
   const float p1[5] = {x.x * x.x, x.x * x.y, x.y * x.y, x.x, x.y};
-  const float w2[6] = {om * (x.z * x.z), om * (x.z * x.w), om * (x.w * x.w), om * x.z, om * x.w, om};
+  const float ou = om * x.z, ov = om * x.w;
+  const float w2[6] = {ou * x.z, ou * x.w, ov * x.w, ou, ov, om};
 #pragma unroll
   for (int q2 = 0; q2 < 6; ++q2) {
 #pragma unroll
@@ -92,15 +93,13 @@ template <> struct RawMatch<FM_BF16> { using T = uint2; };
 template <> struct RawMatch<FM_F64> { using T = double4; };
 
 template <int DT>
-__device__ inline typename RawMatch<DT>::T load_raw(const void* uv, int64_t m) {
-  if constexpr (DT == FM_F32) {
-    return reinterpret_cast<const float4*>(uv)[m];
-  } else if constexpr (DT == FM_BF16) {
-    return reinterpret_cast<const uint2*>(uv)[m];
-  } else {
-    const double2* d = reinterpret_cast<const double2*>(uv) + 2 * m;
+__device__ inline typename RawMatch<DT>::T load_raw(const typename RawMatch<DT>::T* __restrict__ p) {
+  if constexpr (DT == FM_F64) {
+    const double2* d = reinterpret_cast<const double2*>(p);
     const double2 a = d[0], b = d[1];
     return double4{a.x, a.y, b.x, b.y};
+  } else {
+    return *p;
   }
 }
 
@@ -125,8 +124,11 @@ __device__ inline void unpack(const typename RawMatch<DT>::T& r, float4& f, doub
 // Weight of one match and its contribution to the accumulators.  WMODE:
 // W_UNIT (omega = 1), W_ARRAY (omega from `weights`) or W_IRLS (omega from
 // the float64 residual at E_n).  BUILD: accumulate the Gram sums.  WRITE:
-// store omega (and r if r_out).
-template <int DT, int WMODE, bool BUILD, bool WRITE>
+// store omega (and r if r_out).  CHECKED: `ok` says whether this lane's row
+// entry is a match of the work item (lanes past the end carry weight 0);
+// unchecked rows are full.  The kept count of an IRLS pass is taken per
+// wavefront with a ballot, so it lives in a scalar register.
+template <int DT, int WMODE, bool BUILD, bool WRITE, bool CHECKED>
 __device__ inline void process_match(const typename RawMatch<DT>::T& raw, bool ok, int64_t m, const double E[9],
                                      float fdelta, double tau, const float* __restrict__ weights,
                                      float* __restrict__ w_out, float* __restrict__ r_out, float (&acc)[36],
@@ -134,59 +136,84 @@ __device__ inline void process_match(const typename RawMatch<DT>::T& raw, bool o
   float4 xf;
   double x[4];
   unpack<DT>(raw, xf, x);
-  float om = ok ? 1.0f : 0.0f;
-  if constexpr (WMODE == W_ARRAY) {
-    const float wm = weights[m];
-    om = ok ? wm : 0.0f;
-  } else if constexpr (WMODE == W_IRLS) {
+  float om = 1.0f;
+  if constexpr (WMODE == W_UNIT) {
+    if constexpr (CHECKED) om = ok ? 1.0f : 0.0f;
+  } else if constexpr (WMODE == W_ARRAY) {
+    om = weights[m];
+    if constexpr (CHECKED) om = ok ? om : 0.0f;
+  } else {
     // r = x2~^T E x1~ in float64 from the stored coordinates; the
     // keep/filter decision is taken on that value
-    const double e0 = E[0] * x[0] + E[1] * x[1] + E[2];
-    const double e1 = E[3] * x[0] + E[4] * x[1] + E[5];
-    const double e2 = E[6] * x[0] + E[7] * x[1] + E[8];
-    const double res = x[2] * e0 + x[3] * e1 + e2;
+    const double e0 = fma(E[0], x[0], fma(E[1], x[1], E[2]));
+    const double e1 = fma(E[3], x[0], fma(E[4], x[1], E[5]));
+    const double e2 = fma(E[6], x[0], fma(E[7], x[1], E[8]));
+    const double res = fma(x[2], e0, fma(x[3], e1, e2));
     const double a = fabs(res);
+    bool keep = a <= tau;
+    if constexpr (CHECKED) keep = keep && ok;
     const float af = fmaxf((float)a, fdelta);
-    om = (ok && a <= tau) ? __builtin_amdgcn_rcpf(af) : 0.0f;
-    nkept += (om > 0.0f) ? 1u : 0u;
+    om = keep ? __builtin_amdgcn_rcpf(af) : 0.0f;
+    nkept += (unsigned)__popcll(__ballot(keep));
     if constexpr (WRITE) {
-      if (ok && r_out) r_out[m] = (float)res;
+      if (r_out && (!CHECKED || ok)) r_out[m] = (float)res;
     }
   }
   if constexpr (WRITE) {
-    if (ok) w_out[m] = om;
+    if (!CHECKED || ok) w_out[m] = om;
   }
   if constexpr (BUILD) accumulate36(acc, xf, om);
 }
 
-// Stream up to 16 rows of STRIDE matches: this lane takes matches
-// start + lid + STRIDE r, r < nrows (nrows is the same in every lane of the
-// wavefront); rows are loaded BATCH at a time before any is used.  Lanes
-// past `count` load the first match (in bounds) with weight 0.
+// Stream the rows of one work item: this lane takes matches
+// start + lid + STRIDE r for r < nrows (nrows is the same in every lane of
+// the wavefront).  Rows below `nfull` are full and load straight from a
+// per-lane pointer; the rows from nfull on are checked against `count`
+// (lanes past it load the item's first match and weigh it 0).  Full rows are
+// loaded BATCH at a time before any is used; a single checked row is loaded
+// with the first batch.
 template <int DT, int WMODE, bool BUILD, bool WRITE, int STRIDE, int BATCH>
 __device__ inline void stream_rows(const void* __restrict__ uv, int64_t start, int count, int lid, int nrows,
-                                   const double E[9], float fdelta, double tau, const float* __restrict__ weights,
-                                   float* __restrict__ w_out, float* __restrict__ r_out, float (&acc)[36],
-                                   unsigned& nkept) {
+                                   int nfull, const double E[9], float fdelta, double tau,
+                                   const float* __restrict__ weights, float* __restrict__ w_out,
+                                   float* __restrict__ r_out, float (&acc)[36], unsigned& nkept) {
+  using RawT = typename RawMatch<DT>::T;
+  const RawT* __restrict__ base = reinterpret_cast<const RawT*>(uv) + start;
+  const RawT* __restrict__ p = base + lid;
+  // second base for rows 8.. (keeps every full-row load an immediate offset)
+  const RawT* __restrict__ p8 = p + 8 * STRIDE;
+  const int64_t m0 = start + lid;
+  const bool one_tail = nrows - nfull == 1;
+  RawT traw;
+  const int ti = nfull * STRIDE + lid;
+  const bool tok = ti < count;
+  if (one_tail) traw = load_raw<DT>(tok ? p + nfull * STRIDE : base);
 #pragma unroll
   for (int r0 = 0; r0 < kPerLane; r0 += BATCH) {
-    if (r0 >= nrows) break;
-    typename RawMatch<DT>::T raw[BATCH];
+    if (r0 < nfull) {
+      RawT raw[BATCH];
 #pragma unroll
-    for (int r = 0; r < BATCH; ++r) {
-      if (r0 + r < nrows) {
-        const int i = (r0 + r) * STRIDE + lid;
-        raw[r] = load_raw<DT>(uv, i < count ? start + i : start);
-      }
+      for (int r = 0; r < BATCH; ++r)
+        if (r0 + r < nfull) raw[r] = load_raw<DT>(r0 + r < 8 ? p + (r0 + r) * STRIDE : p8 + (r0 + r - 8) * STRIDE);
+#pragma unroll
+      for (int r = 0; r < BATCH; ++r)
+        if (r0 + r < nfull)
+          process_match<DT, WMODE, BUILD, WRITE, false>(raw[r], true, m0 + (r0 + r) * STRIDE, E, fdelta, tau,
+                                                        weights, w_out, r_out, acc, nkept);
     }
-#pragma unroll
-    for (int r = 0; r < BATCH; ++r) {
-      if (r0 + r < nrows) {
-        const int i = (r0 + r) * STRIDE + lid;
-        const bool ok = i < count;
-        process_match<DT, WMODE, BUILD, WRITE>(raw[r], ok, ok ? start + i : start, E, fdelta, tau, weights, w_out,
-                                                r_out, acc, nkept);
-      }
+  }
+  if (one_tail) {
+    process_match<DT, WMODE, BUILD, WRITE, true>(traw, tok, tok ? start + ti : start, E, fdelta, tau, weights,
+                                                 w_out, r_out, acc, nkept);
+  } else {
+    // several checked rows: only a wavefront whose four pair slots are not
+    // all filled (at most one per row count) comes here
+    for (int r = nfull; r < nrows; ++r) {
+      const int i = r * STRIDE + lid;
+      const bool ok = i < count;
+      const RawT raw = load_raw<DT>(ok ? p + r * STRIDE : base);
+      process_match<DT, WMODE, BUILD, WRITE, true>(raw, ok, ok ? start + i : start, E, fdelta, tau, weights, w_out,
+                                                   r_out, acc, nkept);
     }
   }
 }
@@ -219,7 +246,9 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
   constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 8 : kPerLane);
   const int lane = threadIdx.x & (kLanes - 1);
-  const int64_t w = (int64_t)blockIdx.x * kGramWaves + (threadIdx.x >> 6);
+  // wave-uniform work item (scalar registers: the big path's pair data and
+  // E_n are then scalar loads)
+  const int64_t w = (int64_t)blockIdx.x * kGramWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w >= n_big + n_groups) return;  // whole wavefront
   const float fdelta = (float)delta;
   float acc[36];
@@ -233,11 +262,17 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     const int64_t start = off[n] + (int64_t)big_chunk[w] * kChunk;
     const int count = (int)min(off[n + 1] - start, (int64_t)kChunk);
     if constexpr (WMODE == W_IRLS) {
+      // E_n is uniform here; held in vector registers all the same, since a
+      // float64 FMA may read only one scalar operand
 #pragma unroll
-      for (int k = 0; k < 9; ++k) E[k] = ess[n * 9 + k];
+      for (int k = 0; k < 9; ++k) {
+        E[k] = ess[n * 9 + k];
+        asm volatile("" : "+v"(E[k]));
+      }
     }
-    stream_rows<DT, WMODE, BUILD, WRITE, kLanes, kBatch>(uv, start, count, lane, (count + kLanes - 1) / kLanes, E,
-                                                         fdelta, tau, weights, w_out, r_out, acc, nkept);
+    stream_rows<DT, WMODE, BUILD, WRITE, kLanes, kBatch>(uv, start, count, lane, (count + kLanes - 1) / kLanes,
+                                                         count / kLanes, E, fdelta, tau, weights, w_out, r_out, acc,
+                                                         nkept);
     if constexpr (BUILD) {
       int slot;
       const float v = wave_reduce_scatter36(acc, lane, slot);
@@ -256,15 +291,19 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     const bool have = n >= 0;
     const int64_t start = have ? off[n] : 0;
     const int count = have ? (int)(off[n + 1] - start) : 0;
+    // the four pairs of a group have the same row count; rows before the
+    // last are full unless a pair slot is empty
     int nrows = (count + 15) >> 4;
     nrows = max(nrows, __shfl_xor(nrows, 16));
     nrows = max(nrows, __shfl_xor(nrows, 32));
+    nrows = __builtin_amdgcn_readfirstlane(nrows);
+    const int nfull = (__ballot(!have) == 0ull) ? nrows - 1 : 0;
     if constexpr (WMODE == W_IRLS) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) E[k] = have ? ess[n * 9 + k] : 0.0;
     }
-    stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch>(uv, start, count, l16, nrows, E, fdelta, tau, weights, w_out,
-                                                     r_out, acc, nkept);
+    stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch>(uv, start, count, l16, nrows, nfull, E, fdelta, tau, weights,
+                                                     w_out, r_out, acc, nkept);
     if constexpr (BUILD) {
       float v[3];
       row_reduce_scatter36(acc, lane, v);
@@ -281,10 +320,9 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     }
   }
   if constexpr (WMODE == W_IRLS) {
-    // integer count, spread over kKeptSlots counters (a single address would
-    // serialise one atomic per wavefront); exact and order-free
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) nkept += __shfl_xor(nkept, s);
+    // integer count (wave-uniform), spread over kKeptSlots counters (a
+    // single address would serialise one atomic per wavefront); exact and
+    // order-free
     if (lane == 0 && nkept) atomicAdd(&kept_slots[(w % kKeptSlots) * 16], (unsigned long long)nkept);
   }
 }

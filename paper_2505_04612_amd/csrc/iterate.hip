@@ -8,10 +8,12 @@
 //   pair phase    one thread per image pair: E_n and W_n e_n in float64, the
 //                 pair's loss, and the adjoint back to dL/dR and dL/dt of its
 //                 two cameras (a 24-float record per pair);
-//   camera phase  one wavefront per camera: the records of the camera's pairs
-//                 are summed in a fixed order (lanes stride the camera's
-//                 incidence list, then a fixed tree), the Gram-Schmidt adjoint
-//                 gives dL/d(a1, a2), and lane 0 applies Adam.
+//   camera phase  one 16-lane row of a wavefront per camera (four cameras
+//                 per wavefront): the records of the camera's pairs are summed
+//                 in a fixed order (lanes stride the camera's incidence list,
+//                 then a fixed DPP tree inside the row), the Gram-Schmidt
+//                 adjoint gives dL/d(a1, a2), and lanes 0..8 of the row apply
+//                 Adam to one parameter each.
 // The float64 quadratic form matters: near a minimum e^T W e is many orders
 // of magnitude below |W| |e|^2, so float32 would cancel most of its digits.
 #include <hip/hip_cooperative_groups.h>
@@ -30,10 +32,9 @@ __device__ inline double load_w(const WT* p, int k) {
 // `rot` (optional) holds each camera's rotation from Gram-Schmidt of the
 // current parameters, so pairs need not repeat it.
 template <typename WT>
-__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot,
-                                           const int32_t* __restrict__ cams, const WT* __restrict__ W36,
-                                           int64_t n, double two_inv_Z, float* __restrict__ rec) {
-  const int ci = cams[2 * n], cj = cams[2 * n + 1];
+__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot, int ci,
+                                           int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
+                                           float* __restrict__ rec) {
   double a1[3], a2[3], ti[3], tj[3];
   double Ri[3][3], Rj[3][3], Rij[3][3], th[3], E[3][3];
   load_pose(params, ci, a1, a2, ti);
@@ -125,14 +126,17 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
 }
 
 // Pair phase over pairs [first, P) with stride `stride`; writes the records
-// and returns this thread's loss sum (float64, in pair order).
+// and returns this thread's loss sum (float64, in pair order).  The cameras
+// of the first pair come in registers (ci0, cj0), read once per solve.
 template <typename WT>
 __device__ inline double pair_phase(const float* params, const double* rot, const int32_t* cams, const WT* W36,
-                                    int64_t P, double two_inv_Z, float* contrib, int64_t first, int64_t stride) {
+                                    int64_t P, double two_inv_Z, float* contrib, int64_t first, int64_t stride,
+                                    int ci0, int cj0) {
   double sum = 0.0;
   for (int64_t n = first; n < P; n += stride) {
     float rec[24];
-    sum += pair_loss_adjoint(params, rot, cams, W36, n, two_inv_Z, rec);
+    const int ci = n == first ? ci0 : cams[2 * n], cj = n == first ? cj0 : cams[2 * n + 1];
+    sum += pair_loss_adjoint(params, rot, ci, cj, W36, n, two_inv_Z, rec);
     float4* dst = reinterpret_cast<float4*>(contrib + n * 24);
 #pragma unroll
     for (int k = 0; k < 6; ++k) dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
@@ -245,18 +249,86 @@ __device__ inline void gs_adjoint(const double acc[12], const double a1[3], cons
   }
 }
 
+// Row-wide total of the 12 per-lane sums over one 16-lane row, returned in
+// every lane of the row: the same DPP reduce-scatter as wave_sum12 without
+// the cross-row steps, then a gather inside the row.
+__device__ inline void row_sum12(double acc[12], int lane) {
+  double b6[6], b3[3], b2[2], b1[1];
+  rs_stage_d<12, 3>(*reinterpret_cast<double(*)[12]>(acc), b6, lane);
+  rs_stage_d<6, 2>(b6, b3, lane);
+  rs_stage_d<3, 1>(b3, b2, lane);
+  rs_stage_d<2, 0>(b2, b1, lane);
+  const double v = b1[0];
+  const int base = lane & ~15;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = __shfl(v, base + k + k / 3);
+}
+
+// Incidence list of one camera as one 16-lane row reads it: the list bounds
+// and this lane's first four entries (q = lo + l16 + 16 j; -1 past the end).
+// Static during a solve, so the fused loop reads it once.
+struct RowList {
+  int lo, hi, it[4];
+};
+
+__device__ inline RowList row_list(const int32_t* __restrict__ cam_ptr, const int32_t* __restrict__ cam_items, int c,
+                                   int l16) {
+  RowList L;
+  L.lo = cam_ptr[c];
+  L.hi = cam_ptr[c + 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) L.it[j] = L.lo + l16 + 16 * j < L.hi ? cam_items[L.lo + l16 + 16 * j] : -1;
+  return L;
+}
+
+// Summed records of one camera in every lane of its row.
+__device__ inline void row_camera_sums(const RowList& L, const int32_t* __restrict__ cam_items,
+                                       const float* __restrict__ contrib, int lane, double acc[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (L.it[j] >= 0) add_record(contrib, L.it[j], acc);
+  for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record(contrib, cam_items[q], acc);
+  row_sum12(acc, lane);
+}
+
+// Incidence list of one camera as one wavefront reads it: the list bounds
+// and the first two entries of this lane (q = lo + lane and lo + 64 + lane;
+// -1 past the end).  Static during a solve, so the fused loop reads it once.
+struct CamList {
+  int lo, hi, it0, it1;
+};
+
+__device__ inline CamList cam_list(const int32_t* __restrict__ cam_ptr, const int32_t* __restrict__ cam_items, int c,
+                                   int lane) {
+  CamList L;
+  L.lo = cam_ptr[c];
+  L.hi = cam_ptr[c + 1];
+  L.it0 = L.lo + lane < L.hi ? cam_items[L.lo + lane] : -1;
+  L.it1 = L.lo + 64 + lane < L.hi ? cam_items[L.lo + 64 + lane] : -1;
+  return L;
+}
+
+// Summed records of one camera over its incidence list, in every lane
+// (lanes stride the list in pair order; wave_sum12 combines them).
+__device__ inline void camera_sums(const CamList& L, const int32_t* __restrict__ cam_items,
+                                   const float* __restrict__ contrib, int lane, double acc[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  if (L.it0 >= 0) add_record(contrib, L.it0, acc);
+  if (L.it1 >= 0) add_record(contrib, L.it1, acc);
+  for (int q = L.lo + 128 + lane; q < L.hi; q += 64) add_record(contrib, cam_items[q], acc);
+  wave_sum12(acc, lane);
+}
+
 // Gradient of camera c, computed by a whole wavefront; every lane returns
-// dL/dtheta_c [9] (float64).  Lanes stride the camera's incidence list (pair
-// order) and the 12 sums are combined by wave_sum12.
+// dL/dtheta_c [9] (float64).
 __device__ inline void camera_gradient(const float* __restrict__ params, const int32_t* __restrict__ cam_ptr,
                                        const int32_t* __restrict__ cam_items, const float* __restrict__ contrib,
                                        int c, int lane, double grad[9]) {
   double acc[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-  const int lo = cam_ptr[c], hi = cam_ptr[c + 1];
-  for (int q = lo + lane; q < hi; q += 64) add_record(contrib, cam_items[q], acc);
-  wave_sum12(acc, lane);
+  camera_sums(cam_list(cam_ptr, cam_items, c, lane), cam_items, contrib, lane, acc);
   double a1[3], a2[3], t[3];
   load_pose(params, c, a1, a2, t);
   gs_adjoint(acc, a1, a2, grad);
@@ -280,7 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_phase(const float* __restrict__
   __shared__ double lds[kBlock / 64];
   const double iz = Z_dev ? 1.0 / (double)(*Z_dev > 0 ? *Z_dev : 1) : inv_Z;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double v = pair_phase(params, (const double*)nullptr, cams, W36, P, 2.0 * iz, contrib, n, P > 0 ? P : 1);
+  const int ci0 = n < P ? cams[2 * n] : 0, cj0 = n < P ? cams[2 * n + 1] : 0;
+  const double v =
+      pair_phase(params, (const double*)nullptr, cams, W36, P, 2.0 * iz, contrib, n, P > 0 ? P : 1, ci0, cj0);
   const double t = block_sum(v, lds);
   if (threadIdx.x == 0) loss_part[blockIdx.x] = t;
 }
@@ -418,11 +492,19 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
   const WT* W36 = reinterpret_cast<const WT*>(a.W36);
+  // static data of this thread's first pair and this wavefront's first
+  // camera, read once instead of once per iteration
+  const int ci0 = gtid < a.P ? a.cams[2 * gtid] : 0, cj0 = gtid < a.P ? a.cams[2 * gtid + 1] : 0;
+  // cameras 4 gwave + row, then strided by 4 nwaves
+  const int row = lane >> 4, l16 = lane & 15, base = lane & ~15;
+  const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
+  RowList L0 = {0, 0, {-1, -1, -1, -1}};
+  if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
   for (int k = 0; k < a.K; ++k) {
     // iteration 0 runs Gram-Schmidt per pair; later iterations read the
     // rotations the camera phase stored with the updated parameters
     const double v = pair_phase(a.params, k > 0 ? a.rot : nullptr, a.cams, W36, a.P, 2.0 * iz, a.contrib, gtid,
-                                gsize);
+                                gsize, ci0, cj0);
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
     grid.sync();
@@ -434,32 +516,56 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
     const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
     const double step = (double)(a.adam_step0 + k + 1);
     const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
-    for (int64_t c = gwave; c < a.N; c += nwaves) {
-      double g[9];
-      camera_gradient(a.params, a.cam_ptr, a.cam_items, a.contrib, (int)c, lane, g);
-      // lanes 0..8 update one parameter each
+    // the loop bound is uniform over the wavefront (rows past N idle), so
+    // the row exchanges below always run with every lane present
+    for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
+      const int64_t c = c0 + row;
+      const bool live = c < a.N;
+      // parameters and moments first (they do not depend on the records),
+      // so their loads overlap the record loads
+      float p0 = 0.0f, mq = 0.0f, vq = 0.0f;
+      if (live && l16 < 9) {
+        p0 = a.params[c * 9 + l16];
+        mq = a.m[c * 9 + l16];
+        vq = a.v[c * 9 + l16];
+      }
+      double acc[12];
+      const RowList L = c0 == 4 * gwave ? L0 : (live ? row_list(a.cam_ptr, a.cam_items, (int)c, l16)
+                                                     : RowList{0, 0, {-1, -1, -1, -1}});
+      row_camera_sums(L, a.cam_items, a.contrib, lane, acc);
+      double a1[3], a2[3], g[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        a1[j] = (double)__shfl(p0, base + j);
+        a2[j] = (double)__shfl(p0, base + 3 + j);
+      }
+      // a row without a camera has zero sums and zero parameters: keep its
+      // Gram-Schmidt away from 0/0 (its results are not stored)
+      if (!live) a1[0] = a2[1] = 1.0;
+      gs_adjoint(acc, a1, a2, g);
+      // lanes 0..8 of the row update one parameter each
       float pq = 0.0f;
-      if (lane < 9) {
-        const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
-        float mq = a.m[c * 9 + lane], vq = a.v[c * 9 + lane];
-        pq = adam_update(a.params[c * 9 + lane], (float)pick9(g, lane), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
-        a.params[c * 9 + lane] = pq;
-        a.m[c * 9 + lane] = mq;
-        a.v[c * 9 + lane] = vq;
+      if (live && l16 < 9) {
+        const double lr = (l16 < 6 ? a.lr_rot : a.lr_t) * frac;
+        pq = adam_update(p0, (float)pick9(g, l16), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+        a.params[c * 9 + l16] = pq;
+        a.m[c * 9 + l16] = mq;
+        a.v[c * 9 + l16] = vq;
       }
       // rotation of the updated parameters for the next pair phase
       double n1[3], n2[3], R[3][3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        n1[j] = (double)__shfl(pq, j);
-        n2[j] = (double)__shfl(pq, 3 + j);
+        n1[j] = (double)__shfl(pq, base + j);
+        n2[j] = (double)__shfl(pq, base + 3 + j);
       }
+      if (!live) n1[0] = n2[1] = 1.0;
       gs_matrix(gs_forward(n1, n2), R);
-      if (lane < 9) {
+      if (live && l16 < 9) {
         double rv = R[0][0];
 #pragma unroll
-        for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
-        a.rot[c * 9 + lane] = rv;
+        for (int j = 1; j < 9; ++j) rv = (l16 == j) ? R[j / 3][j % 3] : rv;
+        a.rot[c * 9 + l16] = rv;
       }
     }
     grid.sync();

@@ -71,6 +71,61 @@ def test_gram_ragged_parity_and_determinism(fm, ctx, dtype):
     assert np.all(W64.cpu().numpy()[np.diff(offs) == 0] == 0.0)
 
 
+# sizes around the small-pair / big-pair boundary (256), the 16-lane row
+# (16, 17) and the chunk (1024): groups of four equal row counts (all rows
+# but the last full), single-match pairs, and pairs spanning 2-4 chunks
+_EDGE_SIZES = (16, 16, 16, 16, 17, 17, 17, 17, 255, 256, 256, 256, 256, 257, 33, 48, 1, 1, 1, 1,
+               2047, 2048, 3073, 240, 241, 242, 243, 0, 1024, 1025)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_gram_edge_sizes_parity(fm, ctx, dtype):
+    pairs, offs, uv, N = _ragged_scene(seed=11, sizes=_EDGE_SIZES, ncams=7)
+    s = fm.Scene.from_numpy(ctx, N, pairs, offs, uv, dtype)
+    x = stored(uv, dtype)
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0.0, 3.0, int(offs[-1])).astype(np.float32)
+    for weights in (None, torch.from_numpy(w).to(ctx.device)):
+        W64, W32 = fm.build_pair_grams(s, weights)
+        W64b, _ = fm.build_pair_grams(s, weights)
+        torch.cuda.synchronize()
+        assert torch.equal(W64, W64b)
+        om = None if weights is None else w.astype(np.float64)
+        ref = ea.pair_grams(x, offs, om)
+        absg = ea.pair_grams(np.abs(x), offs, om)
+        rel, el = gram_errors(expand36(W64.cpu().numpy()), ref, absg)
+        assert rel <= 1e-5 and el <= 1e-5, (dtype, weights is None, rel, el)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_reweight_build_edge_sizes_parity(fm, ctx, dtype):
+    """Fused IRLS reweight + Gram on the edge sizes: kept count exact, Grams
+    of the oracle's weights within the Gram tolerance."""
+    pairs, offs, uv, N = _ragged_scene(seed=12, sizes=_EDGE_SIZES, ncams=7)
+    s = fm.Scene.from_numpy(ctx, N, pairs, offs, uv, dtype)
+    rng = np.random.default_rng(9)
+    R = np.stack([ea.rot_from_6d(rng.normal(size=3), rng.normal(size=3)) for _ in range(N)])
+    t = rng.normal(size=(N, 3))
+    theta = np.concatenate([R[:, :, 0], R[:, :, 1], t], axis=1).astype(np.float32)
+    delta, tau = np.float32(1e-4), np.float32(0.5)
+    th = torch.from_numpy(theta).to(ctx.device)
+    W64, W32, Z = fm.reweight_build(s, th, float(delta), float(tau))
+    x = stored(uv, dtype)
+    r = ea.residuals(theta.astype(np.float64), pairs, offs, x)
+    om = ea.irls_weights(r, float(delta), float(tau))
+    assert 0 < int(np.count_nonzero(om)) < len(om)
+    assert int(Z.item()) == int(np.count_nonzero(om))
+    # the unfused reweight writes the same weights and residuals
+    w_g, r_g, kept = fm.reweight(s, th, float(delta), float(tau), residuals=True)
+    assert int(kept.item()) == int(Z.item())
+    assert np.allclose(r_g.cpu().numpy(), r, rtol=1e-6, atol=1e-12 + 1e-7 * np.abs(r).max())
+    assert np.allclose(w_g.cpu().numpy(), om, rtol=1e-6, atol=0)
+    ref = ea.pair_grams(x, offs, om)
+    absg = ea.pair_grams(np.abs(x), offs, om)
+    rel, el = gram_errors(expand36(W64.cpu().numpy()), ref, absg)
+    assert rel <= 1e-5 and el <= 1e-5, (dtype, rel, el)
+
+
 @pytest.mark.parametrize("name,dtype", [("tiny", torch.float64), ("medium", torch.float32),
                                         ("medium", torch.bfloat16)])
 def test_gram_scene_parity(fm, ctx, name, dtype):
