@@ -193,6 +193,7 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"[bench] {args.steps} timed steps in {wall:.3f}s")
+    bar_fail = s.barrier_failures()
     gram_ms, n_gram = ctx.profile_read(_lib.K_GRAM)
     ess_ms, n_ess = ctx.profile_read(_lib.K_ESSENTIALS)
     fin_ms, n_fin = ctx.profile_read(_lib.K_FINALIZE)
@@ -202,7 +203,7 @@ def main() -> int:
     # pose check against the stored FP64 oracle solve
     from oracle import ea
     rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), np.array(golden["theta"]), sc.pairs)
-    passed = bool(rot.max() <= 0.1 and tra.max() <= 0.5)
+    passed = bool(rot.max() <= 0.1 and tra.max() <= 0.5 and bar_fail == 0)
 
     M, P = sc.num_matches, sc.num_pairs
     gram_s = gram_ms / 1e3 / max(n_gram, 1)
@@ -230,7 +231,7 @@ def main() -> int:
         "solve_kernel_us_per_iter": solve_ms * 1e3 / iters,
         "pose_check": {"passed": passed, "rot_max_deg": float(rot.max()), "rot_median_deg": float(np.median(rot)),
                        "t_max_deg": float(tra.max()), "t_median_deg": float(np.median(tra)),
-                       "kept_gpu": int(Z.item()), "kept_oracle": golden["kept"]},
+                       "kept_gpu": int(Z.item()), "kept_oracle": golden["kept"], "barrier_failures": bar_fail},
         "roofline": {"bound": "hbm", "kernel": "k_gram_pass (fused IRLS reweight + Gram, float32 coords)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,

@@ -98,8 +98,9 @@ fm_status fm_scene_create(fm_ctx* ctx, int64_t num_pairs, int64_t num_matches, i
                           const int64_t* pair_offsets, const int32_t* pair_cams,
                           const void* uv, fm_dtype dtype, fm_stream stream, fm_scene** out);
 void fm_scene_destroy(fm_scene* scene);
-/* Number of work items (pair chunks of up to 1024 matches) the Gram build
- * launches; host value. */
+/* Number of wavefronts the Gram pass launches (one per chunk of up to 1024
+ * matches of a pair with more than 256 matches, plus one per group of four
+ * smaller pairs); host value. */
 int64_t fm_scene_work_items(const fm_scene* scene);
 
 /* ------------------------------------------------------------------ a1: Gram */
@@ -169,8 +170,9 @@ typedef struct {
   int64_t lr_step0;      /* global step index of this call's first iteration  */
   int64_t lr_total_steps;/* length of the whole schedule (> 0)                */
   int64_t adam_step0;    /* Adam steps already taken on m, v (0 after a reset) */
-  int32_t blocks;        /* workgroups of the persistent kernel (0 = automatic;
-                            capped at the co-resident limit)                  */
+  int32_t blocks;        /* workgroups (512 threads each) of the persistent
+                            kernel (0 = automatic; capped at the co-resident
+                            limit)                                            */
 } fm_adam_cfg;
 
 /* K iterations of {loss + gradient (as fm_epipolar_loss_grad), Adam update of
@@ -183,6 +185,13 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
                             float* params, float* m, float* v, int32_t K, const fm_adam_cfg* cfg,
                             double inv_Z, const int64_t* Z_dev, double* loss_trace,
                             fm_stream stream);
+
+/* Failed grid barriers of fm_epipolar_solve launches on this scene since the
+ * last call (host value in *failures), then cleared.  A barrier wait is
+ * bounded (about a second); if it expires, the launch stops at once and its
+ * results are invalid.  Synchronises the device.  Not expected to be nonzero:
+ * the cooperative launch makes every workgroup resident. */
+fm_status fm_solve_barrier_failures(fm_ctx* ctx, fm_scene* scene, int64_t* failures);
 
 /* ------------------------------------------------------------------ a9: learned weights */
 

@@ -22,7 +22,7 @@ EXPORTS = [
     "fm_create", "fm_destroy", "fm_last_error", "fm_version",
     "fm_scene_create", "fm_scene_destroy", "fm_scene_work_items",
     "fm_build_pair_grams", "fm_reweight", "fm_reweight_build",
-    "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve",
+    "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve", "fm_solve_barrier_failures",
     "fm_profile_enable", "fm_profile_read",
     "fm_match_features", "fm_mlp_forward", "fm_mlp_backward",
 ]
@@ -73,6 +73,7 @@ _SIGNATURES = {
     "fm_epipolar_loss_grad": (_S, [_P, _P, _P, _S, _P, _D, _P, _P, _P, _P]),
     "fm_adam_step": (_S, [_P, _I64, _P, _P, _P, _P, _I64, _P, _S, _F, _F, _F, _P]),
     "fm_epipolar_solve": (_S, [_P, _P, _P, _S, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _D, _P, _P, _P]),
+    "fm_solve_barrier_failures": (_S, [_P, _P, ctypes.POINTER(_I64)]),
     "fm_profile_enable": (_S, [_P, _S]),
     "fm_match_features": (_S, [_P, _P, _P, _F, _P, _P]),
     "fm_mlp_forward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _F, _P, _P, _P]),

@@ -141,6 +141,13 @@ class Scene:
     def work_items(self) -> int:
         return int(self.ctx.lib.fm_scene_work_items(self.handle))
 
+    def barrier_failures(self) -> int:
+        """Failed grid barriers of the fused solve on this scene since the last
+        call (synchronises the device); 0 unless a launch was invalid."""
+        n = ctypes.c_int64(0)
+        check(self.ctx.handle, self.ctx.lib.fm_solve_barrier_failures(self.ctx.handle, self.handle, ctypes.byref(n)))
+        return int(n.value)
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             self.ctx.lib.fm_scene_destroy(self.handle)

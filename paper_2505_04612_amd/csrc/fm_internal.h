@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "fastmap_hip.h"
 
 // Matches per Gram work item: one wavefront of 64 lanes, 16 matches per lane.
@@ -19,6 +21,9 @@ constexpr int kSmall = 16 * kPerLane;
 constexpr int kGramWaves = 4;
 // Threads per block of the per-pair and per-camera kernels.
 constexpr int kBlock = 256;
+// Threads per workgroup of the persistent solve (eight wavefronts: fewer,
+// larger workgroups make its grid barriers cheaper).
+constexpr int kSolveBlock = 512;
 // Integer counters the IRLS pass spreads its kept-match counts over (one
 // 128-byte line each, so concurrent atomics rarely meet on one address).
 constexpr int kKeptSlots = 256;
@@ -43,13 +48,17 @@ struct fm_ctx {
   size_t ws_bytes = 0;
 };
 
-// Bracket a kernel launch with events on its stream when profiling is on.
+// Timing of one kernel launch when profiling is on.  By default the two
+// events bracket the launch on its stream; with `at_dispatch` the caller
+// hands a and b to hipExtLaunchKernelGGL, which records them at the start
+// and end of the kernel itself (no dispatch latency in the interval).
 struct fm_timed {
   fm_ctx* ctx;
   int kernel;
   hipStream_t st;
+  bool at_dispatch;
   hipEvent_t a = nullptr, b = nullptr;
-  fm_timed(fm_ctx* c, int k, hipStream_t s);
+  fm_timed(fm_ctx* c, int k, hipStream_t s, bool dispatch = false);
   ~fm_timed();
 };
 
@@ -85,6 +94,8 @@ struct fm_scene {
   double* loss_part = nullptr;    // [loss_part_cap]
   double* rot = nullptr;          // [N, 9] rotations of the current poses (fused solve)
   int64_t loss_part_cap = 0;
+  unsigned* bar = nullptr;        // [128] solve grid barrier, one 128-B line each: arrival count, generation,
+                                  // failure flag of the running launch, failure total since the last query
   int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
 };
 

@@ -410,19 +410,22 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
   const int64_t items = s->n_big + s->n_groups;
   if (items == 0) return FM_OK;
   const dim3 grid(grid_for(items, kGramWaves)), block(kGramWaves * kLanes);
-  fm_timed timer(s->ctx, FM_K_GRAM, st);
+  fm_timed timer(s->ctx, FM_K_GRAM, st, true);
 #define FM_GRAM_ARGS                                                                                          \
   s->uv, s->offsets, s->big_pair, s->big_chunk, s->n_big, s->groups, s->n_groups, weights, s->ess, delta, tau, \
       s->partials, W64, W32, w_out, r_out, s->kept_slots
   switch (s->dtype) {
     case FM_F32:
-      hipLaunchKernelGGL((k_gram_pass<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, FM_GRAM_ARGS);
+      hipExtLaunchKernelGGL((k_gram_pass<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, timer.a, timer.b, 0,
+                            FM_GRAM_ARGS);
       break;
     case FM_BF16:
-      hipLaunchKernelGGL((k_gram_pass<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, FM_GRAM_ARGS);
+      hipExtLaunchKernelGGL((k_gram_pass<FM_BF16, WMODE, BUILD, WRITE>), grid, block, 0, st, timer.a, timer.b, 0,
+                            FM_GRAM_ARGS);
       break;
     default:
-      hipLaunchKernelGGL((k_gram_pass<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, FM_GRAM_ARGS);
+      hipExtLaunchKernelGGL((k_gram_pass<FM_F64, WMODE, BUILD, WRITE>), grid, block, 0, st, timer.a, timer.b, 0,
+                            FM_GRAM_ARGS);
       break;
   }
 #undef FM_GRAM_ARGS
@@ -432,19 +435,19 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
 
 static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* kept, hipStream_t st) {
   if (s->n_multi + s->n_empty == 0 && !kept) return FM_OK;
-  fm_timed timer(s->ctx, FM_K_FINALIZE, st);
+  fm_timed timer(s->ctx, FM_K_FINALIZE, st, true);
   const int64_t nthreads = (s->n_multi + s->n_empty) * 36 > 0 ? (s->n_multi + s->n_empty) * 36 : 1;
-  hipLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, s->partials,
-                     s->offsets, s->multi, s->multi_first, s->n_multi, s->multi + s->n_multi, s->n_empty, W64, W32,
-                     s->kept_slots, kept);
+  hipExtLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, timer.a, timer.b, 0,
+                        s->partials, s->offsets, s->multi, s->multi_first, s->n_multi, s->multi + s->n_multi,
+                        s->n_empty, W64, W32, s->kept_slots, kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
 
 static fm_status launch_essentials(fm_scene* s, const float* params, hipStream_t st) {
-  fm_timed timer(s->ctx, FM_K_ESSENTIALS, st);
-  hipLaunchKernelGGL(k_pair_essentials, dim3(grid_for(s->P > 0 ? s->P : 1, kBlock)), dim3(kBlock), 0, st, params,
-                     s->pair_cams, s->P, s->ess);
+  fm_timed timer(s->ctx, FM_K_ESSENTIALS, st, true);
+  hipExtLaunchKernelGGL(k_pair_essentials, dim3(grid_for(s->P > 0 ? s->P : 1, kBlock)), dim3(kBlock), 0, st, timer.a,
+                        timer.b, 0, params, (const int32_t*)s->pair_cams, s->P, s->ess);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }

@@ -16,11 +16,7 @@
 //                 Adam to one parameter each.
 // The float64 quadratic form matters: near a minimum e^T W e is many orders
 // of magnitude below |W| |e|^2, so float32 would cancel most of its digits.
-#include <hip/hip_cooperative_groups.h>
-
 #include "fm_internal.h"
-
-namespace cg = cooperative_groups;
 
 template <typename WT>
 __device__ inline double load_w(const WT* p, int k) {
@@ -460,6 +456,62 @@ extern "C" fm_status fm_adam_step(fm_ctx* ctx, int64_t n, float* p, const float*
 
 // ------------------------------------------------------------------ fused persistent solve
 
+// Grid barrier of the persistent solve.  Thread 0 of each workgroup makes
+// the workgroup's writes visible (agent-scope release), counts itself in,
+// and waits for the generation word to move; the last to arrive acquires the
+// others' writes, re-arms the counter and moves the generation.  All atomics
+// are relaxed and agent-scoped; the fences carry the ordering.  The wait is
+// bounded: if it expires (the workgroups were not all resident), the
+// launch's failure flag and the scene's failure total are raised, every later
+// barrier of the launch returns at once and the host reads the total with
+// fm_solve_barrier_failures.
+constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
+
+__device__ inline void grid_barrier(unsigned* __restrict__ bar) {
+  unsigned* count = bar;
+  unsigned* gen = bar + 32;
+  unsigned* fail = bar + 64;
+  __syncthreads();
+  if (threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      bool moved = false;
+      for (unsigned outer = 0; outer < kBarSpinOuter && !moved; ++outer) {
+#pragma unroll 1
+        for (int i = 0; i < 256; ++i) {
+          if (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) {
+            moved = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (!moved && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      }
+      if (!moved) {
+        __hip_atomic_fetch_add(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar + 96, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Re-arms the barrier before a launch: arrival count and the launch's
+// failure flag (a launch that ended on a failed barrier leaves them set).
+__global__ void k_bar_reset(unsigned* __restrict__ bar) {
+  if (threadIdx.x == 0) {
+    bar[0] = 0u;
+    bar[64] = 0u;
+  }
+}
+
 struct SolveArgs {
   float* params;
   float* m;
@@ -472,6 +524,7 @@ struct SolveArgs {
   double* loss_part;
   double* rot;
   double* loss_trace;
+  unsigned* bar;
   const int64_t* Z_dev;
   double inv_Z;
   int64_t P;
@@ -483,9 +536,8 @@ struct SolveArgs {
 };
 
 template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
-  __shared__ double lds[kBlock / 64];
-  cg::grid_group grid = cg::this_grid();
+__global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
+  __shared__ double lds[kSolveBlock / 64];
   const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -507,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
                                 gsize, ci0, cj0);
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
-    grid.sync();
+    grid_barrier(a.bar);
     if (a.loss_trace && gtid == 0) {
       double s = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) s += a.loss_part[b];
@@ -568,14 +620,15 @@ __global__ __launch_bounds__(kBlock) void k_solve(SolveArgs a) {
         a.rot[c * 9 + l16] = rv;
       }
     }
-    grid.sync();
+    grid_barrier(a.bar);
   }
 }
 
 int fm_solve_coop_blocks(fm_ctx* ctx) {
   int per_cu64 = 0, per_cu32 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_solve<double>, kBlock, 0) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, k_solve<float>, kBlock, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_solve<double>, kSolveBlock, 0) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, k_solve<float>, kSolveBlock, 0) != hipSuccess) return 0;
   const int per_cu = per_cu64 < per_cu32 ? per_cu64 : per_cu32;
   return per_cu * ctx->num_cu;
 }
@@ -597,16 +650,15 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   if (!Z_dev && !(inv_Z >= 0.0)) return fm_fail(ctx, FM_EINVAL, "fm_epipolar_solve: inv_Z must be >= 0");
   if (K == 0) return FM_OK;
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  // enough threads for one pair each or one wavefront per camera, within the
-  // co-resident limit of a cooperative launch
-  // about one pair per thread or one wavefront per camera, capped at 32
-  // workgroups below 32k pairs (measured: more workgroups make the two grid
-  // barriers per iteration dearer than the work they share) and at the
-  // co-resident limit
-  int64_t want = grid_for(s->P, kBlock);
-  const int64_t want_c = grid_for((int64_t)s->N * 64, kBlock);
+  // about one pair per thread or one 16-lane row per camera, capped at 16
+  // workgroups below 32k pairs and at 192 above (each workgroup adds about
+  // 0.02 us to each of the two grid barriers per iteration, measured, so
+  // past these sizes a second round of pairs per thread is cheaper than more
+  // workgroups), and at the co-resident limit
+  int64_t want = grid_for(s->P, kSolveBlock);
+  const int64_t want_c = grid_for((int64_t)s->N * 16, kSolveBlock);
   if (want_c > want) want = want_c;
-  if (s->P < 32768 && want > 32) want = 32;
+  if (want > (s->P < 32768 ? 16 : 192)) want = s->P < 32768 ? 16 : 192;
   if (cfg->blocks > 0) want = cfg->blocks;
   if (want < 1) want = 1;
   if (want > s->coop_blocks) want = s->coop_blocks;
@@ -615,17 +667,32 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   a.params = params; a.m = m; a.v = v;
   a.cams = s->pair_cams; a.W36 = W36; a.cam_ptr = s->cam_ptr; a.cam_items = s->cam_items;
   a.contrib = s->contrib; a.loss_part = s->loss_part; a.rot = s->rot; a.loss_trace = loss_trace; a.Z_dev = Z_dev;
+  a.bar = s->bar;
   a.inv_Z = inv_Z; a.P = s->P; a.N = s->N; a.K = K;
   a.lr_rot = cfg->lr_rot; a.lr_t = cfg->lr_t; a.log_frac = log((double)cfg->lr_final_frac);
   a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;
   a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
   void* args[] = {&a};
+  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, s->bar);
+  FM_CHECK_LAUNCH(ctx);
   fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
-  hipError_t e = wdt == FM_F64
-                     ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want), dim3(kBlock),
-                                                  args, 0, (hipStream_t)stream)
-                     : hipLaunchCooperativeKernel((const void*)k_solve<float>, dim3((unsigned)want), dim3(kBlock),
-                                                  args, 0, (hipStream_t)stream);
+  hipError_t e = wdt == FM_F64 ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want),
+                                                           dim3(kSolveBlock), args, 0, (hipStream_t)stream)
+                               : hipLaunchCooperativeKernel((const void*)k_solve<float>, dim3((unsigned)want),
+                                                           dim3(kSolveBlock), args, 0, (hipStream_t)stream);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+  return FM_OK;
+}
+
+extern "C" fm_status fm_solve_barrier_failures(fm_ctx* ctx, fm_scene* s, int64_t* failures) {
+  if (!ctx) return FM_EINVAL;
+  if (!s || !failures) return fm_fail(ctx, FM_EINVAL, "fm_solve_barrier_failures: NULL argument");
+  if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "fm_solve_barrier_failures: scene belongs to another context");
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  FM_HIP_TRY(ctx, hipDeviceSynchronize());
+  unsigned f = 0;
+  FM_HIP_TRY(ctx, hipMemcpy(&f, s->bar + 96, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (f) FM_HIP_TRY(ctx, hipMemset(s->bar + 96, 0, sizeof(unsigned)));
+  *failures = (int64_t)f;
   return FM_OK;
 }

@@ -49,17 +49,17 @@ static hipEvent_t pool_get(fm_ctx* ctx) {
   return e;
 }
 
-fm_timed::fm_timed(fm_ctx* c, int k, hipStream_t s) : ctx(c), kernel(k), st(s) {
+fm_timed::fm_timed(fm_ctx* c, int k, hipStream_t s, bool dispatch) : ctx(c), kernel(k), st(s), at_dispatch(dispatch) {
   if (ctx && ctx->profile) {
     a = pool_get(ctx);
     b = pool_get(ctx);
-    if (a) (void)hipEventRecord(a, st);
+    if (a && b && !at_dispatch) (void)hipEventRecord(a, st);
   }
 }
 
 fm_timed::~fm_timed() {
   if (a && b) {
-    (void)hipEventRecord(b, st);
+    if (!at_dispatch) (void)hipEventRecord(b, st);
     ctx->timings.push_back({kernel, a, b});
   } else {
     if (a) ctx->event_pool.push_back(a);
@@ -239,6 +239,7 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->contrib);
   (void)hipFree(s->loss_part);
   (void)hipFree(s->rot);
+  (void)hipFree(s->bar);
   delete s;
 }
 
@@ -412,13 +413,16 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
     scene_free(s);
     return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative solve kernel");
   }
-  s->loss_part_cap = (int64_t)grid_for(P, kBlock);
+  s->loss_part_cap = (int64_t)grid_for(P, kBlock);   // also covers k_pair_phase's blocks
   if (s->loss_part_cap < s->coop_blocks) s->loss_part_cap = s->coop_blocks;
   SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_big > 0 ? s->n_big : 1)));
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
   SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * (N > 0 ? N : 1)));
+  SCENE_TRY(hipMalloc(&s->bar, sizeof(unsigned) * 128));
+  SCENE_TRY(hipMemsetAsync(s->bar, 0, sizeof(unsigned) * 128, st));
+  SCENE_TRY(hipStreamSynchronize(st));
   *out = s;
   return FM_OK;
 }

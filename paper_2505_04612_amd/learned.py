@@ -96,9 +96,10 @@ class TrainCfg:
     seed: int = 0
 
 
-def train_mlp(ctx: api.Context, feats: torch.Tensor, target: torch.Tensor, cfg: TrainCfg):
+def train_mlp(ctx: api.Context, feats: torch.Tensor, target: torch.Tensor, cfg: TrainCfg, progress=None):
     """Minimise sum (mlp(f) - target)^2 over minibatches with the library's
-    forward, backward and Adam kernels.  Returns (weights, loss history)."""
+    forward, backward and Adam kernels.  Returns (weights, loss history);
+    `progress(step, loss)` is called with each history entry."""
     dev = ctx.device
     mean = feats.mean(dim=0)
     std = feats.std(dim=0).clamp_min(1e-6)
@@ -126,6 +127,8 @@ def train_mlp(ctx: api.Context, feats: torch.Tensor, target: torch.Tensor, cfg: 
         api.adam_step(ctx, w.flat, g.flat, m, v, step, lr, 0.9, 0.999, 1e-8)
         if step % 100 == 0 or step == 1:
             hist.append((step, float(torch.mean((out - tb) ** 2).item())))
+            if progress is not None:
+                progress(*hist[-1])
     return w, hist
 
 
@@ -189,9 +192,13 @@ def main(argv=None) -> int:
     t0 = time.time()
     train_seeds = list(range(100, 100 + args.train))
     test_seeds = list(range(200, 200 + args.test))
+    scenes = []
     with concurrent.futures.ProcessPoolExecutor(max_workers=args.workers) as ex:
-        scenes = list(ex.map(_gen, train_seeds + test_seeds, [args.cams] * (args.train + args.test),
-                             [args.points] * (args.train + args.test)))
+        for sc in ex.map(_gen, train_seeds + test_seeds, [args.cams] * (args.train + args.test),
+                         [args.points] * (args.train + args.test)):
+            scenes.append(sc)
+            print(f"[learned] scene {len(scenes)}/{args.train + args.test} (seed {sc['seed']}) "
+                  f"{time.time() - t0:.0f}s", flush=True)
     print(f"[learned] generated {len(scenes)} scenes in {time.time() - t0:.0f}s "
           f"(e.g. {scenes[0]['stats']})", flush=True)
     ctx = api.default_context()
@@ -213,7 +220,9 @@ def main(argv=None) -> int:
     tgt = torch.cat(tgt_all).contiguous()
     print(f"[learned] targets from {args.train} IRLS solves: {feats.shape[0]} samples "
           f"({time.time() - t0:.0f}s)", flush=True)
-    w, hist = train_mlp(ctx, feats, tgt, TrainCfg(steps=args.steps))
+    w, hist = train_mlp(ctx, feats, tgt, TrainCfg(steps=args.steps),
+                        progress=lambda k, l: print(f"[learned] step {k} loss {l:.4g}", flush=True)
+                        if k % 500 == 0 else None)
     print(f"[learned] trained: loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g} ({time.time() - t0:.0f}s)", flush=True)
     ls = LearnedSchedule(iters=args.learned_iters)
     rows = []

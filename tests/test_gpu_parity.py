@@ -71,11 +71,12 @@ def test_gram_ragged_parity_and_determinism(fm, ctx, dtype):
     assert np.all(W64.cpu().numpy()[np.diff(offs) == 0] == 0.0)
 
 
-# sizes around the small-pair / big-pair boundary (256), the 16-lane row
-# (16, 17) and the chunk (1024): groups of four equal row counts (all rows
-# but the last full), single-match pairs, and pairs spanning 2-4 chunks
+# sizes around the small-pair / big-pair boundary (256; 128 for float64
+# coordinates), the 16-lane row (16, 17) and the chunk (1024; 512 for
+# float64): groups of four equal row counts (all rows but the last full),
+# groups with empty slots, single-match pairs, and pairs spanning 2-4 chunks
 _EDGE_SIZES = (16, 16, 16, 16, 17, 17, 17, 17, 255, 256, 256, 256, 256, 257, 33, 48, 1, 1, 1, 1,
-               2047, 2048, 3073, 240, 241, 242, 243, 0, 1024, 1025)
+               2047, 2048, 3073, 240, 241, 242, 243, 0, 1024, 1025, 128, 129, 511, 512, 513, 97)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
@@ -287,9 +288,33 @@ def test_fused_solve_matches_oracle_steps(fm, ctx):
         L, g = ea.loss_grad(tr, sc.pairs, W, inv_Z)
         losses.append(L)
         tr, mr, vr = ea.adam_step(tr, g, mr, vr, k + 1, ea.lr_at(sched, k), sched.beta1, sched.beta2, sched.eps)
+    assert s.barrier_failures() == 0
     assert np.allclose(trace.cpu().numpy(), losses, rtol=1e-5)
     rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), tr, sc.pairs)
     assert rot.max() < 1e-3 and tra.max() < 1e-2
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_fused_solve_grid_invariance(fm, ctx, name):
+    """The fused loop's camera sums run in a fixed order, so the parameters
+    after K iterations are bit-identical for any number of workgroups (1 to
+    beyond the automatic choice): every grid barrier must publish every
+    workgroup's records and poses before the next phase reads them."""
+    sc = scene(name)
+    s = _scene_on_gpu(fm, ctx, sc, torch.float64 if name == "tiny" else torch.float32)
+    W64, _ = fm.build_pair_grams(s)
+    th = torch.from_numpy(_theta(sc)).to(ctx.device)
+    results = []
+    for blocks in (1, 2, 5, 16, 37):
+        p = th.clone()
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        fm.epipolar_solve(s, W64, p, m, v, 30, 3e-3, 1e-2, 1e-3, 0, 30, 0, inv_Z=1.0 / sc.num_matches,
+                          blocks=blocks)
+        results.append((blocks, p, m, v))
+    assert s.barrier_failures() == 0
+    for blocks, p, m, v in results[1:]:
+        assert torch.equal(p, results[0][1]) and torch.equal(m, results[0][2]) and torch.equal(v, results[0][3]), blocks
 
 
 def _oracle_sched(s):
@@ -307,6 +332,7 @@ def test_full_solve_pose_parity(fm, ctx, name, dtype, iters):
     th0 = _theta(sc)
     sched = solver.Schedule(iters=iters, round_len=100)
     p, losses, Z = solver.solve(s, torch.from_numpy(th0).to(ctx.device), sched)
+    assert s.barrier_failures() == 0
     th_o, tr_o, w_o = ea.solve(th0.astype(np.float64), sc.pairs, sc.offsets, stored(sc.uv, dtype),
                                _oracle_sched(sched))
     rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), th_o, sc.pairs)
