@@ -14,8 +14,11 @@ Reported (one JSON line):
                   or 0.5 deg translation direction;
   iters_per_s     Adam iterations per second of device time of the fused
                   solve kernel;
-  roofline        of the Gram pass (HBM-bound: 16 B per match read + 72 B per
-                  pair (E_n) per launch);
+  roofline        of the Gram pass (HBM-bound: 16 B per match read, 72 B per
+                  pair (E_n) read and 288 B per pair (FP64 Gram) written per
+                  launch); `traffic` is the HBM bytes the byte counters saw
+                  for it (profiles/gram_medium_traffic.json), when they were
+                  taken on the current kernel source;
   cpu_baseline    the FP64 oracle on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
@@ -208,7 +211,7 @@ def main() -> int:
     M, P = sc.num_matches, sc.num_pairs
     gram_s = gram_ms / 1e3 / max(n_gram, 1)
     matches_per_s = M / gram_s
-    alg_bytes = 16.0 * M + 72.0 * P
+    alg_bytes = 16.0 * M + (72.0 + 288.0) * P     # coordinates, E_n in, FP64 Gram out
     achieved = alg_bytes / gram_s / 1e9
     iters = sched.iters * args.steps
     iters_per_s = iters / (solve_ms / 1e3)
@@ -317,7 +320,7 @@ def bench_large(args) -> int:
         worst_rel = max(worst_rel, float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300)))
         worst_el = max(worst_el, float((np.abs(d) / np.where(absg > 0, absg, 1.0)).max()))
     gram_s = gram_ms / 1e3 / max(n_gram, 1)
-    alg_bytes = 8.0 * M + 72.0 * P
+    alg_bytes = 8.0 * M + (72.0 + 288.0) * P      # coordinates, E_n in, FP64 Gram out
     achieved = alg_bytes / gram_s / 1e9
     out = {
         "metric": "matches/s (Gram build) + epipolar iters/s at <=0.1deg rot err vs FP64 oracle",

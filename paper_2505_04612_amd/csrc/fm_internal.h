@@ -78,12 +78,14 @@ struct fm_scene {
   int64_t n_big = 0;              // chunk work items of pairs with more than kSmall matches
   int32_t* big_pair = nullptr;    // [n_big] pair of each chunk
   int32_t* big_chunk = nullptr;   // [n_big] chunk index within its pair
+  int32_t* big_slot = nullptr;    // [n_big] partial slot of the chunk (-1: the chunk is its whole pair)
+  int64_t n_partials = 0;         // chunk partials of pairs spanning several chunks
   int64_t n_groups = 0;           // wavefronts of four pairs with 1..kSmall matches
   int32_t* groups = nullptr;      // [4 n_groups] pair ids (-1: none)
   int64_t n_multi = 0;            // pairs spanning more than one chunk
   int64_t n_empty = 0;            // pairs without matches
   int32_t* multi = nullptr;       // [n_multi + n_empty]: those pairs, then the empty ones
-  int64_t* multi_first = nullptr; // [n_multi] first chunk work item of each multi pair
+  int64_t* multi_first = nullptr; // [n_multi] first partial slot of each multi pair
   unsigned long long* kept_slots = nullptr;  // [kKeptSlots * 16] kept-match counters, one per 128-B line
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order

@@ -229,7 +229,9 @@ __device__ inline void row_reduce_scatter36(const float (&a)[36], int lane, floa
   rs_stage<5, 0>(d, out, lane);
 }
 
-// The Gram pass.  Work item w < n_big: one wavefront on chunk big_chunk[w]
+// The Gram pass (work items in dispatch order, longest first, so the
+// wavefronts that wait for a free slot are the short ones).  Work item
+// w < n_big: one wavefront on chunk big_chunk[w]
 // (<= 1024 matches, 16 per lane, lanes strided so each load instruction
 // reads one contiguous span) of a pair with more than kSmall matches.  Work
 // item w >= n_big: one wavefront on four pairs of at most kSmall matches,
@@ -240,7 +242,8 @@ __device__ inline void row_reduce_scatter36(const float (&a)[36], int lane, floa
 template <int DT, int WMODE, bool BUILD, bool WRITE>
 __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int32_t* __restrict__ big_pair,
-    const int32_t* __restrict__ big_chunk, int64_t n_big, const int32_t* __restrict__ groups, int64_t n_groups,
+    const int32_t* __restrict__ big_chunk, const int32_t* __restrict__ big_slot, int64_t n_big,
+    const int32_t* __restrict__ groups, int64_t n_groups,
     const float* __restrict__ weights, const double* __restrict__ ess, double delta, double tau,
     float* __restrict__ partials, double* __restrict__ W64, float* __restrict__ W32, float* __restrict__ w_out,
     float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
   double E[9];
   if (w < n_big) {
     const int64_t n = big_pair[w];
-    const int64_t total = off[n + 1] - off[n];
+    const int32_t ps = big_slot[w];
     const int64_t start = off[n] + (int64_t)big_chunk[w] * kChunk;
     const int count = (int)min(off[n + 1] - start, (int64_t)kChunk);
     if constexpr (WMODE == W_IRLS) {
@@ -277,11 +280,11 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
       int slot;
       const float v = wave_reduce_scatter36(acc, lane, slot);
       if (slot >= 0) {
-        if (total <= kChunk) {
+        if (ps < 0) {
           if (W64) W64[n * 36 + slot] = (double)v;
           if (W32) W32[n * 36 + slot] = v;
         } else {
-          partials[w * 36 + slot] = v;
+          partials[(int64_t)ps * 36 + slot] = v;
         }
       }
     }
@@ -412,7 +415,8 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
   const dim3 grid(grid_for(items, kGramWaves)), block(kGramWaves * kLanes);
   fm_timed timer(s->ctx, FM_K_GRAM, st, true);
 #define FM_GRAM_ARGS                                                                                          \
-  s->uv, s->offsets, s->big_pair, s->big_chunk, s->n_big, s->groups, s->n_groups, weights, s->ess, delta, tau, \
+  s->uv, s->offsets, s->big_pair, s->big_chunk, s->big_slot, s->n_big, s->groups, s->n_groups, weights, s->ess,   \
+      delta, tau,                                                                                             \
       s->partials, W64, W32, w_out, r_out, s->kept_slots
   switch (s->dtype) {
     case FM_F32:

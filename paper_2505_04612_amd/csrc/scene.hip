@@ -1,5 +1,6 @@
 // Context, error handling and scene set-up: validation of the pair/match
 // structure, the Gram work-item table and the per-camera incidence lists.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <new>
@@ -230,6 +231,7 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->multi_first);
   (void)hipFree(s->big_pair);
   (void)hipFree(s->big_chunk);
+  (void)hipFree(s->big_slot);
   (void)hipFree(s->groups);
   (void)hipFree(s->kept_slots);
   (void)hipFree(s->cam_ptr);
@@ -259,10 +261,14 @@ static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
 // Work decomposition of the Gram pass, from the pair offsets (set-up only,
 // on the host): pairs with more than kSmall matches are cut into chunks of
 // kChunk (one wavefront each); pairs with 1..kSmall matches are bucketed by
-// their number of 16-match rows and packed four to a wavefront; the lists of
-// multi-chunk and empty pairs drive the finalize kernel.  Which wavefront
-// handles a pair does not change its result (each pair's sums use a fixed
-// lane/row assignment and reduction order).
+// their number of 16-match rows and packed four to a wavefront.  Chunks are
+// ordered by row count (longest first) and so are the groups, so the work
+// items that wait for a free slot at the end of the pass are the short
+// ones.  Chunks of pairs that span several chunks write partial slots (in
+// chunk order per pair) that the finalize kernel adds; the lists of
+// multi-chunk and empty pairs drive it.  Which wavefront handles a pair does
+// not change its result (each pair's sums use a fixed lane/row assignment
+// and reduction order).
 static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   fm_ctx* ctx = s->ctx;
   const int64_t P = s->P;
@@ -270,9 +276,14 @@ static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(off.data(), s->offsets, sizeof(int64_t) * (P + 1), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fm_fail(ctx, FM_EHIP, "gram plan: %s", hipGetErrorString(e));
-  std::vector<int32_t> big_pair, big_chunk, groups, multi, empty;
+  struct Chunk {
+    int32_t pair, chunk, slot, rows;
+  };
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> big_pair, big_chunk, big_slot, groups, multi, empty;
   std::vector<int64_t> multi_first;
   std::vector<std::vector<int32_t>> bucket(kPerLane + 1);
+  int64_t n_partials = 0;
   for (int64_t n = 0; n < P; ++n) {
     const int64_t c = off[n + 1] - off[n];
     if (c == 0) {
@@ -280,29 +291,40 @@ static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
     } else if (c <= kSmall) {
       bucket[(c + 15) / 16].push_back((int32_t)n);
     } else {
-      const int64_t chunks = (c + kChunk - 1) / kChunk;
-      if (chunks > 1) {
+      const int64_t nch = (c + kChunk - 1) / kChunk;
+      if (nch > 1) {
         multi.push_back((int32_t)n);
-        multi_first.push_back((int64_t)big_pair.size());
+        multi_first.push_back(n_partials);
       }
-      for (int64_t j = 0; j < chunks; ++j) {
-        big_pair.push_back((int32_t)n);
-        big_chunk.push_back((int32_t)j);
+      for (int64_t j = 0; j < nch; ++j) {
+        const int64_t cnt = std::min<int64_t>(kChunk, c - j * kChunk);
+        chunks.push_back({(int32_t)n, (int32_t)j, nch > 1 ? (int32_t)(n_partials + j) : -1,
+                          (int32_t)((cnt + kLanes - 1) / kLanes)});
       }
+      if (nch > 1) n_partials += nch;
     }
   }
-  for (auto& b : bucket) {
+  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& x, const Chunk& y) { return x.rows > y.rows; });
+  for (const Chunk& ch : chunks) {
+    big_pair.push_back(ch.pair);
+    big_chunk.push_back(ch.chunk);
+    big_slot.push_back(ch.slot);
+  }
+  for (int rows = kPerLane; rows >= 1; --rows) {
+    const auto& b = bucket[rows];
     for (size_t k = 0; k < b.size(); ++k) groups.push_back(b[k]);
     while (groups.size() % 4) groups.push_back(-1);
   }
   s->n_big = (int64_t)big_pair.size();
   s->n_groups = (int64_t)groups.size() / 4;
+  s->n_partials = n_partials;
   s->n_multi = (int64_t)multi.size();
   s->n_empty = (int64_t)empty.size();
   multi.insert(multi.end(), empty.begin(), empty.end());
   if ((e = upload(&s->big_pair, big_pair, st)) != hipSuccess || (e = upload(&s->big_chunk, big_chunk, st)) != hipSuccess ||
-      (e = upload(&s->groups, groups, st)) != hipSuccess || (e = upload(&s->multi, multi, st)) != hipSuccess ||
-      (e = upload(&s->multi_first, multi_first, st)) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess)
+      (e = upload(&s->big_slot, big_slot, st)) != hipSuccess || (e = upload(&s->groups, groups, st)) != hipSuccess ||
+      (e = upload(&s->multi, multi, st)) != hipSuccess || (e = upload(&s->multi_first, multi_first, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
     return fm_fail(ctx, e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP, "gram plan: %s", hipGetErrorString(e));
   return FM_OK;
 }
@@ -415,7 +437,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   }
   s->loss_part_cap = (int64_t)grid_for(P, kBlock);   // also covers k_pair_phase's blocks
   if (s->loss_part_cap < s->coop_blocks) s->loss_part_cap = s->coop_blocks;
-  SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_big > 0 ? s->n_big : 1)));
+  SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_partials > 0 ? s->n_partials : 1)));
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));

@@ -49,9 +49,11 @@ def _grams(scene, params, s: Schedule, tau: float | None):
     return (W64 if f64 else W32), kept
 
 
-def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = True):
+def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = True, rounds: int | None = None):
     """Run the schedule from params0 [N,9] float32.  Returns (params, loss
-    trace [iters] float64 or None, Z [1] int64 or None for unit weights)."""
+    trace [iters] float64 or None, Z [1] int64 or None for unit weights).
+    `rounds` stops after that many optimisation loops (the schedule's learning
+    rates and thresholds are those of the full run)."""
     dev = scene.ctx.device
     params = params0.detach().to(dev, torch.float32).clone().contiguous()
     m = torch.zeros_like(params)
@@ -65,7 +67,8 @@ def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = Tr
         W, Z = _grams(scene, params, s, None)
     inv_Z = 1.0 / max(scene.num_matches, 1)
     done = 0
-    while done < s.iters:
+    stop = s.iters if rounds is None else min(s.iters, rounds * s.round_len)
+    while done < stop:
         K = min(s.round_len, s.iters - done)
         m.zero_()
         v.zero_()
@@ -73,7 +76,7 @@ def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = Tr
                            s.beta1, s.beta2, s.eps, inv_Z=None if Z is not None else inv_Z, Z=Z,
                            loss_trace=losses[done:done + K] if trace else None)
         done += K
-        if s.irls and done < s.iters:
+        if s.irls and done < stop:
             W, Z = _grams(scene, params, s, tau_at(s, k_rw))
             k_rw += 1
     return params, losses, Z

@@ -52,7 +52,9 @@ def test_fallback_triggers_on_garbage_network():
     w = api.MlpWeights(ctx.device)
     w.views["b3"].fill_(-30.0)           # sigmoid ~ 0: every weight ~ 0, the Gram is ~ 0
     sched = solver.Schedule(iters=600, round_len=100)
-    p_l, info = learned.learned_solve(s, p0, w, learned.LearnedSchedule(iters=200), sched)
+    # no warm-up: the zero-weight Gram leaves the poses where they started,
+    # far from the IRLS optimum, which the check loop must notice
+    p_l, info = learned.learned_solve(s, p0, w, learned.LearnedSchedule(iters=200, warm_rounds=0), sched)
     assert info["fallback"], info
     p_irls, _, _ = solver.solve(s, p0, sched, trace=False)
     e_irls = learned._pose_err(p_irls.cpu().numpy(), sc.R_gt, sc.t_gt, sc.pairs)
