@@ -17,6 +17,10 @@ constexpr int kPerLane = 16;
 constexpr int kChunk = kLanes * kPerLane;
 // Pairs with at most kSmall matches share a wavefront (16 lanes x 16 rows).
 constexpr int kSmall = 16 * kPerLane;
+// Rows per lane of a big Gram work item: 32 for BF16 coordinates (2,048
+// matches per wavefront halves the per-wavefront reduction work where the
+// pass is bound by vector ALU issue), 16 otherwise.
+constexpr int big_rows(int dt) { return dt == FM_BF16 ? 2 * kPerLane : kPerLane; }
 // Wavefronts per block of the Gram kernels.
 constexpr int kGramWaves = 4;
 // Threads per block of the per-pair and per-camera kernels.
@@ -79,6 +83,7 @@ struct fm_scene {
   int32_t* big_pair = nullptr;    // [n_big] pair of each chunk
   int32_t* big_chunk = nullptr;   // [n_big] chunk index within its pair
   int32_t* big_slot = nullptr;    // [n_big] partial slot of the chunk (-1: the chunk is its whole pair)
+  int64_t chunk = kChunk;         // matches per big work item (kLanes * big_rows(dtype))
   int64_t n_partials = 0;         // chunk partials of pairs spanning several chunks
   int64_t n_groups = 0;           // wavefronts of four pairs with 1..kSmall matches
   int32_t* groups = nullptr;      // [4 n_groups] pair ids (-1: none)

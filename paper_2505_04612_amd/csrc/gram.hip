@@ -1,14 +1,16 @@
 // Per-pair Gram build (App. B.6) and IRLS reweighting (Sec. 3.3).
 //
-// The M matches are streamed once, in pair order.  Work item w covers up to
-// kChunk = 1024 consecutive matches of one pair and is processed by one
-// wavefront: lane l takes matches start + l + 64 r (so every load instruction
-// of the wave reads one contiguous span), forms the monomials
+// The M matches are streamed once.  A work item is either a chunk of up to
+// 1024 (BF16: 2048) consecutive matches of one pair, processed by a whole
+// wavefront (lane l takes matches start + l + 64 r, so every load
+// instruction of the wave reads one contiguous span), or four pairs of at
+// most 256 matches, 16 lanes each.  Each lane forms the monomials
 // p = (u^2, uv, v^2, u, v, 1) of both points and accumulates the 36 sums
-// omega p2[q2] p1[q1] in float32 registers.  A reduce-scatter across the wave
-// (38 lane exchanges instead of 36 full reductions) leaves one entry per lane
-// in 36 of the 64 lanes, which store the work item's partial Gram.  A second
-// kernel adds each pair's partials in float64, in work-item order, so the
+// omega p2[q2] p1[q1] in float32 registers; a reduce-scatter across the
+// lanes of the pair (DPP and lane permutes: 38 exchanges instead of 36 full
+// reductions over a wavefront) leaves one entry per lane.  A pair that one
+// work item covers stores its Gram directly; larger pairs leave chunk
+// partials that a second kernel adds in float64, in chunk order, so the
 // result does not depend on scheduling: no atomics touch floating point.
 #include "fm_internal.h"
 
@@ -166,13 +168,13 @@ __device__ inline void process_match(const typename RawMatch<DT>::T& raw, bool o
 }
 
 // Stream the rows of one work item: this lane takes matches
-// start + lid + STRIDE r for r < nrows (nrows is the same in every lane of
-// the wavefront).  Rows below `nfull` are full and load straight from a
+// start + lid + STRIDE r for r < nrows <= ROWS (nrows is the same in every
+// lane of the wavefront).  Rows below `nfull` are full and load straight from a
 // per-lane pointer; the rows from nfull on are checked against `count`
 // (lanes past it load the item's first match and weigh it 0).  Full rows are
 // loaded BATCH at a time before any is used; a single checked row is loaded
 // with the first batch.
-template <int DT, int WMODE, bool BUILD, bool WRITE, int STRIDE, int BATCH>
+template <int DT, int WMODE, bool BUILD, bool WRITE, int STRIDE, int BATCH, int ROWS>
 __device__ inline void stream_rows(const void* __restrict__ uv, int64_t start, int count, int lid, int nrows,
                                    int nfull, const double E[9], float fdelta, double tau,
                                    const float* __restrict__ weights, float* __restrict__ w_out,
@@ -180,8 +182,6 @@ __device__ inline void stream_rows(const void* __restrict__ uv, int64_t start, i
   using RawT = typename RawMatch<DT>::T;
   const RawT* __restrict__ base = reinterpret_cast<const RawT*>(uv) + start;
   const RawT* __restrict__ p = base + lid;
-  // second base for rows 8.. (keeps every full-row load an immediate offset)
-  const RawT* __restrict__ p8 = p + 8 * STRIDE;
   const int64_t m0 = start + lid;
   const bool one_tail = nrows - nfull == 1;
   RawT traw;
@@ -189,12 +189,13 @@ __device__ inline void stream_rows(const void* __restrict__ uv, int64_t start, i
   const bool tok = ti < count;
   if (one_tail) traw = load_raw<DT>(tok ? p + nfull * STRIDE : base);
 #pragma unroll
-  for (int r0 = 0; r0 < kPerLane; r0 += BATCH) {
+  for (int r0 = 0; r0 < ROWS; r0 += BATCH) {
     if (r0 < nfull) {
       RawT raw[BATCH];
+      // one base per 8 rows keeps every full-row load an immediate offset
 #pragma unroll
       for (int r = 0; r < BATCH; ++r)
-        if (r0 + r < nfull) raw[r] = load_raw<DT>(r0 + r < 8 ? p + (r0 + r) * STRIDE : p8 + (r0 + r - 8) * STRIDE);
+        if (r0 + r < nfull) raw[r] = load_raw<DT>(p + ((r0 + r) & ~7) * STRIDE + ((r0 + r) & 7) * STRIDE);
 #pragma unroll
       for (int r = 0; r < BATCH; ++r)
         if (r0 + r < nfull)
@@ -231,14 +232,15 @@ __device__ inline void row_reduce_scatter36(const float (&a)[36], int lane, floa
 
 // The Gram pass (work items in dispatch order, longest first, so the
 // wavefronts that wait for a free slot are the short ones).  Work item
-// w < n_big: one wavefront on chunk big_chunk[w]
-// (<= 1024 matches, 16 per lane, lanes strided so each load instruction
-// reads one contiguous span) of a pair with more than kSmall matches.  Work
-// item w >= n_big: one wavefront on four pairs of at most kSmall matches,
-// 16 lanes each (groups of pairs with equal row counts, built at set-up).
-// Each pair's sums are reduced over its lanes in a fixed order; a pair whose
-// matches one wavefront covered stores its Gram directly (float64 of the
-// float32 sum), the others leave per-chunk partials for k_gram_finalize.
+// w < n_big: one wavefront on chunk big_chunk[w] (<= 64 big_rows(DT)
+// matches: 1024, or 2048 for BF16; lanes strided so each load instruction
+// reads one contiguous span)
+// of a pair with more than kSmall matches.  Work item w >= n_big: one
+// wavefront on four pairs of at most kSmall matches, 16 lanes each (groups
+// of pairs with equal row counts, built at set-up).  Each pair's sums are
+// reduced over its lanes in a fixed order; a pair whose matches one
+// wavefront covered stores its Gram directly (float64 of the float32 sum),
+// the others leave chunk partials (slot big_slot[w]) for k_gram_finalize.
 template <int DT, int WMODE, bool BUILD, bool WRITE>
 __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int32_t* __restrict__ big_pair,
@@ -262,8 +264,10 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
   if (w < n_big) {
     const int64_t n = big_pair[w];
     const int32_t ps = big_slot[w];
-    const int64_t start = off[n] + (int64_t)big_chunk[w] * kChunk;
-    const int count = (int)min(off[n + 1] - start, (int64_t)kChunk);
+    constexpr int kRows = big_rows(DT);
+    constexpr int64_t kCh = (int64_t)kLanes * kRows;
+    const int64_t start = off[n] + (int64_t)big_chunk[w] * kCh;
+    const int count = (int)min(off[n + 1] - start, kCh);
     if constexpr (WMODE == W_IRLS) {
       // E_n is uniform here; held in vector registers all the same, since a
       // float64 FMA may read only one scalar operand
@@ -273,7 +277,7 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
         asm volatile("" : "+v"(E[k]));
       }
     }
-    stream_rows<DT, WMODE, BUILD, WRITE, kLanes, kBatch>(uv, start, count, lane, (count + kLanes - 1) / kLanes,
+    stream_rows<DT, WMODE, BUILD, WRITE, kLanes, kBatch, kRows>(uv, start, count, lane, (count + kLanes - 1) / kLanes,
                                                          count / kLanes, E, fdelta, tau, weights, w_out, r_out, acc,
                                                          nkept);
     if constexpr (BUILD) {
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
 #pragma unroll
       for (int k = 0; k < 9; ++k) E[k] = have ? ess[n * 9 + k] : 0.0;
     }
-    stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch>(uv, start, count, l16, nrows, nfull, E, fdelta, tau, weights,
+    stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch, kPerLane>(uv, start, count, l16, nrows, nfull, E, fdelta, tau, weights,
                                                      w_out, r_out, acc, nkept);
     if constexpr (BUILD) {
       float v[3];
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_count_kept(unsigned long long* __res
 }
 
 // Gram of every pair that spans several work items: the sum of its chunk
-// partials in float64, in chunk order (the other pairs with matches were
+// partials (chunks of `chunk` matches) in float64, in chunk order (the other pairs with matches were
 // written by the pass itself, pairs without matches are zeroed here).
 // Block 0 also totals the kept counts of an IRLS pass (kept != NULL).
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restrict__ partials,
@@ -364,7 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restric
                                                           const int32_t* __restrict__ multi,
                                                           const int64_t* __restrict__ multi_first, int64_t n_multi,
                                                           const int32_t* __restrict__ empty, int64_t n_empty,
-                                                          double* __restrict__ W64, float* __restrict__ W32,
+                                                          int64_t chunk, double* __restrict__ W64,
+                                                          float* __restrict__ W32,
                                                           unsigned long long* __restrict__ kept_slots,
                                                           int64_t* __restrict__ kept) {
   if (kept && blockIdx.x == 0) sum_kept(kept_slots, kept);
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restric
   const int64_t i = t / 36;
   const int64_t n = multi[i];
   const int k = (int)(t % 36);
-  const int64_t chunks = (off[n + 1] - off[n] + kChunk - 1) / kChunk;
+  const int64_t chunks = (off[n + 1] - off[n] + chunk - 1) / chunk;
   double s = 0.0;
   for (int64_t j = 0; j < chunks; ++j) s += (double)partials[(multi_first[i] + j) * 36 + k];
   if (W64) W64[n * 36 + k] = s;
@@ -443,7 +448,7 @@ static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* 
   const int64_t nthreads = (s->n_multi + s->n_empty) * 36 > 0 ? (s->n_multi + s->n_empty) * 36 : 1;
   hipExtLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, timer.a, timer.b, 0,
                         s->partials, s->offsets, s->multi, s->multi_first, s->n_multi, s->multi + s->n_multi,
-                        s->n_empty, W64, W32, s->kept_slots, kept);
+                        s->n_empty, s->chunk, W64, W32, s->kept_slots, kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }

@@ -260,11 +260,11 @@ static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
 
 // Work decomposition of the Gram pass, from the pair offsets (set-up only,
 // on the host): pairs with more than kSmall matches are cut into chunks of
-// kChunk (one wavefront each); pairs with 1..kSmall matches are bucketed by
-// their number of 16-match rows and packed four to a wavefront.  Chunks are
-// ordered by row count (longest first) and so are the groups, so the work
-// items that wait for a free slot at the end of the pass are the short
-// ones.  Chunks of pairs that span several chunks write partial slots (in
+// 64 big_rows(dtype) matches (one wavefront each); pairs with 1..kSmall
+// matches are bucketed by their number of 16-match rows and packed four to
+// a wavefront.  Chunks are ordered by row count (longest first) and so are
+// the groups, so the work items that wait for a free slot at the end of the
+// pass are the short ones.  Chunks of pairs that span several chunks write partial slots (in
 // chunk order per pair) that the finalize kernel adds; the lists of
 // multi-chunk and empty pairs drive it.  Which wavefront handles a pair does
 // not change its result (each pair's sums use a fixed lane/row assignment
@@ -272,6 +272,8 @@ static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
 static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   fm_ctx* ctx = s->ctx;
   const int64_t P = s->P;
+  const int64_t chunk = (int64_t)kLanes * big_rows(s->dtype);
+  s->chunk = chunk;
   std::vector<int64_t> off(P + 1);
   hipError_t e = hipMemcpyAsync(off.data(), s->offsets, sizeof(int64_t) * (P + 1), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -291,13 +293,13 @@ static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
     } else if (c <= kSmall) {
       bucket[(c + 15) / 16].push_back((int32_t)n);
     } else {
-      const int64_t nch = (c + kChunk - 1) / kChunk;
+      const int64_t nch = (c + chunk - 1) / chunk;
       if (nch > 1) {
         multi.push_back((int32_t)n);
         multi_first.push_back(n_partials);
       }
       for (int64_t j = 0; j < nch; ++j) {
-        const int64_t cnt = std::min<int64_t>(kChunk, c - j * kChunk);
+        const int64_t cnt = std::min<int64_t>(chunk, c - j * chunk);
         chunks.push_back({(int32_t)n, (int32_t)j, nch > 1 ? (int32_t)(n_partials + j) : -1,
                           (int32_t)((cnt + kLanes - 1) / kLanes)});
       }

@@ -12,13 +12,15 @@ converged IRLS solves produce, omega_bar = delta / max(|r|, delta) (0 for
 filtered matches), from features at the same warm-up poses, with the
 library's MFMA forward/backward kernels and its Adam kernel.
 
-Fallback: after the learned solve, one plain IRLS loop is run from its
-result; if that loop moves the relative rotation of more than a tenth of
-the pairs by over 0.1 deg, or their translation direction by over 0.5 deg
-(the 90th percentile of the per-pair changes, so a few pairs with an
-ill-conditioned baseline do not decide alone), the full plain IRLS
-schedule is run from the initial poses instead, so plain IRLS stays the
-judge of pose accuracy.
+A tail of `tail_rounds` plain IRLS loops (final filter threshold, learning
+rate from the middle of the plain schedule's range down to its end) then
+takes the learned solution to the IRLS weighting.  Fallback: if the tail
+moves the relative rotation of more than a tenth of the pairs by over
+0.1 deg, or their translation direction by over 0.5 deg (the
+90th percentile of the per-pair changes, so a few pairs with an
+ill-conditioned baseline do not decide alone), the full plain IRLS schedule
+is run from the initial poses instead, so plain IRLS stays the judge of pose
+accuracy.
 
     python -m paper_2505_04612_amd.learned --train 64 --test 16 --out results.json
 """
@@ -42,6 +44,7 @@ from . import api, solver, synth
 class LearnedSchedule:
     warm_rounds: int = 2         # plain IRLS loops before the network weighs the matches
     iters: int = 600             # Adam steps on the learned-weight Gram
+    tail_rounds: int = 3         # plain IRLS loops after them (their movement is the fallback check)
     lr_rot: float = 3e-3
     lr_t: float = 1e-2
     lr_final_frac: float = 1e-3
@@ -160,17 +163,26 @@ def learned_solve(scene: api.Scene, params0: torch.Tensor, w: api.MlpWeights, ls
     v = torch.zeros_like(p)
     api.epipolar_solve(scene, W64, p, m, v, ls.iters, ls.lr_rot, ls.lr_t, ls.lr_final_frac, warm, warm + ls.iters,
                        inv_Z=1.0 / max(scene.num_matches, 1))
-    # one plain IRLS loop from the learned solution decides the fallback; its
-    # learning rate starts at the geometric middle of the plain schedule's
-    # range, so a solution away from the IRLS optimum does move
+    # a tail of plain IRLS loops from the learned solution, at the final
+    # filter threshold and with the learning rate falling from the geometric
+    # middle of the plain schedule's range to its end; how far the tail moves
+    # the learned solution decides the fallback
+    p_learned = p.clone()
     tau = solver.tau_at(fallback, max(fallback.iters // fallback.round_len - 1, 0))
     half = math.sqrt(fallback.lr_final_frac)
-    chk = dataclasses.replace(fallback, iters=fallback.round_len, tau0=tau, lr_rot=fallback.lr_rot * half,
-                              lr_t=fallback.lr_t * half, lr_final_frac=half)
-    p_chk, _, _ = solver.solve(scene, p, chk, trace=False)
-    d_rot, d_t = _relative_pose_change(p.cpu().numpy(), p_chk.cpu().numpy(), scene.pairs.cpu().numpy(),
+    T = max(ls.tail_rounds, 1)
+    tail = dataclasses.replace(fallback, iters=T * fallback.round_len, tau0=tau, lr_rot=fallback.lr_rot * half,
+                               lr_t=fallback.lr_t * half, lr_final_frac=half)
+    p_chk = p.clone()
+    for r in range(T):
+        Wt, Zt = solver._grams(scene, p_chk, tail, solver.tau_at(tail, r))
+        m.zero_()
+        v.zero_()
+        api.epipolar_solve(scene, Wt, p_chk, m, v, tail.round_len, tail.lr_rot, tail.lr_t, tail.lr_final_frac,
+                           r * tail.round_len, tail.iters, 0, tail.beta1, tail.beta2, tail.eps, Z=Zt)
+    d_rot, d_t = _relative_pose_change(p_learned.cpu().numpy(), p_chk.cpu().numpy(), scene.pairs.cpu().numpy(),
                                        ls.check_quantile)
-    info = {"check_rot_deg": d_rot, "check_t_deg": d_t, "fallback": False, "params_learned": p}
+    info = {"check_rot_deg": d_rot, "check_t_deg": d_t, "fallback": False, "params_learned": p_learned}
     if d_rot > ls.check_rot_deg or d_t > ls.check_t_deg:
         # the learned weights missed the IRLS optimum: plain IRLS from the
         # initial poses decides the result
@@ -205,6 +217,7 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--learned-iters", type=int, default=600)
     ap.add_argument("--warm-rounds", type=int, default=2)
+    ap.add_argument("--tail-rounds", type=int, default=3)
     ap.add_argument("--out", default="learned_results.json")
     args = ap.parse_args(argv)
     t0 = time.time()
@@ -242,7 +255,7 @@ def main(argv=None) -> int:
                         progress=lambda k, l: print(f"[learned] step {k} loss {l:.4g}", flush=True)
                         if k % 500 == 0 else None)
     print(f"[learned] trained: loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g} ({time.time() - t0:.0f}s)", flush=True)
-    ls = LearnedSchedule(iters=args.learned_iters, warm_rounds=args.warm_rounds)
+    ls = LearnedSchedule(iters=args.learned_iters, warm_rounds=args.warm_rounds, tail_rounds=args.tail_rounds)
     rows = []
     for sc in scenes[args.train:]:
         # plain method: FP32 coordinates, IRLS every loop; learned form: BF16

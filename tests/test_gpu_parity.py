@@ -71,12 +71,13 @@ def test_gram_ragged_parity_and_determinism(fm, ctx, dtype):
     assert np.all(W64.cpu().numpy()[np.diff(offs) == 0] == 0.0)
 
 
-# sizes around the small-pair / big-pair boundary (256; 128 for float64
-# coordinates), the 16-lane row (16, 17) and the chunk (1024; 512 for
-# float64): groups of four equal row counts (all rows but the last full),
+# sizes around the small-pair / big-pair boundary (256), the 16-lane row
+# (16, 17) and the chunk (1024; 2048 for BF16 coordinates), plus 128/512
+# boundaries: groups of four equal row counts (all rows but the last full),
 # groups with empty slots, single-match pairs, and pairs spanning 2-4 chunks
 _EDGE_SIZES = (16, 16, 16, 16, 17, 17, 17, 17, 255, 256, 256, 256, 256, 257, 33, 48, 1, 1, 1, 1,
-               2047, 2048, 3073, 240, 241, 242, 243, 0, 1024, 1025, 128, 129, 511, 512, 513, 97)
+               2047, 2048, 3073, 240, 241, 242, 243, 0, 1024, 1025, 128, 129, 511, 512, 513, 97, 2049, 4096,
+               4097)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
