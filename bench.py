@@ -149,7 +149,7 @@ def main() -> int:
                     help="processes generating the large workload (default: up to 16; 1 = no child processes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the hot path runs on a single MI355X and this build "
+        print(f"bench.py measures one GPU: the hot path runs on a single MI355X and this library "
               f"has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
         return 2
 

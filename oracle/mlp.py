@@ -2,7 +2,7 @@
 
 A per-match robust weight is proposed by a small MLP from three features of
 the match at the current poses (the paper weights matches by IRLS, Sec. 3.3;
-the learned proposal is an addition of this build, so nothing here is pinned
+the learned proposal is not part of the paper, so nothing here is pinned
 by a printed value of the paper: the pins are finite differences and closed
 forms):
   f0 = log max(|r|, delta), r = x2~^T E_n x1~ the epipolar residual;

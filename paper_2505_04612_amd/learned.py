@@ -19,8 +19,8 @@ moves the relative rotation of more than a tenth of the pairs by over
 0.1 deg, or their translation direction by over 0.5 deg (the
 90th percentile of the per-pair changes, so a few pairs with an
 ill-conditioned baseline do not decide alone), the full plain IRLS schedule
-is run from the initial poses instead, so plain IRLS stays the judge of pose
-accuracy.
+is run from the initial poses instead, so plain IRLS remains the reference
+for pose accuracy.
 
     python -m paper_2505_04612_amd.learned --train 64 --test 16 --out results.json
 """

@@ -18,7 +18,7 @@ def declared():
     return sorted(set(re.findall(r"\b(fm_[a-z0-9_]+)\s*\(", src)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_four_core_calls():
     names = declared()
     for n in ("fm_build_pair_grams", "fm_epipolar_loss_grad", "fm_adam_step", "fm_reweight"):
         assert n in names
