@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "fm_internal.h"
+#include "gram_plan.h"
 
 fm_status fm_fail(fm_ctx* ctx, fm_status st, const char* fmt, ...) {
   if (ctx) {
@@ -258,74 +259,27 @@ static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
   return e;
 }
 
-// Work decomposition of the Gram pass, from the pair offsets (set-up only,
-// on the host): pairs with more than kSmall matches are cut into chunks of
-// 64 big_rows(dtype) matches (one wavefront each); pairs with 1..kSmall
-// matches are bucketed by their number of 16-match rows and packed four to
-// a wavefront.  Chunks are ordered by row count (longest first) and so are
-// the groups, so the work items that wait for a free slot at the end of the
-// pass are the short ones.  Chunks of pairs that span several chunks write partial slots (in
-// chunk order per pair) that the finalize kernel adds; the lists of
-// multi-chunk and empty pairs drive it.  Which wavefront handles a pair does
-// not change its result (each pair's sums use a fixed lane/row assignment
-// and reduction order).
+// Work decomposition of the Gram pass (make_gram_plan, host only): chunks of
+// 64 big_rows(dtype) matches for pairs with more than kSmall matches, groups
+// of four smaller pairs, both longest first; uploaded once per scene.
 static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   fm_ctx* ctx = s->ctx;
   const int64_t P = s->P;
-  const int64_t chunk = (int64_t)kLanes * big_rows(s->dtype);
-  s->chunk = chunk;
   std::vector<int64_t> off(P + 1);
   hipError_t e = hipMemcpyAsync(off.data(), s->offsets, sizeof(int64_t) * (P + 1), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fm_fail(ctx, FM_EHIP, "gram plan: %s", hipGetErrorString(e));
-  struct Chunk {
-    int32_t pair, chunk, slot, rows;
-  };
-  std::vector<Chunk> chunks;
-  std::vector<int32_t> big_pair, big_chunk, big_slot, groups, multi, empty;
-  std::vector<int64_t> multi_first;
-  std::vector<std::vector<int32_t>> bucket(kPerLane + 1);
-  int64_t n_partials = 0;
-  for (int64_t n = 0; n < P; ++n) {
-    const int64_t c = off[n + 1] - off[n];
-    if (c == 0) {
-      empty.push_back((int32_t)n);
-    } else if (c <= kSmall) {
-      bucket[(c + 15) / 16].push_back((int32_t)n);
-    } else {
-      const int64_t nch = (c + chunk - 1) / chunk;
-      if (nch > 1) {
-        multi.push_back((int32_t)n);
-        multi_first.push_back(n_partials);
-      }
-      for (int64_t j = 0; j < nch; ++j) {
-        const int64_t cnt = std::min<int64_t>(chunk, c - j * chunk);
-        chunks.push_back({(int32_t)n, (int32_t)j, nch > 1 ? (int32_t)(n_partials + j) : -1,
-                          (int32_t)((cnt + kLanes - 1) / kLanes)});
-      }
-      if (nch > 1) n_partials += nch;
-    }
-  }
-  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& x, const Chunk& y) { return x.rows > y.rows; });
-  for (const Chunk& ch : chunks) {
-    big_pair.push_back(ch.pair);
-    big_chunk.push_back(ch.chunk);
-    big_slot.push_back(ch.slot);
-  }
-  for (int rows = kPerLane; rows >= 1; --rows) {
-    const auto& b = bucket[rows];
-    for (size_t k = 0; k < b.size(); ++k) groups.push_back(b[k]);
-    while (groups.size() % 4) groups.push_back(-1);
-  }
-  s->n_big = (int64_t)big_pair.size();
-  s->n_groups = (int64_t)groups.size() / 4;
-  s->n_partials = n_partials;
-  s->n_multi = (int64_t)multi.size();
-  s->n_empty = (int64_t)empty.size();
-  multi.insert(multi.end(), empty.begin(), empty.end());
-  if ((e = upload(&s->big_pair, big_pair, st)) != hipSuccess || (e = upload(&s->big_chunk, big_chunk, st)) != hipSuccess ||
-      (e = upload(&s->big_slot, big_slot, st)) != hipSuccess || (e = upload(&s->groups, groups, st)) != hipSuccess ||
-      (e = upload(&s->multi, multi, st)) != hipSuccess || (e = upload(&s->multi_first, multi_first, st)) != hipSuccess ||
+  s->chunk = (int64_t)kLanes * big_rows(s->dtype);
+  const GramPlan g = make_gram_plan(off.data(), P, kLanes, big_rows(s->dtype), kSmall);
+  s->n_big = (int64_t)g.big_pair.size();
+  s->n_groups = (int64_t)g.groups.size() / 4;
+  s->n_partials = g.n_partials;
+  s->n_multi = g.n_multi;
+  s->n_empty = g.n_empty;
+  if ((e = upload(&s->big_pair, g.big_pair, st)) != hipSuccess ||
+      (e = upload(&s->big_chunk, g.big_chunk, st)) != hipSuccess ||
+      (e = upload(&s->big_slot, g.big_slot, st)) != hipSuccess || (e = upload(&s->groups, g.groups, st)) != hipSuccess ||
+      (e = upload(&s->multi, g.multi, st)) != hipSuccess || (e = upload(&s->multi_first, g.multi_first, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return fm_fail(ctx, e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP, "gram plan: %s", hipGetErrorString(e));
   return FM_OK;
