@@ -249,10 +249,10 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     const float* __restrict__ weights, const double* __restrict__ ess, double delta, double tau,
     float* __restrict__ partials, double* __restrict__ W64, float* __restrict__ W32, float* __restrict__ w_out,
     float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
-  // rows loaded per batch (measured on the medium scene, FP32: 2 rows
-  // 14.9 us, 4 rows 15.6, 8 rows 17.0; BF16 is bound by vector ALU issue and
-  // loads all 16 rows of a batch at once)
-  constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 2 : kPerLane);
+  // rows loaded per batch (measured on the medium scene, FP32: 1 row
+  // 13.6-13.9 us, 2 rows 14.4-14.9, 4 rows 15.6, 8 rows 17.0; BF16 is bound
+  // by vector ALU issue and loads all 16 rows of a batch at once)
+  constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 1 : kPerLane);
   const int lane = threadIdx.x & (kLanes - 1);
   // wave-uniform work item (scalar registers: the big path's pair data and
   // E_n are then scalar loads)
