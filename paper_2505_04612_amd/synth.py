@@ -533,3 +533,37 @@ def make(name: str, **kw) -> Scene:
 def noise_free(scene_fn, **kw) -> Scene:
     """The same recipe with zero pixel noise and no outliers."""
     return scene_fn(sigma=0.0, frac=0.0, **kw)
+
+
+# ------------------------------------------------------------------ translation averaging inputs
+
+@dataclasses.dataclass
+class TranslationInputs:
+    t_rel: np.ndarray       # [P,3] float64 unit relative translations t^{i->j} (camera j's frame)
+    outlier: np.ndarray     # [P] bool, True where t_rel is a random direction
+    init: np.ndarray        # [runs,N,3] float64 initial camera centres, N(0, I) per run
+    sigma_deg: float
+    outlier_frac: float
+
+
+def translation_inputs(scene: Scene, sigma_deg: float = 2.0, outlier_frac: float = 0.1,
+                       runs: int = 4, seed: int | None = None) -> TranslationInputs:
+    """Inputs of translation averaging on a scene's pair graph (Sec. 3.3,
+    Global Translation): per pair the measured unit direction of camera i's
+    centre seen from camera j, t^{i->j} ~ R_j (o_i - o_j) / |o_i - o_j|, with
+    Gaussian noise of sigma_deg per axis (radians after conversion) before
+    renormalising, and outlier_frac of the pairs replaced by directions
+    uniform on the sphere; plus `runs` independent N(0, I) initialisations of
+    the N camera centres.  The stage follows rotation averaging, so the
+    rotations it uses are the scene's true ones."""
+    rng = np.random.default_rng((scene.seed if seed is None else seed) + 20_000)
+    R, t = scene.R_gt, scene.t_gt
+    o = -np.einsum("nba,nb->na", R, t)
+    i, j = scene.pairs[:, 0], scene.pairs[:, 1]
+    P = len(scene.pairs)
+    tr = _normalize(np.einsum("pab,pb->pa", R[j], o[i] - o[j]))
+    tr = _normalize(tr + rng.normal(0.0, np.deg2rad(sigma_deg), size=(P, 3)))
+    outl = rng.random(P) < outlier_frac
+    tr[outl] = _normalize(rng.normal(size=(int(outl.sum()), 3)))
+    init = rng.normal(size=(runs, R.shape[0], 3))
+    return TranslationInputs(tr, outl, init, sigma_deg, outlier_frac)
