@@ -186,12 +186,71 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
                             double inv_Z, const int64_t* Z_dev, double* loss_trace,
                             fm_stream stream);
 
-/* Failed grid barriers of fm_epipolar_solve launches on this scene since the
- * last call (host value in *failures), then cleared.  A barrier wait is
+/* Failed grid barriers of fm_epipolar_solve and fm_translation_solve launches
+ * on this scene since the last call (host value in *failures), then cleared.  A barrier wait is
  * bounded (about a second); if it expires, the launch stops at once and its
  * results are invalid.  Synchronises the device.  Not expected to be nonzero:
  * the cooperative launch makes every workgroup resident. */
 fm_status fm_solve_barrier_failures(fm_ctx* ctx, fm_scene* scene, int64_t* failures);
+
+/* ------------------------------------------------------------------ translation averaging */
+
+/* Global translation averaging, the stage before epipolar adjustment
+ * (Sec. 3.3 "Global Translation", eq. global-translation-objective, and the
+ * appendix on multiple initialisations), on the scene's pair graph (its
+ * matches are not used):
+ *   target   d_n = o^{i->j} = -R_j^T t^{i->j}: world-to-camera rotation R_j of
+ *            the pair's second camera and the pair's unit relative
+ *            translation t^{i->j} (camera j's frame);
+ *   loss     L_t(o) = (1/P) sum_n | (o_j - o_i)/|o_j - o_i| - d_n |_1 over the
+ *            camera centres o; the L1 subgradient takes sign(0) = 0, and a
+ *            pair whose two centres coincide adds nothing (P still counts it).
+ * Independent runs (different initialisations) are processed together:
+ * `runs` (1..64) copies of the centres laid out [runs, N, 3] float32.  The
+ * calls below keep a per-scene workspace sized for the largest `runs` seen;
+ * a call with more runs than before synchronises the device and grows it. */
+
+/* dirs [P,3] float32 = -R_j^T t_rel[n] for each pair n, with R_j the
+ * Gram-Schmidt rotation of params[j] (a1, a2; t ignored), params [N,9]
+ * float32, t_rel [P,3] float32.  Float64 arithmetic. */
+fm_status fm_translation_directions(fm_ctx* ctx, fm_scene* scene, const float* params,
+                                    const float* t_rel, float* dirs, fm_stream stream);
+
+/* L_t and its gradient for each run at centres [runs,N,3]:
+ *   loss [runs] double (NULL = not written): the float32-rounded pair terms
+ *        summed in float64;
+ *   grad [runs,N,3] float32 (NULL = not written): per pair
+ *        dL/ds = (I - u u^T) sign(u - d_n) / (P |s|), s = o_j - o_i, u = s/|s|
+ *        (float64, stored float32), added to camera j and subtracted from
+ *        camera i, summed per camera over its pairs in a fixed order. */
+fm_status fm_translation_loss_grad(fm_ctx* ctx, fm_scene* scene, const float* dirs, int32_t runs,
+                                   const float* centres, double* loss, float* grad, fm_stream stream);
+
+/* K iterations of {gradient as fm_translation_loss_grad, Adam update of the
+ * centres} for every run, in ONE persistent cooperative kernel (grid
+ * barriers between the per-pair and per-camera phases, as fm_epipolar_solve).
+ * centres, m, v [runs,N,3] float32 are updated in place.  `cfg` (host) as for
+ * fm_epipolar_solve, with lr_t the centres' initial rate (lr_rot unused).
+ * loss_trace [runs,K] double receives L_t of each run before each update
+ * (NULL = not written; tracing adds a workgroup reduction per run and
+ * iteration).  The centres do not depend on cfg->blocks. */
+fm_status fm_translation_solve(fm_ctx* ctx, fm_scene* scene, const float* dirs, int32_t runs,
+                               float* centres, float* m, float* v, int32_t K, const fm_adam_cfg* cfg,
+                               double* loss_trace, fm_stream stream);
+
+/* Merge of the runs (appendix on multiple initialisations): every run is
+ * moved to its centroid and scaled to unit mean distance from it (a run
+ * whose centres all coincide is only moved); each camera takes its aligned
+ * centre from the run in which the mean L1 term of the camera's pairs is
+ * lowest (the lowest run index among equals; a camera in no pair scores 0
+ * and takes run 0).
+ *   merged   [N,3] float32 (required);
+ *   choice   [N] int32 run taken per camera (NULL = not written);
+ *   cam_loss [runs,N] double the per-camera mean terms (NULL = not written).
+ * Float64 arithmetic. */
+fm_status fm_translation_merge(fm_ctx* ctx, fm_scene* scene, const float* dirs, int32_t runs,
+                               const float* centres, float* merged, int32_t* choice, double* cam_loss,
+                               fm_stream stream);
 
 /* ------------------------------------------------------------------ a9: learned weights */
 
@@ -240,7 +299,9 @@ fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_m
  * bracketed by HIP events recorded on the launch's stream.
  *   FM_K_GRAM 0 (Gram / reweight pass over the matches), FM_K_SOLVE 1 (fused
  *   persistent loop), FM_K_ESSENTIALS 2, FM_K_FINALIZE 3, FM_K_PAIR 4 and
- *   FM_K_CAMERA 5 (the two kernels of fm_epipolar_loss_grad).
+ *   FM_K_CAMERA 5 (the two kernels of fm_epipolar_loss_grad), FM_K_TA_SOLVE 6
+ *   (persistent translation loop), FM_K_TA_PAIR 7 and FM_K_TA_CAMERA 8 (the
+ *   two kernels of fm_translation_loss_grad).
  * fm_profile_enable synchronises the device and clears earlier records;
  * fm_profile_read waits for the recorded events and returns the summed
  * elapsed milliseconds and the launch count of one kernel (host outputs). */

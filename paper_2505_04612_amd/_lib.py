@@ -25,8 +25,9 @@ EXPORTS = [
     "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve", "fm_solve_barrier_failures",
     "fm_profile_enable", "fm_profile_read",
     "fm_match_features", "fm_mlp_forward", "fm_mlp_backward",
+    "fm_translation_directions", "fm_translation_loss_grad", "fm_translation_solve", "fm_translation_merge",
 ]
-K_GRAM, K_SOLVE, K_ESSENTIALS, K_FINALIZE, K_PAIR, K_CAMERA = range(6)
+K_GRAM, K_SOLVE, K_ESSENTIALS, K_FINALIZE, K_PAIR, K_CAMERA, K_TA_SOLVE, K_TA_PAIR, K_TA_CAMERA = range(9)
 
 
 class FastMapError(RuntimeError):
@@ -79,6 +80,10 @@ _SIGNATURES = {
     "fm_mlp_forward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _F, _P, _P, _P]),
     "fm_mlp_backward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(MlpGrad), _P]),
     "fm_profile_read": (_S, [_P, _S, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "fm_translation_directions": (_S, [_P, _P, _P, _P, _P, _P]),
+    "fm_translation_loss_grad": (_S, [_P, _P, _P, _I32, _P, _P, _P, _P]),
+    "fm_translation_solve": (_S, [_P, _P, _P, _I32, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _P, _P]),
+    "fm_translation_merge": (_S, [_P, _P, _P, _I32, _P, _P, _P, _P, _P]),
 }
 
 _lib = None

@@ -281,6 +281,74 @@ def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: tor
         ctypes.byref(cfg), float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss_trace), _stream()))
 
 
+# ------------------------------------------------------------------ translation averaging
+
+def _runs_of(scene: Scene, centres: torch.Tensor) -> int:
+    if centres.ndim != 3 or centres.shape[1:] != (scene.num_cams, 3):
+        raise ValueError(f"centres: expected [runs, {scene.num_cams}, 3], got {tuple(centres.shape)}")
+    return int(centres.shape[0])
+
+
+def translation_directions(scene: Scene, params: torch.Tensor, t_rel: torch.Tensor) -> torch.Tensor:
+    """Targets -R_j^T t_rel per pair [P,3] float32 (R_j from params' 6D rotation)."""
+    dev = scene.ctx.device
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    _require(t_rel, torch.float32, (scene.num_pairs, 3), "t_rel", dev)
+    d = torch.empty((scene.num_pairs, 3), dtype=torch.float32, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_translation_directions(scene.ctx.handle, scene.handle, _ptr(params),
+                                                                    _ptr(t_rel), _ptr(d), _stream()))
+    return d
+
+
+def translation_loss_grad(scene: Scene, dirs: torch.Tensor, centres: torch.Tensor, want_loss: bool = True,
+                          want_grad: bool = True):
+    """(loss [runs] float64 | None, grad [runs,N,3] float32 | None) of L_t."""
+    dev = scene.ctx.device
+    R = _runs_of(scene, centres)
+    _require(dirs, torch.float32, (scene.num_pairs, 3), "dirs", dev)
+    _require(centres, torch.float32, (R, scene.num_cams, 3), "centres", dev)
+    loss = torch.empty(R, dtype=torch.float64, device=dev) if want_loss else None
+    grad = torch.empty((R, scene.num_cams, 3), dtype=torch.float32, device=dev) if want_grad else None
+    check(scene.ctx.handle, scene.ctx.lib.fm_translation_loss_grad(scene.ctx.handle, scene.handle, _ptr(dirs), R,
+                                                                   _ptr(centres), _ptr(loss), _ptr(grad), _stream()))
+    return loss, grad
+
+
+def translation_solve(scene: Scene, dirs: torch.Tensor, centres: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                      K: int, lr: float, lr_final_frac: float, lr_step0: int = 0, lr_total: int | None = None,
+                      adam_step0: int = 0, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-12,
+                      loss_trace: torch.Tensor | None = None, blocks: int = 0) -> None:
+    """K fused Adam iterations on L_t for every run (one persistent kernel);
+    centres, m, v [runs,N,3] are updated in place; loss_trace [runs,K] optional."""
+    dev = scene.ctx.device
+    R = _runs_of(scene, centres)
+    _require(dirs, torch.float32, (scene.num_pairs, 3), "dirs", dev)
+    for name, t in (("centres", centres), ("m", m), ("v", v)):
+        _require(t, torch.float32, (R, scene.num_cams, 3), name, dev)
+    if loss_trace is not None:
+        _require(loss_trace, torch.float64, (R, K), "loss_trace", dev)
+    cfg = _lib.AdamCfg(0.0, lr, lr_final_frac, beta1, beta2, eps, lr_step0, lr_total if lr_total else K,
+                       adam_step0, blocks)
+    check(scene.ctx.handle, scene.ctx.lib.fm_translation_solve(
+        scene.ctx.handle, scene.handle, _ptr(dirs), R, _ptr(centres), _ptr(m), _ptr(v), int(K), ctypes.byref(cfg),
+        _ptr(loss_trace), _stream()))
+
+
+def translation_merge(scene: Scene, dirs: torch.Tensor, centres: torch.Tensor):
+    """(merged [N,3] float32, choice [N] int32, cam_loss [runs,N] float64)."""
+    dev = scene.ctx.device
+    R = _runs_of(scene, centres)
+    _require(dirs, torch.float32, (scene.num_pairs, 3), "dirs", dev)
+    _require(centres, torch.float32, (R, scene.num_cams, 3), "centres", dev)
+    merged = torch.empty((scene.num_cams, 3), dtype=torch.float32, device=dev)
+    choice = torch.empty(scene.num_cams, dtype=torch.int32, device=dev)
+    cam = torch.empty((R, scene.num_cams), dtype=torch.float64, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_translation_merge(scene.ctx.handle, scene.handle, _ptr(dirs), R,
+                                                               _ptr(centres), _ptr(merged), _ptr(choice), _ptr(cam),
+                                                               _stream()))
+    return merged, choice, cam
+
+
 # ------------------------------------------------------------------ a9: learned weights
 
 MLP_SHAPES = {"W1": (64, 3), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (1, 64), "b3": (1,)}

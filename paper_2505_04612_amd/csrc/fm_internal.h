@@ -34,7 +34,7 @@ constexpr int kKeptSlots = 256;
 
 // Kernel identifiers of the optional launch timing (fm_profile_*).
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
-       FM_K_COUNT = 6 };
+       FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_COUNT = 9 };
 
 struct fm_timing {
   int kernel;
@@ -104,6 +104,13 @@ struct fm_scene {
   unsigned* bar = nullptr;        // [128] solve grid barrier, one 128-B line each: arrival count, generation,
                                   // failure flag of the running launch, failure total since the last query
   int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
+  // translation averaging workspace, grown on demand by the translation calls
+  int32_t ta_runs_cap = 0;        // runs the workspace holds
+  int64_t ta_part_cap = 0;        // loss partials per run
+  void* ta_rec = nullptr;         // [ta_runs_cap, P] float4 per-pair records: dL/ds and the pair's L1 term
+  double* ta_part = nullptr;      // [ta_runs_cap, ta_part_cap] per-workgroup loss partials
+  double* ta_stats = nullptr;     // [ta_runs_cap, 4] centroid and mean norm of each run
+  int ta_coop_blocks = 0;         // max co-resident blocks of the translation loop
 };
 
 // Error reporting helpers: set ctx->err and return the status.
@@ -200,3 +207,97 @@ __device__ __host__ constexpr int mono_q(int a, int c) {
   return (a == c) ? (a == 0 ? 0 : (a == 1 ? 2 : 5))
                   : ((a + c) == 1 ? 1 : ((a + c) == 2 ? 3 : 4));
 }
+
+// Incidence list of one camera as one 16-lane row reads it: the list bounds
+// and this lane's first four entries (q = lo + l16 + 16 j; -1 past the end).
+// Static during a solve, so the fused loop reads it once.
+struct RowList {
+  int lo, hi, it[4];
+};
+
+__device__ inline RowList row_list(const int32_t* __restrict__ cam_ptr, const int32_t* __restrict__ cam_items, int c,
+                                   int l16) {
+  RowList L;
+  L.lo = cam_ptr[c];
+  L.hi = cam_ptr[c + 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) L.it[j] = L.lo + l16 + 16 * j < L.hi ? cam_items[L.lo + l16 + 16 * j] : -1;
+  return L;
+}
+
+// Deterministic block sum of one double per thread (fixed tree).
+__device__ inline double block_sum(double v, double* lds) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+  __syncthreads();
+  return t;
+}
+
+// One Adam update (Kingma & Ba, bias-corrected) of a float32 value; the
+// arithmetic is float64, the stored moments float32.
+__device__ inline float adam_update(float p, float g, float& m, float& v, double lr, double b1, double b2,
+                                    double eps, double bc1, double bc2) {
+  const double md = b1 * (double)m + (1.0 - b1) * (double)g;
+  const double vd = b2 * (double)v + (1.0 - b2) * (double)g * (double)g;
+  m = (float)md;
+  v = (float)vd;
+  return (float)((double)p - lr * (md / bc1) / (sqrt(vd / bc2) + eps));
+}
+
+// Grid barrier of the persistent solves (epipolar and translation loops).
+// Thread 0 of each workgroup makes the workgroup's writes visible
+// (agent-scope release), counts itself in, and waits for the generation word
+// to move; the last to arrive acquires the others' writes, re-arms the
+// counter and moves the generation.  All atomics are relaxed and
+// agent-scoped; the fences carry the ordering.  The wait is bounded: if it
+// expires (the workgroups were not all resident), the launch's failure flag
+// and the scene's failure total are raised, every later barrier of the
+// launch returns at once and the host reads the total with
+// fm_solve_barrier_failures.
+constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
+
+__device__ inline void grid_barrier(unsigned* __restrict__ bar) {
+  unsigned* count = bar;
+  unsigned* gen = bar + 32;
+  unsigned* fail = bar + 64;
+  __syncthreads();
+  if (threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      bool moved = false;
+      for (unsigned outer = 0; outer < kBarSpinOuter && !moved; ++outer) {
+#pragma unroll 1
+        for (int i = 0; i < 256; ++i) {
+          if (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) {
+            moved = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (!moved && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      }
+      if (!moved) {
+        __hip_atomic_fetch_add(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar + 96, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Clears the arrival count and the launch's failure flag of a grid barrier
+// before a persistent launch (iterate.hip).
+hipError_t fm_bar_reset(unsigned* bar, hipStream_t st);

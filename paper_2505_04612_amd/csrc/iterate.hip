@@ -140,20 +140,6 @@ __device__ inline double pair_phase(const float* params, const double* rot, cons
   return sum;
 }
 
-// Deterministic block sum of one double per thread (fixed tree).
-__device__ inline double block_sum(double v, double* lds) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
-  if (lane == 0) lds[wv] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
-  __syncthreads();
-  return t;
-}
-
 template <int CTRL>
 __device__ inline double dpp_mov_d(double v) {
   const long long bits = __double_as_longlong(v);
@@ -258,23 +244,6 @@ __device__ inline void row_sum12(double acc[12], int lane) {
   const int base = lane & ~15;
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = __shfl(v, base + k + k / 3);
-}
-
-// Incidence list of one camera as one 16-lane row reads it: the list bounds
-// and this lane's first four entries (q = lo + l16 + 16 j; -1 past the end).
-// Static during a solve, so the fused loop reads it once.
-struct RowList {
-  int lo, hi, it[4];
-};
-
-__device__ inline RowList row_list(const int32_t* __restrict__ cam_ptr, const int32_t* __restrict__ cam_items, int c,
-                                   int l16) {
-  RowList L;
-  L.lo = cam_ptr[c];
-  L.hi = cam_ptr[c + 1];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) L.it[j] = L.lo + l16 + 16 * j < L.hi ? cam_items[L.lo + l16 + 16 * j] : -1;
-  return L;
 }
 
 // Summed records of one camera in every lane of its row.
@@ -415,15 +384,6 @@ extern "C" fm_status fm_epipolar_loss_grad(fm_ctx* ctx, fm_scene* s, const void*
 
 // ------------------------------------------------------------------ Adam
 
-__device__ inline float adam_update(float p, float g, float& m, float& v, double lr, double b1, double b2,
-                                    double eps, double bc1, double bc2) {
-  const double md = b1 * (double)m + (1.0 - b1) * (double)g;
-  const double vd = b2 * (double)v + (1.0 - b2) * (double)g * (double)g;
-  m = (float)md;
-  v = (float)vd;
-  return (float)((double)p - lr * (md / bc1) / (sqrt(vd / bc2) + eps));
-}
-
 __global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, const float* __restrict__ lr, int lr_stride, double b1, double b2,
                        double eps, double bc1, double bc2) {
@@ -456,53 +416,6 @@ extern "C" fm_status fm_adam_step(fm_ctx* ctx, int64_t n, float* p, const float*
 
 // ------------------------------------------------------------------ fused persistent solve
 
-// Grid barrier of the persistent solve.  Thread 0 of each workgroup makes
-// the workgroup's writes visible (agent-scope release), counts itself in,
-// and waits for the generation word to move; the last to arrive acquires the
-// others' writes, re-arms the counter and moves the generation.  All atomics
-// are relaxed and agent-scoped; the fences carry the ordering.  The wait is
-// bounded: if it expires (the workgroups were not all resident), the
-// launch's failure flag and the scene's failure total are raised, every later
-// barrier of the launch returns at once and the host reads the total with
-// fm_solve_barrier_failures.
-constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
-
-__device__ inline void grid_barrier(unsigned* __restrict__ bar) {
-  unsigned* count = bar;
-  unsigned* gen = bar + 32;
-  unsigned* fail = bar + 64;
-  __syncthreads();
-  if (threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      bool moved = false;
-      for (unsigned outer = 0; outer < kBarSpinOuter && !moved; ++outer) {
-#pragma unroll 1
-        for (int i = 0; i < 256; ++i) {
-          if (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) {
-            moved = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        if (!moved && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-      }
-      if (!moved) {
-        __hip_atomic_fetch_add(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(bar + 96, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-}
-
 // Re-arms the barrier before a launch: arrival count and the launch's
 // failure flag (a launch that ended on a failed barrier leaves them set).
 __global__ void k_bar_reset(unsigned* __restrict__ bar) {
@@ -510,6 +423,11 @@ __global__ void k_bar_reset(unsigned* __restrict__ bar) {
     bar[0] = 0u;
     bar[64] = 0u;
   }
+}
+
+hipError_t fm_bar_reset(unsigned* bar, hipStream_t st) {
+  hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, bar);
+  return hipGetLastError();
 }
 
 struct SolveArgs {

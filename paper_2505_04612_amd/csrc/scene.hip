@@ -243,6 +243,9 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->loss_part);
   (void)hipFree(s->rot);
   (void)hipFree(s->bar);
+  (void)hipFree(s->ta_rec);
+  (void)hipFree(s->ta_part);
+  (void)hipFree(s->ta_stats);
   delete s;
 }
 

@@ -1,0 +1,501 @@
+// Global translation averaging (FastMap, arXiv 2505.04612, Sec. 3.3 "Global
+// Translation", eq. global-translation-objective; App. "Multiple
+// Initializations") on a scene's pair graph.
+//
+// Independent runs share every launch: centres and Adam moments are laid out
+// [runs, N, 3] and the per-pair records [runs, P] (float4: dL/ds and the
+// pair's L1 term), so a thread loads its pair's cameras and target once and
+// evaluates the pair for every run, and a 16-lane row reads its camera's
+// incidence list once and sums it for every run.  Every sum over a camera's
+// pairs runs in the same lane order whatever the grid, so the centres a solve
+// produces do not depend on the launch shape.
+#include "fm_internal.h"
+
+#include <cmath>
+
+namespace {
+
+constexpr int kTaMaxRuns = 64;
+
+// The L1 term of eq. global-translation-objective for one pair, float64:
+// s = o_j - o_i, u = s/|s|, |u - d|_1.  With `g` it also writes
+// dL/ds = (I - u u^T) sign(u - d) * invP / |s| (sign(0) = 0).  A pair whose
+// centres coincide has no direction: term and record are 0.
+__device__ inline double ta_term(const float* __restrict__ oi, const float* __restrict__ oj, const double d[3],
+                                 double invP, double* g) {
+  double s[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = (double)oj[k] - (double)oi[k];
+  const double ns = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+  if (!(ns > 0.0)) {
+    if (g) g[0] = g[1] = g[2] = 0.0;
+    return 0.0;
+  }
+  const double r = 1.0 / ns;
+  double u[3], sg[3], term = 0.0, ug = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u[k] = s[k] * r;
+    const double e = u[k] - d[k];
+    term += fabs(e);
+    sg[k] = e > 0.0 ? invP : (e < 0.0 ? -invP : 0.0);
+    ug += u[k] * sg[k];
+  }
+  if (g) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = (sg[k] - u[k] * ug) * r;
+  }
+  return term;
+}
+
+__device__ inline void load_dir(const float* __restrict__ dirs, int64_t n, double d[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) d[k] = (double)dirs[3 * n + k];
+}
+
+// One pair for every run: records [runs, P].
+__device__ inline void ta_pair_runs(const float* __restrict__ centres, int32_t N, int runs, int64_t P, int64_t n,
+                                    int ci, int cj, const double d[3], double invP, float4* __restrict__ rec) {
+  const int64_t run_stride = (int64_t)N * 3;
+  for (int r = 0; r < runs; ++r) {
+    const float* o = centres + r * run_stride;
+    double g[3];
+    const double term = ta_term(o + 3 * (int64_t)ci, o + 3 * (int64_t)cj, d, invP, g);
+    rec[r * P + n] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)term);
+  }
+}
+
+// Per-run workgroup sums of the pair terms this workgroup's threads wrote
+// (each thread re-reads its own records): part[r * stride + blockIdx.x].
+__device__ inline void ta_loss_partials(const float4* __restrict__ rec, int64_t P, int runs, double* __restrict__ part,
+                                        int64_t stride, int64_t gtid, int64_t gsize, double* lds) {
+  for (int r = 0; r < runs; ++r) {
+    double v = 0.0;
+    for (int64_t n = gtid; n < P; n += gsize) v += (double)rec[r * P + n].w;
+    const double t = block_sum(v, lds);
+    if (threadIdx.x == 0) part[r * stride + blockIdx.x] = t;
+  }
+}
+
+// Gradient of one camera for run r, in every lane of its 16-lane row: the
+// records of the camera's pairs, +dL/ds where it is the second camera of
+// the pair and -dL/ds where it is the first, summed lane-strided over the
+// incidence list and then across the row.
+__device__ inline void ta_row_grad(const RowList& L, const int32_t* __restrict__ cam_items,
+                                   const float4* __restrict__ rec_r, int l16, double acc[3]) {
+  acc[0] = acc[1] = acc[2] = 0.0;
+  auto add = [&](int item) {
+    const float4 q = rec_r[item >> 1];
+    const double sgn = (item & 1) ? 1.0 : -1.0;
+    acc[0] += sgn * (double)q.x;
+    acc[1] += sgn * (double)q.y;
+    acc[2] += sgn * (double)q.z;
+  };
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (L.it[j] >= 0) add(L.it[j]);
+  for (int q = L.lo + 64 + l16; q < L.hi; q += 16) add(cam_items[q]);
+#pragma unroll
+  for (int s = 8; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] += __shfl_xor(acc[k], s);
+  }
+}
+
+__device__ inline double pick3(const double a[3], int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
+
+// ------------------------------------------------------------------ target directions
+
+__global__ __launch_bounds__(kBlock) void k_ta_directions(const float* __restrict__ params,
+                                                          const int32_t* __restrict__ cams,
+                                                          const float* __restrict__ t_rel, int64_t P,
+                                                          float* __restrict__ dirs) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P) return;
+  double a1[3], a2[3], t[3], R[3][3];
+  load_pose(params, cams[2 * n + 1], a1, a2, t);
+  gs_matrix(gs_forward(a1, a2), R);
+  double tr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tr[k] = (double)t_rel[3 * n + k];
+  // -R_j^T t: column k of R dotted with t
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dirs[3 * n + k] = (float)(-(R[0][k] * tr[0] + R[1][k] * tr[1] + R[2][k] * tr[2]));
+}
+
+// ------------------------------------------------------------------ standalone loss + gradient
+
+__global__ __launch_bounds__(kBlock) void k_ta_pair(const float* __restrict__ centres, const int32_t* __restrict__ cams,
+                                                    const float* __restrict__ dirs, int64_t P, int32_t N, int runs,
+                                                    double invP, float4* __restrict__ rec, double* __restrict__ part,
+                                                    int64_t part_stride) {
+  __shared__ double lds[kBlock / 64];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gsize = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t n = gtid; n < P; n += gsize) {
+    double d[3];
+    load_dir(dirs, n, d);
+    ta_pair_runs(centres, N, runs, P, n, cams[2 * n], cams[2 * n + 1], d, invP, rec);
+  }
+  if (part) ta_loss_partials(rec, P, runs, part, part_stride, gtid, gsize, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ta_camera(const int32_t* __restrict__ cam_ptr,
+                                                      const int32_t* __restrict__ cam_items,
+                                                      const float4* __restrict__ rec, int64_t P, int32_t N, int runs,
+                                                      float* __restrict__ grad) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = gtid >> 4;
+  const int l16 = (int)(gtid & 15);
+  if (c >= N) return;   // whole rows leave together: the row exchanges stay within live rows
+  const RowList L = row_list(cam_ptr, cam_items, (int)c, l16);
+  for (int r = 0; r < runs; ++r) {
+    double acc[3];
+    ta_row_grad(L, cam_items, rec + r * P, l16, acc);
+    if (l16 < 3) grad[(r * (int64_t)N + c) * 3 + l16] = (float)pick3(acc, l16);
+  }
+}
+
+__global__ void k_ta_loss_final(const double* __restrict__ part, int64_t stride, int64_t nblocks, int runs,
+                                double invP, double* __restrict__ loss) {
+  const int r = threadIdx.x;
+  if (r >= runs) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nblocks; ++b) s += part[r * stride + b];
+  loss[r] = s * invP;
+}
+
+// ------------------------------------------------------------------ fused persistent loop
+
+struct TaArgs {
+  float* centres;
+  float* m;
+  float* v;
+  const int32_t* cams;
+  const float* dirs;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  float4* rec;
+  double* part;
+  int64_t part_stride;
+  double* trace;
+  unsigned* bar;
+  int64_t P;
+  int32_t N;
+  int32_t runs;
+  int32_t K;
+  double invP, lr, log_frac, b1, b2, eps;
+  int64_t lr_step0, lr_total, adam_step0;
+};
+
+__global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
+  __shared__ double lds[kSolveBlock / 64];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const int row = lane >> 4, l16 = lane & 15;
+  // static data of this thread's first pair and this row's first camera,
+  // read once instead of once per iteration
+  int ci0 = 0, cj0 = 0;
+  double d0[3] = {0.0, 0.0, 0.0};
+  if (gtid < a.P) {
+    ci0 = a.cams[2 * gtid];
+    cj0 = a.cams[2 * gtid + 1];
+    load_dir(a.dirs, gtid, d0);
+  }
+  const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
+  RowList L0 = {0, 0, {-1, -1, -1, -1}};
+  if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
+  for (int k = 0; k < a.K; ++k) {
+    if (gtid < a.P) ta_pair_runs(a.centres, a.N, a.runs, a.P, gtid, ci0, cj0, d0, a.invP, a.rec);
+    for (int64_t n = gtid + gsize; n < a.P; n += gsize) {
+      double d[3];
+      load_dir(a.dirs, n, d);
+      ta_pair_runs(a.centres, a.N, a.runs, a.P, n, a.cams[2 * n], a.cams[2 * n + 1], d, a.invP, a.rec);
+    }
+    if (a.trace) ta_loss_partials(a.rec, a.P, a.runs, a.part, a.part_stride, gtid, gsize, lds);
+    grid_barrier(a.bar);
+    if (a.trace && gtid == 0) {
+      for (int r = 0; r < a.runs; ++r) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) s += a.part[r * a.part_stride + b];
+        a.trace[(int64_t)r * a.K + k] = s * a.invP;
+      }
+    }
+    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
+    const double step = (double)(a.adam_step0 + k + 1);
+    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    // the loop bound is uniform over the wavefront (rows past N idle with an
+    // empty list), so the row exchanges run with every lane present
+    for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
+      const int64_t c = c0 + row;
+      const bool live = c < a.N;
+      const RowList L = c0 == 4 * gwave ? L0 : (live ? row_list(a.cam_ptr, a.cam_items, (int)c, l16)
+                                                     : RowList{0, 0, {-1, -1, -1, -1}});
+      for (int r = 0; r < a.runs; ++r) {
+        const int64_t idx = (r * (int64_t)a.N + c) * 3 + l16;
+        float p = 0.0f, mq = 0.0f, vq = 0.0f;
+        if (live && l16 < 3) {
+          p = a.centres[idx];
+          mq = a.m[idx];
+          vq = a.v[idx];
+        }
+        double acc[3];
+        ta_row_grad(L, a.cam_items, a.rec + r * a.P, l16, acc);
+        if (live && l16 < 3) {
+          a.centres[idx] = adam_update(p, (float)pick3(acc, l16), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+          a.m[idx] = mq;
+          a.v[idx] = vq;
+        }
+      }
+    }
+    grid_barrier(a.bar);
+  }
+}
+
+// ------------------------------------------------------------------ merge of runs
+
+// Centroid and mean distance to it of each run's centres (one workgroup per
+// run, float64, fixed-order sums): stats[r] = (cx, cy, cz, mean norm).
+__global__ __launch_bounds__(kBlock) void k_ta_stats(const float* __restrict__ centres, int32_t N,
+                                                     double* __restrict__ stats) {
+  __shared__ double lds[kBlock / 64];
+  __shared__ double cen[3];
+  const float* o = centres + (int64_t)blockIdx.x * N * 3;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int c = threadIdx.x; c < N; c += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k] += (double)o[3 * c + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = block_sum(s[k], lds);
+    if (threadIdx.x == 0) cen[k] = t / (double)N;
+  }
+  __syncthreads();
+  double sn = 0.0;
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    const double dx = (double)o[3 * c] - cen[0], dy = (double)o[3 * c + 1] - cen[1], dz = (double)o[3 * c + 2] - cen[2];
+    sn += sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  const double t = block_sum(sn, lds);
+  if (threadIdx.x == 0) {
+    double* st = stats + 4 * (int64_t)blockIdx.x;
+    st[0] = cen[0];
+    st[1] = cen[1];
+    st[2] = cen[2];
+    st[3] = t / (double)N;
+  }
+}
+
+// Per camera (one 16-lane row): the mean L1 term of its pairs in every run,
+// the run with the lowest mean (the first among equals), and that run's
+// centre moved to its run's centroid and scaled to unit mean norm.
+__global__ __launch_bounds__(kBlock) void k_ta_merge(const float* __restrict__ centres, const int32_t* __restrict__ cams,
+                                                     const float* __restrict__ dirs, const int32_t* __restrict__ cam_ptr,
+                                                     const int32_t* __restrict__ cam_items,
+                                                     const double* __restrict__ stats, int32_t N, int runs,
+                                                     double* __restrict__ cam_loss, int32_t* __restrict__ choice,
+                                                     float* __restrict__ merged) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = gtid >> 4;
+  const int l16 = (int)(gtid & 15);
+  if (c >= N) return;   // whole rows leave together
+  const int lo = cam_ptr[c], hi = cam_ptr[c + 1];
+  const double cnt = (double)(hi - lo);
+  int best = 0;
+  double best_v = 0.0;
+  for (int r = 0; r < runs; ++r) {
+    const float* o = centres + (int64_t)r * N * 3;
+    double acc = 0.0;
+    for (int q = lo + l16; q < hi; q += 16) {
+      const int64_t n = cam_items[q] >> 1;
+      double d[3];
+      load_dir(dirs, n, d);
+      acc += ta_term(o + 3 * (int64_t)cams[2 * n], o + 3 * (int64_t)cams[2 * n + 1], d, 0.0, nullptr);
+    }
+#pragma unroll
+    for (int s = 8; s >= 1; s >>= 1) acc += __shfl_xor(acc, s);
+    const double mean = hi > lo ? acc / cnt : 0.0;
+    if (cam_loss && l16 == 0) cam_loss[(int64_t)r * N + c] = mean;
+    if (r == 0 || mean < best_v) {
+      best = r;
+      best_v = mean;
+    }
+  }
+  if (l16 < 3) {
+    const double* st = stats + 4 * best;
+    const double x = (double)centres[((int64_t)best * N + c) * 3 + l16] - st[l16];
+    merged[c * 3 + l16] = (float)(st[3] > 0.0 ? x / st[3] : x);
+  }
+  if (choice && l16 == 0) choice[c] = best;
+}
+
+// ------------------------------------------------------------------ host side
+
+fm_status ta_check(fm_ctx* ctx, fm_scene* s, const char* fn) {
+  if (!s) return fm_fail(ctx, FM_EINVAL, "%s: scene is NULL", fn);
+  if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "%s: scene belongs to another context", fn);
+  return FM_OK;
+}
+
+fm_status ta_check_runs(fm_ctx* ctx, const char* fn, int32_t runs) {
+  if (runs < 1 || runs > kTaMaxRuns) return fm_fail(ctx, FM_EINVAL, "%s: runs must be in [1, %d]", fn, kTaMaxRuns);
+  return FM_OK;
+}
+
+// Workspace for `runs` runs (records, loss partials, run statistics), grown
+// on demand: a larger request synchronises the device and reallocates.
+fm_status ta_reserve(fm_ctx* ctx, fm_scene* s, int runs) {
+  if (s->ta_coop_blocks <= 0) {
+    int per_cu = 0;
+    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ta_solve, kSolveBlock, 0));
+    s->ta_coop_blocks = per_cu * ctx->num_cu;
+    if (s->ta_coop_blocks <= 0) return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative translation kernel");
+  }
+  if (runs <= s->ta_runs_cap) return FM_OK;
+  int64_t part = (int64_t)grid_for(s->P, kBlock);
+  if (part < s->ta_coop_blocks) part = s->ta_coop_blocks;
+  FM_HIP_TRY(ctx, hipDeviceSynchronize());
+  (void)hipFree(s->ta_rec);
+  (void)hipFree(s->ta_part);
+  (void)hipFree(s->ta_stats);
+  s->ta_rec = nullptr;
+  s->ta_part = nullptr;
+  s->ta_stats = nullptr;
+  s->ta_runs_cap = 0;
+  const int64_t P1 = s->P > 0 ? s->P : 1;
+  if (hipMalloc(&s->ta_rec, sizeof(float4) * runs * P1) != hipSuccess ||
+      hipMalloc(&s->ta_part, sizeof(double) * runs * part) != hipSuccess ||
+      hipMalloc(&s->ta_stats, sizeof(double) * 4 * runs) != hipSuccess) {
+    (void)hipGetLastError();
+    return fm_fail(ctx, FM_ENOMEM, "translation workspace for %d runs: allocation failed", runs);
+  }
+  s->ta_part_cap = part;
+  s->ta_runs_cap = runs;
+  return FM_OK;
+}
+
+}  // namespace
+
+extern "C" fm_status fm_translation_directions(fm_ctx* ctx, fm_scene* s, const float* params, const float* t_rel,
+                                               float* dirs, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ta_check(ctx, s, "fm_translation_directions");
+  if (rc != FM_OK) return rc;
+  if (s->P == 0) return FM_OK;
+  if (!params || !t_rel || !dirs) return fm_fail(ctx, FM_EINVAL, "fm_translation_directions: NULL argument");
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_ta_directions, dim3(grid_for(s->P, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, params,
+                     s->pair_cams, t_rel, s->P, dirs);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
+}
+
+extern "C" fm_status fm_translation_loss_grad(fm_ctx* ctx, fm_scene* s, const float* dirs, int32_t runs,
+                                              const float* centres, double* loss, float* grad, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ta_check(ctx, s, "fm_translation_loss_grad");
+  if (rc != FM_OK) return rc;
+  if ((rc = ta_check_runs(ctx, "fm_translation_loss_grad", runs)) != FM_OK) return rc;
+  if ((s->P > 0 && !dirs) || (s->N > 0 && !centres))
+    return fm_fail(ctx, FM_EINVAL, "fm_translation_loss_grad: NULL argument");
+  if (!loss && !grad) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (s->P == 0) {
+    if (loss) FM_HIP_TRY(ctx, hipMemsetAsync(loss, 0, sizeof(double) * runs, st));
+    if (grad && s->N > 0) FM_HIP_TRY(ctx, hipMemsetAsync(grad, 0, sizeof(float) * 3 * runs * (size_t)s->N, st));
+    return FM_OK;
+  }
+  if ((rc = ta_reserve(ctx, s, runs)) != FM_OK) return rc;
+  const double invP = 1.0 / (double)s->P;
+  const unsigned gp = grid_for(s->P, kBlock);
+  {
+    fm_timed timer(ctx, FM_K_TA_PAIR, st);
+    hipLaunchKernelGGL(k_ta_pair, dim3(gp), dim3(kBlock), 0, st, centres, s->pair_cams, dirs, s->P, s->N, (int)runs,
+                       invP, reinterpret_cast<float4*>(s->ta_rec), loss ? s->ta_part : nullptr, s->ta_part_cap);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  if (loss) {
+    hipLaunchKernelGGL(k_ta_loss_final, dim3(1), dim3(64), 0, st, s->ta_part, s->ta_part_cap, (int64_t)gp, (int)runs,
+                       invP, loss);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  if (grad && s->N > 0) {
+    fm_timed timer(ctx, FM_K_TA_CAMERA, st);
+    hipLaunchKernelGGL(k_ta_camera, dim3(grid_for((int64_t)s->N * 16, kBlock)), dim3(kBlock), 0, st, s->cam_ptr,
+                       s->cam_items, reinterpret_cast<const float4*>(s->ta_rec), s->P, s->N, (int)runs, grad);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  return FM_OK;
+}
+
+extern "C" fm_status fm_translation_solve(fm_ctx* ctx, fm_scene* s, const float* dirs, int32_t runs, float* centres,
+                                          float* m, float* v, int32_t K, const fm_adam_cfg* cfg, double* loss_trace,
+                                          fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ta_check(ctx, s, "fm_translation_solve");
+  if (rc != FM_OK) return rc;
+  if ((rc = ta_check_runs(ctx, "fm_translation_solve", runs)) != FM_OK) return rc;
+  if (!cfg || (s->P > 0 && !dirs) || (s->N > 0 && (!centres || !m || !v)))
+    return fm_fail(ctx, FM_EINVAL, "fm_translation_solve: NULL argument");
+  if (K < 0) return fm_fail(ctx, FM_EINVAL, "fm_translation_solve: K < 0");
+  if (cfg->lr_total_steps <= 0 || cfg->lr_step0 < 0 || cfg->adam_step0 < 0 || !(cfg->lr_final_frac > 0.0f) ||
+      !(cfg->lr_t >= 0.0f) ||
+      !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f && cfg->eps >= 0.0f))
+    return fm_fail(ctx, FM_EINVAL, "fm_translation_solve: bad Adam configuration");
+  if (K == 0 || s->N == 0) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = ta_reserve(ctx, s, runs)) != FM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // sized like the epipolar loop: about one pair per thread or one 16-lane
+  // row per camera, capped at 16 workgroups while runs x P < 32k and at 192
+  // above, and at the co-resident limit
+  int64_t want = grid_for(s->P, kSolveBlock);
+  const int64_t want_c = grid_for((int64_t)s->N * 16, kSolveBlock);
+  if (want_c > want) want = want_c;
+  const int64_t cap = (int64_t)runs * s->P < 32768 ? 16 : 192;
+  if (want > cap) want = cap;
+  if (cfg->blocks > 0) want = cfg->blocks;
+  if (want < 1) want = 1;
+  if (want > s->ta_coop_blocks) want = s->ta_coop_blocks;
+  if (want > s->ta_part_cap) want = s->ta_part_cap;
+  TaArgs a;
+  a.centres = centres; a.m = m; a.v = v;
+  a.cams = s->pair_cams; a.dirs = dirs; a.cam_ptr = s->cam_ptr; a.cam_items = s->cam_items;
+  a.rec = reinterpret_cast<float4*>(s->ta_rec); a.part = s->ta_part; a.part_stride = s->ta_part_cap;
+  a.trace = loss_trace; a.bar = s->bar;
+  a.P = s->P; a.N = s->N; a.runs = runs; a.K = K;
+  a.invP = s->P > 0 ? 1.0 / (double)s->P : 0.0;
+  a.lr = cfg->lr_t; a.log_frac = log((double)cfg->lr_final_frac);
+  a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;
+  a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
+  void* args[] = {&a};
+  FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
+  fm_timed timer(ctx, FM_K_TA_SOLVE, st);
+  hipError_t e = hipLaunchCooperativeKernel((const void*)k_ta_solve, dim3((unsigned)want), dim3(kSolveBlock), args, 0, st);
+  if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+  return FM_OK;
+}
+
+extern "C" fm_status fm_translation_merge(fm_ctx* ctx, fm_scene* s, const float* dirs, int32_t runs,
+                                          const float* centres, float* merged, int32_t* choice, double* cam_loss,
+                                          fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ta_check(ctx, s, "fm_translation_merge");
+  if (rc != FM_OK) return rc;
+  if ((rc = ta_check_runs(ctx, "fm_translation_merge", runs)) != FM_OK) return rc;
+  if ((s->P > 0 && !dirs) || (s->N > 0 && (!centres || !merged)))
+    return fm_fail(ctx, FM_EINVAL, "fm_translation_merge: NULL argument");
+  if (s->N == 0) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = ta_reserve(ctx, s, runs)) != FM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_ta_stats, dim3(runs), dim3(kBlock), 0, st, centres, s->N, s->ta_stats);
+  FM_CHECK_LAUNCH(ctx);
+  hipLaunchKernelGGL(k_ta_merge, dim3(grid_for((int64_t)s->N * 16, kBlock)), dim3(kBlock), 0, st, centres,
+                     s->pair_cams, dirs, s->cam_ptr, s->cam_items, s->ta_stats, s->N, (int)runs, cam_loss, choice,
+                     merged);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
+}

@@ -1,0 +1,233 @@
+"""Translation averaging on the GPU (Sec. 3.3 "Global Translation"; appendix
+on multiple initialisations) against the FP64 oracle on the same stored
+inputs: target directions, loss and gradient for several runs, the fused
+persistent loop, the merge of runs, and the whole stage."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ea
+from oracle import translation as ta
+from paper_2505_04612_amd import synth
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx():
+    from paper_2505_04612_amd import api
+    return api.default_context()
+
+
+def _graph_scene(ctx, N, pairs):
+    """A scene with the pair graph only (no matches)."""
+    from paper_2505_04612_amd import api
+    P = len(pairs)
+    return api.Scene.from_numpy(ctx, N, pairs, np.zeros(P + 1, np.int64), np.zeros((0, 4)), torch.float32)
+
+
+def _random_graph(seed=11, N=1000, P=20_001):
+    """Ragged random pair graph: one hub camera in 300 pairs (its incidence
+    list runs past 64 entries), cameras 990..999 in no pair, the rest random."""
+    rng = np.random.default_rng(seed)
+    hub = np.stack([np.zeros(300, np.int64), rng.choice(np.arange(1, 990), 300, replace=False)], 1)
+    a = rng.integers(1, 990, size=P - 300)
+    b = rng.integers(1, 989, size=P - 300)
+    b = b + (b >= a)
+    pairs = np.concatenate([hub, np.stack([np.minimum(a, b), np.maximum(a, b)], 1)]).astype(np.int32)
+    return N, pairs
+
+
+def _inputs(sc, runs, seed=None):
+    inp = synth.translation_inputs(sc, runs=runs, seed=seed)
+    return inp
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return helpers.scene("tiny")
+
+
+@pytest.fixture(scope="module")
+def medium():
+    return helpers.scene("medium")
+
+
+def _scene_of(ctx, sc):
+    from paper_2505_04612_amd import api
+    P = len(sc.pairs)
+    return api.Scene.from_numpy(ctx, sc.R_gt.shape[0], sc.pairs, np.zeros(P + 1, np.int64), np.zeros((0, 4)),
+                                torch.float32)
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_directions_parity(name):
+    from paper_2505_04612_amd import api
+    ctx = _ctx()
+    sc = helpers.scene(name)
+    inp = _inputs(sc, 1)
+    s = _scene_of(ctx, sc)
+    params = np.concatenate([sc.R_gt[:, :, 0], sc.R_gt[:, :, 1], sc.t_gt], 1).astype(np.float32)
+    d = api.translation_directions(s, torch.from_numpy(params).to(ctx.device),
+                                   torch.from_numpy(inp.t_rel.astype(np.float32)).to(ctx.device)).cpu().numpy()
+    # the oracle on the stored float32 values: the rotation from the float32
+    # 6D parameters, the float32 relative translations
+    R = ea.rot_from_6d(_f32(params[:, 0:3]), _f32(params[:, 3:6]))
+    want = ta.target_directions(R, _f32(inp.t_rel), sc.pairs)
+    np.testing.assert_allclose(d, want, rtol=0, atol=4e-7)
+
+
+def _loss_grad_case(ctx, s, N, pairs, dirs32, cen32):
+    from paper_2505_04612_amd import api
+    loss, grad = api.translation_loss_grad(s, torch.from_numpy(dirs32).to(ctx.device),
+                                           torch.from_numpy(cen32).to(ctx.device))
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+    for r in range(cen32.shape[0]):
+        L, g = ta.loss_grad(_f32(cen32[r]), pairs, _f32(dirs32))
+        # pair terms are rounded to float32 before the float64 sum
+        assert abs(loss[r] - L) <= 1e-6 * max(L, 1e-30), (r, loss[r], L)
+        # records are float32: error relative to the largest entry of the
+        # camera's sum of absolute contributions, bounded by the largest
+        # gradient entry times the camera degree
+        scale = np.abs(g).max()
+        np.testing.assert_allclose(grad[r], g, rtol=1e-5, atol=2e-6 * scale)
+
+
+def test_loss_grad_parity_tiny_and_medium(tiny, medium):
+    ctx = _ctx()
+    for sc in (tiny, medium):
+        inp = _inputs(sc, 3)
+        s = _scene_of(ctx, sc)
+        dirs = ta.target_directions(sc.R_gt, inp.t_rel, sc.pairs).astype(np.float32)
+        cen = inp.init.astype(np.float32)
+        u = np.stack([ta.pair_terms(_f32(cen[r]), sc.pairs, _f32(dirs))[2] for r in range(3)])
+        assert np.abs(u - _f32(dirs)[None]).min() > 1e-6     # away from the L1 kinks
+        _loss_grad_case(ctx, s, sc.R_gt.shape[0], sc.pairs, dirs, cen)
+
+
+def test_loss_grad_parity_ragged_graph_with_hub_isolated_and_coincident():
+    ctx = _ctx()
+    N, pairs = _random_graph()
+    rng = np.random.default_rng(12)
+    dirs = rng.normal(size=(len(pairs), 3))
+    dirs = (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).astype(np.float32)
+    cen = rng.normal(size=(2, N, 3)).astype(np.float32)
+    # coincident centres for the pair (i, j) of pair 400 in run 1
+    i, j = pairs[400]
+    cen[1, j] = cen[1, i]
+    s = _graph_scene(ctx, N, pairs)
+    _loss_grad_case(ctx, s, N, pairs, dirs, cen)
+    from paper_2505_04612_amd import api
+    _, grad = api.translation_loss_grad(s, torch.from_numpy(dirs).to(ctx.device), torch.from_numpy(cen).to(ctx.device))
+    # cameras in no pair get exactly zero
+    assert np.all(grad.cpu().numpy()[:, 990:] == 0.0)
+
+
+def _solve_gpu(ctx, s, dirs32, cen32, K, lr, frac, trace=False, blocks=0):
+    from paper_2505_04612_amd import api
+    c = torch.from_numpy(cen32).to(ctx.device).contiguous()
+    m = torch.zeros_like(c)
+    v = torch.zeros_like(c)
+    tr = torch.empty((c.shape[0], K), dtype=torch.float64, device=ctx.device) if trace else None
+    api.translation_solve(s, torch.from_numpy(dirs32).to(ctx.device), c, m, v, K, lr, frac, loss_trace=tr,
+                          blocks=blocks)
+    assert s.barrier_failures() == 0
+    return c.cpu().numpy(), (tr.cpu().numpy() if trace else None)
+
+
+def test_fused_steps_match_oracle_adam(medium):
+    ctx = _ctx()
+    inp = _inputs(medium, 4)
+    s = _scene_of(ctx, medium)
+    dirs = ta.target_directions(medium.R_gt, inp.t_rel, medium.pairs).astype(np.float32)
+    cen = inp.init.astype(np.float32)
+    K, lr, frac = 5, 3e-2, 1e-2
+    got, trace = _solve_gpu(ctx, s, dirs, cen, K, lr, frac, trace=True)
+    for r in range(4):
+        want, wtr = ta.solve(_f32(cen[r]), medium.pairs, _f32(dirs), K, lr, frac)
+        # five steps of at most lr each; float32 records and moments
+        np.testing.assert_allclose(got[r], want, rtol=0, atol=2e-5)
+        np.testing.assert_allclose(trace[r], wtr, rtol=2e-6)
+
+
+def test_fused_solve_grid_invariance(tiny):
+    ctx = _ctx()
+    inp = _inputs(tiny, 3)
+    s = _scene_of(ctx, tiny)
+    dirs = ta.target_directions(tiny.R_gt, inp.t_rel, tiny.pairs).astype(np.float32)
+    cen = inp.init.astype(np.float32)
+    ref, _ = _solve_gpu(ctx, s, dirs, cen, 50, 3e-2, 1e-2, blocks=1)
+    for b in (2, 3, 16):
+        got, _ = _solve_gpu(ctx, s, dirs, cen, 50, 3e-2, 1e-2, blocks=b)
+        assert np.array_equal(got, ref), b
+
+
+def test_merge_parity_on_gpu_runs(medium):
+    from paper_2505_04612_amd import api
+    ctx = _ctx()
+    inp = _inputs(medium, 4)
+    s = _scene_of(ctx, medium)
+    dirs = ta.target_directions(medium.R_gt, inp.t_rel, medium.pairs).astype(np.float32)
+    runs, _ = _solve_gpu(ctx, s, dirs, inp.init.astype(np.float32), 300, 3e-2, 1e-2)
+    merged, choice, cam = api.translation_merge(s, torch.from_numpy(dirs).to(ctx.device),
+                                                torch.from_numpy(runs).to(ctx.device))
+    merged, choice, cam = merged.cpu().numpy(), choice.cpu().numpy(), cam.cpu().numpy()
+    wm, wc, wcam = ta.merge(_f32(runs), medium.pairs, _f32(dirs))
+    np.testing.assert_allclose(cam, wcam, rtol=1e-12, atol=1e-15)
+    # the choice is an argmin over float64 scores: where the two best runs
+    # are closer than the rounding of the scores, either is correct
+    srt = np.sort(wcam, axis=0)
+    clear = (srt[1] - srt[0]) > 1e-12 * np.maximum(srt[0], 1e-300)
+    assert np.array_equal(choice[clear], wc[clear])
+    ok = wcam[choice, np.arange(len(choice))] <= srt[0] * (1 + 1e-12) + 1e-300
+    assert ok.all()
+    aligned = np.stack([ta.normalize(_f32(runs[r])) for r in range(4)])
+    np.testing.assert_allclose(merged, aligned[choice, np.arange(len(choice))], rtol=0, atol=2e-7 * np.abs(wm).max())
+
+
+def test_whole_stage_matches_oracle_endpoint(tiny):
+    from paper_2505_04612_amd import translation
+    ctx = _ctx()
+    inp = _inputs(tiny, 4)
+    s = _scene_of(ctx, tiny)
+    dirs = ta.target_directions(tiny.R_gt, inp.t_rel, tiny.pairs).astype(np.float32)
+    sched = translation.TranslationSchedule(iters=1000, final_iters=1000)
+    o, info = translation.average(s, torch.from_numpy(dirs).to(ctx.device),
+                                  torch.from_numpy(inp.init.astype(np.float32)).to(ctx.device), sched, trace=True)
+    assert s.barrier_failures() == 0
+    o = o.cpu().numpy()
+    want, winfo = ta.averaging(_f32(inp.init.astype(np.float32)), tiny.pairs, _f32(dirs), 1000, 1000, 3e-2, 1e-2)
+    gt = ta.normalize(-np.einsum("nba,nb->na", tiny.R_gt, tiny.t_gt))
+    e_gpu = np.linalg.norm(ta.normalize(_f32(o)) - gt, axis=1)
+    e_orc = np.linalg.norm(ta.normalize(want) - gt, axis=1)
+    # same endpoint up to the final learning rate's jitter
+    np.testing.assert_allclose(ta.normalize(_f32(o)), ta.normalize(want), rtol=0, atol=5e-3)
+    assert e_gpu.max() <= e_orc.max() + 5e-3
+    # the final loop starts near the optimum: its last loss matches the oracle's
+    tr = info["trace_final"].cpu().numpy()
+    assert abs(tr[-1] - winfo["trace"][-1]) <= 1e-3 * winfo["trace"][-1]
+
+
+def test_empty_graph_and_run_limits():
+    from paper_2505_04612_amd import api
+    from paper_2505_04612_amd._lib import FastMapError
+    ctx = _ctx()
+    s = _graph_scene(ctx, 5, np.zeros((0, 2), np.int32))
+    dirs = torch.zeros((0, 3), dtype=torch.float32, device=ctx.device)
+    cen = torch.randn((2, 5, 3), dtype=torch.float32, device=ctx.device)
+    loss, grad = api.translation_loss_grad(s, dirs, cen)
+    assert np.all(loss.cpu().numpy() == 0.0) and np.all(grad.cpu().numpy() == 0.0)
+    before = cen.clone()
+    api.translation_solve(s, dirs, cen, torch.zeros_like(cen), torch.zeros_like(cen), 10, 1e-2, 1e-2)
+    assert torch.equal(before, cen)
+    merged, choice, cam = api.translation_merge(s, dirs, cen)
+    assert np.all(choice.cpu().numpy() == 0)
+    np.testing.assert_allclose(merged.cpu().numpy(), ta.normalize(_f32(cen[0].cpu().numpy())), atol=1e-6)
+    for bad in (0, 65):
+        c = torch.zeros((bad, 5, 3), dtype=torch.float32, device=ctx.device)
+        with pytest.raises(FastMapError):
+            api.translation_loss_grad(s, dirs, c)
