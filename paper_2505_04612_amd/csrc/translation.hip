@@ -17,15 +17,11 @@ namespace {
 
 constexpr int kTaMaxRuns = 64;
 
-// The L1 term of eq. global-translation-objective for one pair, float64:
-// s = o_j - o_i, u = s/|s|, |u - d|_1.  With `g` it also writes
+// The L1 term of eq. global-translation-objective for one pair, float64, from
+// s = o_j - o_i: u = s/|s|, |u - d|_1.  With `g` it also writes
 // dL/ds = (I - u u^T) sign(u - d) * invP / |s| (sign(0) = 0).  A pair whose
 // centres coincide has no direction: term and record are 0.
-__device__ inline double ta_term(const float* __restrict__ oi, const float* __restrict__ oj, const double d[3],
-                                 double invP, double* g) {
-  double s[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) s[k] = (double)oj[k] - (double)oi[k];
+__device__ inline double ta_term(const double s[3], const double d[3], double invP, double* g) {
   const double ns = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
   if (!(ns > 0.0)) {
     if (g) g[0] = g[1] = g[2] = 0.0;
@@ -48,21 +44,59 @@ __device__ inline double ta_term(const float* __restrict__ oi, const float* __re
   return term;
 }
 
+__device__ inline double ta_term_at(const float* __restrict__ oi, const float* __restrict__ oj, const double d[3]) {
+  double s[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = (double)oj[k] - (double)oi[k];
+  return ta_term(s, d, 0.0, nullptr);
+}
+
+// Runs are taken in groups of kTaGroup (the rest in a group of two and a
+// single run): every load a group needs is issued, unconditionally, before any of its arithmetic, so a
+// thread waits for memory once per group rather than once per run.  (A load
+// under a lane condition makes the compiler wait for it on its own.)
+constexpr int kTaGroup = 4;
+
 __device__ inline void load_dir(const float* __restrict__ dirs, int64_t n, double d[3]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) d[k] = (double)dirs[3 * n + k];
 }
 
-// One pair for every run: records [runs, P].
+// One pair for runs r0 .. r0 + G - 1: records [runs, P].
+template <int G>
+__device__ inline void ta_pair_group(const float* __restrict__ centres, int64_t run_stride, int r0, int64_t P,
+                                     int64_t n, int ci, int cj, const double d[3], double invP,
+                                     float4* __restrict__ rec) {
+  float oi[G][3], oj[G][3];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const float* o = centres + (r0 + q) * run_stride;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      oi[q][k] = o[3 * (int64_t)ci + k];
+      oj[q][k] = o[3 * (int64_t)cj + k];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    double sv[3], g[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sv[k] = (double)oj[q][k] - (double)oi[q][k];
+    const double term = ta_term(sv, d, invP, g);
+    rec[(r0 + q) * P + n] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)term);
+  }
+}
+
 __device__ inline void ta_pair_runs(const float* __restrict__ centres, int32_t N, int runs, int64_t P, int64_t n,
                                     int ci, int cj, const double d[3], double invP, float4* __restrict__ rec) {
   const int64_t run_stride = (int64_t)N * 3;
-  for (int r = 0; r < runs; ++r) {
-    const float* o = centres + r * run_stride;
-    double g[3];
-    const double term = ta_term(o + 3 * (int64_t)ci, o + 3 * (int64_t)cj, d, invP, g);
-    rec[r * P + n] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)term);
+  int r0 = 0;
+  for (; r0 + kTaGroup <= runs; r0 += kTaGroup) ta_pair_group<kTaGroup>(centres, run_stride, r0, P, n, ci, cj, d, invP, rec);
+  if (r0 + 2 <= runs) {
+    ta_pair_group<2>(centres, run_stride, r0, P, n, ci, cj, d, invP, rec);
+    r0 += 2;
   }
+  if (r0 < runs) ta_pair_group<1>(centres, run_stride, r0, P, n, ci, cj, d, invP, rec);
 }
 
 // Per-run workgroup sums of the pair terms this workgroup's threads wrote
@@ -77,29 +111,51 @@ __device__ inline void ta_loss_partials(const float4* __restrict__ rec, int64_t 
   }
 }
 
-// Gradient of one camera for run r, in every lane of its 16-lane row: the
-// records of the camera's pairs, +dL/ds where it is the second camera of
-// the pair and -dL/ds where it is the first, summed lane-strided over the
-// incidence list and then across the row.
+// Gradients of one camera for runs r0 .. r0 + G - 1, in every lane of its
+// 16-lane row: the records of the camera's pairs, +dL/ds where it is the
+// second camera of the pair and -dL/ds where it is the first, summed
+// lane-strided over the incidence list and then across the row by a fixed
+// butterfly.  Prefix entries past the list's end read pair 0's record and
+// add nothing.
+template <int G>
 __device__ inline void ta_row_grad(const RowList& L, const int32_t* __restrict__ cam_items,
-                                   const float4* __restrict__ rec_r, int l16, double acc[3]) {
-  acc[0] = acc[1] = acc[2] = 0.0;
-  auto add = [&](int item) {
-    const float4 q = rec_r[item >> 1];
-    const double sgn = (item & 1) ? 1.0 : -1.0;
-    acc[0] += sgn * (double)q.x;
-    acc[1] += sgn * (double)q.y;
-    acc[2] += sgn * (double)q.z;
-  };
+                                   const float4* __restrict__ rec, int64_t P, int r0, int l16, double acc[G][3]) {
+  float4 q[G][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (L.it[j] >= 0) add(L.it[j]);
-  for (int q = L.lo + 64 + l16; q < L.hi; q += 16) add(cam_items[q]);
+  for (int g = 0; g < G; ++g)
 #pragma unroll
-  for (int s = 8; s >= 1; s >>= 1) {
+    for (int j = 0; j < 4; ++j) q[g][j] = rec[(r0 + g) * P + (L.it[j] >= 0 ? (L.it[j] >> 1) : 0)];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc[k] += __shfl_xor(acc[k], s);
+  for (int g = 0; g < G; ++g) {
+    acc[g][0] = acc[g][1] = acc[g][2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double sgn = L.it[j] < 0 ? 0.0 : ((L.it[j] & 1) ? 1.0 : -1.0);
+      acc[g][0] += sgn * (double)q[g][j].x;
+      acc[g][1] += sgn * (double)q[g][j].y;
+      acc[g][2] += sgn * (double)q[g][j].z;
+    }
   }
+  // entries past the first 64 of a long list
+  for (int qi = L.lo + 64 + l16; qi < L.hi; qi += 16) {
+    const int item = cam_items[qi];
+    const double sgn = (item & 1) ? 1.0 : -1.0;
+    float4 f[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) f[g] = rec[(r0 + g) * P + (item >> 1)];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      acc[g][0] += sgn * (double)f[g].x;
+      acc[g][1] += sgn * (double)f[g].y;
+      acc[g][2] += sgn * (double)f[g].z;
+    }
+  }
+#pragma unroll
+  for (int sh = 8; sh >= 1; sh >>= 1)
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[g][k] += __shfl_xor(acc[g][k], sh);
 }
 
 __device__ inline double pick3(const double a[3], int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
@@ -148,10 +204,19 @@ __global__ __launch_bounds__(kBlock) void k_ta_camera(const int32_t* __restrict_
   const int l16 = (int)(gtid & 15);
   if (c >= N) return;   // whole rows leave together: the row exchanges stay within live rows
   const RowList L = row_list(cam_ptr, cam_items, (int)c, l16);
-  for (int r = 0; r < runs; ++r) {
-    double acc[3];
-    ta_row_grad(L, cam_items, rec + r * P, l16, acc);
-    if (l16 < 3) grad[(r * (int64_t)N + c) * 3 + l16] = (float)pick3(acc, l16);
+  const int k3 = l16 < 3 ? l16 : 2;
+  int r0 = 0;
+  for (; r0 + kTaGroup <= runs; r0 += kTaGroup) {
+    double acc[kTaGroup][3];
+    ta_row_grad<kTaGroup>(L, cam_items, rec, P, r0, l16, acc);
+    if (l16 < 3)
+#pragma unroll
+      for (int g = 0; g < kTaGroup; ++g) grad[((r0 + g) * (int64_t)N + c) * 3 + k3] = (float)pick3(acc[g], k3);
+  }
+  for (; r0 < runs; ++r0) {
+    double acc[1][3];
+    ta_row_grad<1>(L, cam_items, rec, P, r0, l16, acc);
+    if (l16 < 3) grad[(r0 * (int64_t)N + c) * 3 + k3] = (float)pick3(acc[0], k3);
   }
 }
 
@@ -186,6 +251,34 @@ struct TaArgs {
   double invP, lr, log_frac, b1, b2, eps;
   int64_t lr_step0, lr_total, adam_step0;
 };
+
+// Adam steps of one camera (its row) for runs r0 .. r0 + G - 1; lanes 0..2
+// own the coordinates.  Parameters and moments are loaded first (they do not
+// depend on the records); lanes 3..15 load coordinate 2 and discard it.
+template <int G>
+__device__ inline void ta_camera_group(const TaArgs& a, const RowList& L, int64_t c, int l16, int r0, double lr,
+                                       double bc1, double bc2) {
+  const int k3 = l16 < 3 ? l16 : 2;
+  float p[G], mq[G], vq[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int64_t idx = ((r0 + g) * (int64_t)a.N + c) * 3 + k3;
+    p[g] = a.centres[idx];
+    mq[g] = a.m[idx];
+    vq[g] = a.v[idx];
+  }
+  double acc[G][3];
+  ta_row_grad<G>(L, a.cam_items, a.rec, a.P, r0, l16, acc);
+  if (l16 < 3) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t idx = ((r0 + g) * (int64_t)a.N + c) * 3 + k3;
+      a.centres[idx] = adam_update(p[g], (float)pick3(acc[g], k3), mq[g], vq[g], lr, a.b1, a.b2, a.eps, bc1, bc2);
+      a.m[idx] = mq[g];
+      a.v[idx] = vq[g];
+    }
+  }
+}
 
 __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
   __shared__ double lds[kSolveBlock / 64];
@@ -225,28 +318,20 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
     const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
     const double step = (double)(a.adam_step0 + k + 1);
     const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
-    // the loop bound is uniform over the wavefront (rows past N idle with an
-    // empty list), so the row exchanges run with every lane present
+    // rows past N skip the camera work as a whole
     for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
       const int64_t c = c0 + row;
       const bool live = c < a.N;
       const RowList L = c0 == 4 * gwave ? L0 : (live ? row_list(a.cam_ptr, a.cam_items, (int)c, l16)
                                                      : RowList{0, 0, {-1, -1, -1, -1}});
-      for (int r = 0; r < a.runs; ++r) {
-        const int64_t idx = (r * (int64_t)a.N + c) * 3 + l16;
-        float p = 0.0f, mq = 0.0f, vq = 0.0f;
-        if (live && l16 < 3) {
-          p = a.centres[idx];
-          mq = a.m[idx];
-          vq = a.v[idx];
+      if (live) {   // whole rows: the row exchanges stay within live rows
+        int r0 = 0;
+        for (; r0 + kTaGroup <= a.runs; r0 += kTaGroup) ta_camera_group<kTaGroup>(a, L, c, l16, r0, lr, bc1, bc2);
+        if (r0 + 2 <= a.runs) {
+          ta_camera_group<2>(a, L, c, l16, r0, lr, bc1, bc2);
+          r0 += 2;
         }
-        double acc[3];
-        ta_row_grad(L, a.cam_items, a.rec + r * a.P, l16, acc);
-        if (live && l16 < 3) {
-          a.centres[idx] = adam_update(p, (float)pick3(acc, l16), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
-          a.m[idx] = mq;
-          a.v[idx] = vq;
-        }
+        if (r0 < a.runs) ta_camera_group<1>(a, L, c, l16, r0, lr, bc1, bc2);
       }
     }
     grid_barrier(a.bar);
@@ -311,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_ta_merge(const float* __restrict__ c
       const int64_t n = cam_items[q] >> 1;
       double d[3];
       load_dir(dirs, n, d);
-      acc += ta_term(o + 3 * (int64_t)cams[2 * n], o + 3 * (int64_t)cams[2 * n + 1], d, 0.0, nullptr);
+      acc += ta_term_at(o + 3 * (int64_t)cams[2 * n], o + 3 * (int64_t)cams[2 * n + 1], d);
     }
 #pragma unroll
     for (int s = 8; s >= 1; s >>= 1) acc += __shfl_xor(acc, s);
