@@ -567,3 +567,37 @@ def translation_inputs(scene: Scene, sigma_deg: float = 2.0, outlier_frac: float
     tr[outl] = _normalize(rng.normal(size=(int(outl.sum()), 3)))
     init = rng.normal(size=(runs, R.shape[0], 3))
     return TranslationInputs(tr, outl, init, sigma_deg, outlier_frac)
+
+
+# ------------------------------------------------------------------ rotation averaging inputs
+
+@dataclasses.dataclass
+class RotationInputs:
+    R_rel: np.ndarray       # [P,3,3] float64 measured relative rotations R^{i->j}
+    outlier: np.ndarray     # [P] bool, True where R_rel is a random rotation
+    sigma_deg: float
+    outlier_frac: float
+
+
+def rotation_inputs(scene: Scene, sigma_deg: float = 2.0, outlier_frac: float = 0.1,
+                    seed: int | None = None) -> RotationInputs:
+    """Inputs of rotation averaging on a scene's pair graph (Sec. 3.3, Global
+    Rotation): per pair the measured relative rotation R^{i->j} ~ R_j R_i^T,
+    rotated by sigma_deg * |N(0, 1)| about a random axis, and outlier_frac of
+    the pairs replaced by rotations uniform on SO(3) (random unit quaternions)."""
+    rng = np.random.default_rng((scene.seed if seed is None else seed) + 30_000)
+    R = scene.R_gt
+    i, j = scene.pairs[:, 0], scene.pairs[:, 1]
+    P = len(scene.pairs)
+    Q = np.einsum("pab,pcb->pac", R[j], R[i])
+    axis = _normalize(rng.normal(size=(P, 3)))
+    ang = np.deg2rad(sigma_deg) * np.abs(rng.normal(size=P))
+    Q = _axis_angle(axis, ang) @ Q
+    outl = rng.random(P) < outlier_frac
+    q = _normalize(rng.normal(size=(int(outl.sum()), 4)))
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    Q[outl] = np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+    return RotationInputs(Q, outl, sigma_deg, outlier_frac)
