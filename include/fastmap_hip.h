@@ -186,8 +186,9 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
                             double inv_Z, const int64_t* Z_dev, double* loss_trace,
                             fm_stream stream);
 
-/* Failed grid barriers of fm_epipolar_solve and fm_translation_solve launches
- * on this scene since the last call (host value in *failures), then cleared.  A barrier wait is
+/* Failed grid barriers of the persistent launches (fm_epipolar_solve,
+ * fm_translation_solve, fm_rotation_solve, fm_rotation_init) on this scene
+ * since the last call (host value in *failures), then cleared.  A barrier wait is
  * bounded (about a second); if it expires, the launch stops at once and its
  * results are invalid.  Synchronises the device.  Not expected to be nonzero:
  * the cooperative launch makes every workgroup resident. */
@@ -252,6 +253,40 @@ fm_status fm_translation_merge(fm_ctx* ctx, fm_scene* scene, const float* dirs, 
                                const float* centres, float* merged, int32_t* choice, double* cam_loss,
                                fm_stream stream);
 
+/* ------------------------------------------------------------------ rotation averaging */
+
+/* Global rotation averaging, the first pose stage (Sec. 3.3 "Global
+ * Rotation", eq. rotation-objective and its geodesic distance; the appendix
+ * on rotation initialisation), on the scene's pair graph (its matches are
+ * not used):
+ *   input    Rrel [P,9] float32, row-major: the measured relative rotation
+ *            R^{i->j} of each pair (R_j ~ R^{i->j} R_i, world-to-camera);
+ *   params   [N,6] float32 per camera (a1, a2): R_i = [b1 b2 b3] by
+ *            Gram-Schmidt (the 6D representation);
+ *   loss     L_R = (1/P) sum_n arccos((tr(R_j^T R^{i->j} R_i) - 1)/2), the
+ *            argument clipped to [-1, 1]; where it is +-1 the pair adds no
+ *            gradient.
+ * The calls use the scene's pair-record and rotation workspace (the same
+ * the epipolar calls use), so they must not overlap epipolar calls on the
+ * scene. */
+
+/* L_R at params (loss [1] double, NULL = not written) and dL_R/dparams
+ * (grad [N,6] float32, NULL = not written): per pair in float64, records in
+ * float32, summed per camera over its pairs in a fixed order, Gram-Schmidt
+ * adjoint in float64. */
+fm_status fm_rotation_loss_grad(fm_ctx* ctx, fm_scene* scene, const float* Rrel, const float* params,
+                                double* loss, float* grad, fm_stream stream);
+
+/* K iterations of {gradient as fm_rotation_loss_grad, Adam update of params}
+ * in ONE persistent cooperative kernel (as fm_epipolar_solve; the rotations
+ * of the current parameters are kept between the two phases).  params, m, v
+ * [N,6] float32 are updated in place.  `cfg` (host) as for fm_epipolar_solve
+ * with lr_rot the initial rate (lr_t unused).  loss_trace [K] double receives
+ * L_R before each update (NULL = not written). */
+fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* scene, const float* Rrel, float* params, float* m,
+                            float* v, int32_t K, const fm_adam_cfg* cfg, double* loss_trace,
+                            fm_stream stream);
+
 /* ------------------------------------------------------------------ a9: learned weights */
 
 /* Learned robust weights (an addition to the paper's IRLS, Sec. 3.3): a
@@ -301,7 +336,9 @@ fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_m
  *   persistent loop), FM_K_ESSENTIALS 2, FM_K_FINALIZE 3, FM_K_PAIR 4 and
  *   FM_K_CAMERA 5 (the two kernels of fm_epipolar_loss_grad), FM_K_TA_SOLVE 6
  *   (persistent translation loop), FM_K_TA_PAIR 7 and FM_K_TA_CAMERA 8 (the
- *   two kernels of fm_translation_loss_grad).
+ *   two kernels of fm_translation_loss_grad), FM_K_RA_SOLVE 9 (persistent
+ *   rotation loop), FM_K_RA_PAIR 10 and FM_K_RA_CAMERA 11 (the two kernels of
+ *   fm_rotation_loss_grad), FM_K_RA_INIT 12 (rotation initialisation).
  * fm_profile_enable synchronises the device and clears earlier records;
  * fm_profile_read waits for the recorded events and returns the summed
  * elapsed milliseconds and the launch count of one kernel (host outputs). */

@@ -349,6 +349,40 @@ def translation_merge(scene: Scene, dirs: torch.Tensor, centres: torch.Tensor):
     return merged, choice, cam
 
 
+# ------------------------------------------------------------------ rotation averaging
+
+def rotation_loss_grad(scene: Scene, Rrel: torch.Tensor, params6: torch.Tensor, want_loss: bool = True,
+                       want_grad: bool = True):
+    """(loss [1] float64 | None, grad [N,6] float32 | None) of L_R."""
+    dev = scene.ctx.device
+    _require(Rrel, torch.float32, (scene.num_pairs, 9), "Rrel", dev)
+    _require(params6, torch.float32, (scene.num_cams, 6), "params6", dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev) if want_loss else None
+    grad = torch.empty((scene.num_cams, 6), dtype=torch.float32, device=dev) if want_grad else None
+    check(scene.ctx.handle, scene.ctx.lib.fm_rotation_loss_grad(scene.ctx.handle, scene.handle, _ptr(Rrel),
+                                                                _ptr(params6), _ptr(loss), _ptr(grad), _stream()))
+    return loss, grad
+
+
+def rotation_solve(scene: Scene, Rrel: torch.Tensor, params6: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                   K: int, lr: float, lr_final_frac: float, lr_step0: int = 0, lr_total: int | None = None,
+                   adam_step0: int = 0, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-12,
+                   loss_trace: torch.Tensor | None = None, blocks: int = 0) -> None:
+    """K fused Adam iterations on L_R (one persistent kernel); params6, m, v
+    [N,6] are updated in place; loss_trace [K] float64 optional."""
+    dev = scene.ctx.device
+    _require(Rrel, torch.float32, (scene.num_pairs, 9), "Rrel", dev)
+    for name, t in (("params6", params6), ("m", m), ("v", v)):
+        _require(t, torch.float32, (scene.num_cams, 6), name, dev)
+    if loss_trace is not None:
+        _require(loss_trace, torch.float64, (K,), "loss_trace", dev)
+    cfg = _lib.AdamCfg(lr, 0.0, lr_final_frac, beta1, beta2, eps, lr_step0, lr_total if lr_total else K,
+                       adam_step0, blocks)
+    check(scene.ctx.handle, scene.ctx.lib.fm_rotation_solve(
+        scene.ctx.handle, scene.handle, _ptr(Rrel), _ptr(params6), _ptr(m), _ptr(v), int(K), ctypes.byref(cfg),
+        _ptr(loss_trace), _stream()))
+
+
 # ------------------------------------------------------------------ a9: learned weights
 
 MLP_SHAPES = {"W1": (64, 3), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (1, 64), "b3": (1,)}

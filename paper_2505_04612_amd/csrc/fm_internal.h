@@ -34,7 +34,8 @@ constexpr int kKeptSlots = 256;
 
 // Kernel identifiers of the optional launch timing (fm_profile_*).
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
-       FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_COUNT = 9 };
+       FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_RA_SOLVE = 9, FM_K_RA_PAIR = 10,
+       FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_COUNT = 13 };
 
 struct fm_timing {
   int kernel;
@@ -111,6 +112,7 @@ struct fm_scene {
   double* ta_part = nullptr;      // [ta_runs_cap, ta_part_cap] per-workgroup loss partials
   double* ta_stats = nullptr;     // [ta_runs_cap, 4] centroid and mean norm of each run
   int ta_coop_blocks = 0;         // max co-resident blocks of the translation loop
+  int ra_coop_blocks = 0;         // max co-resident blocks of the rotation loop
 };
 
 // Error reporting helpers: set ctx->err and return the status.
@@ -223,6 +225,132 @@ __device__ inline RowList row_list(const int32_t* __restrict__ cam_ptr, const in
 #pragma unroll
   for (int j = 0; j < 4; ++j) L.it[j] = L.lo + l16 + 16 * j < L.hi ? cam_items[L.lo + l16 + 16 * j] : -1;
   return L;
+}
+
+template <int CTRL>
+__device__ inline double dpp_mov_d(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Reduce-scatter stage over lane bit BIT (see the Gram pass for the partner
+// rules): keep the lower or upper half of S values and add the partner's.
+template <int S, int BIT>
+__device__ inline void rs_stage_d(const double (&in)[S], double (&out)[(S + 1) / 2], int lane) {
+  constexpr int H = (S + 1) / 2;
+  const bool up = (lane >> BIT) & 1;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const double lo = in[k];
+    const double hi = (k + H < S) ? in[k + H] : 0.0;
+    const double send = up ? lo : hi;
+    double recv;
+    if constexpr (BIT == 3) recv = dpp_mov_d<0x140>(send);        // row_mirror
+    else if constexpr (BIT == 2) recv = dpp_mov_d<0x141>(send);   // row_half_mirror
+    else if constexpr (BIT == 1) recv = dpp_mov_d<0x4E>(send);    // quad_perm xor 2
+    else recv = dpp_mov_d<0xB1>(send);                            // quad_perm xor 1
+    out[k] = (up ? hi : lo) + recv;
+  }
+}
+
+__device__ inline void add_record(const float* __restrict__ contrib, int item, double acc[12]) {
+  const float4* src = reinterpret_cast<const float4*>(contrib + (int64_t)(item >> 1) * 24 + (item & 1) * 12);
+  const float4 r0 = src[0], r1 = src[1], r2 = src[2];
+  acc[0] += r0.x; acc[1] += r0.y; acc[2] += r0.z; acc[3] += r0.w;
+  acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
+  acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
+}
+
+// Wave-wide total of the 12 per-lane sums (dL/dR 3x3, dL/dt), returned in
+// every lane: reduce-scatter over lane bits 3..0 (12 -> 6 -> 3 -> 2 -> 1,
+// DPP), add across the four rows, gather back.  Fixed order: deterministic.
+__device__ inline void wave_sum12(double acc[12], int lane) {
+  double b6[6], b3[3], b2[2], b1[1];
+  rs_stage_d<12, 3>(*reinterpret_cast<double(*)[12]>(acc), b6, lane);
+  rs_stage_d<6, 2>(b6, b3, lane);
+  rs_stage_d<3, 1>(b3, b2, lane);
+  rs_stage_d<2, 0>(b2, b1, lane);
+  double v = b1[0];
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  // entry s now sits in lane s + s / 3 of every row
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = __shfl(v, k + k / 3);
+}
+
+// dL/dtheta [9] of one camera from its summed dL/dR (columns g1, g2, g3 in
+// acc[3r + col]) and dL/dt (acc[9..11]): the Gram-Schmidt adjoint in float64.
+__device__ inline void gs_adjoint(const double acc[12], const double a1[3], const double a2[3], double grad[9]) {
+  const Gs f = gs_forward(a1, a2);
+  double g1[3], g2[3], g3[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    g1[r] = acc[3 * r + 0];
+    g2[r] = acc[3 * r + 1];
+    g3[r] = acc[3 * r + 2];
+  }
+  // b3 = b1 x b2
+  g1[0] += f.b2[1] * g3[2] - f.b2[2] * g3[1];
+  g1[1] += f.b2[2] * g3[0] - f.b2[0] * g3[2];
+  g1[2] += f.b2[0] * g3[1] - f.b2[1] * g3[0];
+  g2[0] += g3[1] * f.b1[2] - g3[2] * f.b1[1];
+  g2[1] += g3[2] * f.b1[0] - g3[0] * f.b1[2];
+  g2[2] += g3[0] * f.b1[1] - g3[1] * f.b1[0];
+  // b2 = u2/|u2|, u2 = a2 - (b1.a2) b1
+  const double b2g2 = f.b2[0] * g2[0] + f.b2[1] * g2[1] + f.b2[2] * g2[2];
+  double gu[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gu[k] = (g2[k] - b2g2 * f.b2[k]) / f.n2;
+  const double b1gu = f.b1[0] * gu[0] + f.b1[1] * gu[1] + f.b1[2] * gu[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    grad[3 + k] = gu[k] - f.b1[k] * b1gu;
+    g1[k] += -f.d12 * gu[k] - a2[k] * b1gu;
+  }
+  // b1 = a1/|a1|
+  const double b1g1 = f.b1[0] * g1[0] + f.b1[1] * g1[1] + f.b1[2] * g1[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    grad[k] = (g1[k] - b1g1 * f.b1[k]) / f.n1;
+    grad[6 + k] = acc[9 + k];
+  }
+}
+
+// Row-wide total of the 12 per-lane sums over one 16-lane row, returned in
+// every lane of the row: the same DPP reduce-scatter as wave_sum12 without
+// the cross-row steps, then a gather inside the row.
+__device__ inline void row_sum12(double acc[12], int lane) {
+  double b6[6], b3[3], b2[2], b1[1];
+  rs_stage_d<12, 3>(*reinterpret_cast<double(*)[12]>(acc), b6, lane);
+  rs_stage_d<6, 2>(b6, b3, lane);
+  rs_stage_d<3, 1>(b3, b2, lane);
+  rs_stage_d<2, 0>(b2, b1, lane);
+  const double v = b1[0];
+  const int base = lane & ~15;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = __shfl(v, base + k + k / 3);
+}
+
+// Summed records of one camera in every lane of its row.
+__device__ inline void row_camera_sums(const RowList& L, const int32_t* __restrict__ cam_items,
+                                       const float* __restrict__ contrib, int lane, double acc[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (L.it[j] >= 0) add_record(contrib, L.it[j], acc);
+  for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record(contrib, cam_items[q], acc);
+  row_sum12(acc, lane);
+}
+
+// The element q of a per-lane array held identically by all lanes.
+__device__ inline double pick9(const double g[9], int q) {
+  double v = g[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) v = (q == k) ? g[k] : v;
+  return v;
 }
 
 // Deterministic block sum of one double per thread (fixed tree).

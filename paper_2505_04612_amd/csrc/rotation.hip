@@ -1,0 +1,338 @@
+// Global rotation averaging (FastMap, arXiv 2505.04612, Sec. 3.3 "Global
+// Rotation": eq. rotation-objective with the geodesic distance, the 6D
+// rotation parameterisation) on a scene's pair graph.
+//
+// The per-pair records use the epipolar loop's layout ([P, 24] floats: for
+// each side of the pair dL/dR as 3x3 row-major and three unused entries), so
+// the camera side shares its row sums and Gram-Schmidt adjoint.  Parameters
+// are (a1, a2) per camera, [N, 6].
+#include "fm_internal.h"
+
+#include <cmath>
+
+namespace {
+
+// One pair's geodesic term and its record, float64.  With Q = R^{i->j},
+// M = R_j^T Q R_i, c = (tr M - 1)/2 and d = arccos(c) (c clipped to
+// [-1, 1]): dd/dc = -1/sqrt(1 - c^2) (0 where |c| = 1), dc/dR_j = Q R_i / 2
+// = R_j M / 2 and dc/dR_i = Q^T R_j / 2 = R_i M^T / 2; both scaled by invP.
+// The records keep only the part of these that moves along the rotation
+// group (R_j K and -R_i K with K = (M - M^T)/2): the rest is annihilated by
+// the Gram-Schmidt adjoint, and it grows like 1/d, so a float32 record of
+// the full matrix would lose the O(1) tangent part to rounding when d is
+// small.  Returns d.
+__device__ inline double ra_pair(const double Ri[3][3], const double Rj[3][3], const float* __restrict__ q,
+                                 double invP, float* __restrict__ rec) {
+  double Q[3][3], QRi[3][3], M[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Q[a][b] = (double)q[3 * a + b];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) QRi[a][b] = Q[a][0] * Ri[0][b] + Q[a][1] * Ri[1][b] + Q[a][2] * Ri[2][b];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) M[a][b] = Rj[0][a] * QRi[0][b] + Rj[1][a] * QRi[1][b] + Rj[2][a] * QRi[2][b];
+  double c = 0.5 * (M[0][0] + M[1][1] + M[2][2] - 1.0);
+  const bool inside = c > -1.0 && c < 1.0;
+  c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+  if (rec) {
+    const double half_gc = inside ? -0.5 * invP / sqrt(1.0 - c * c) : 0.0;
+    double K[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) K[a][b] = 0.5 * (M[a][b] - M[b][a]);
+    float gi[12], gj[12];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        gj[3 * a + b] = (float)(half_gc * (Rj[a][0] * K[0][b] + Rj[a][1] * K[1][b] + Rj[a][2] * K[2][b]));
+        gi[3 * a + b] = (float)(-half_gc * (Ri[a][0] * K[0][b] + Ri[a][1] * K[1][b] + Ri[a][2] * K[2][b]));
+      }
+    gi[9] = gi[10] = gi[11] = 0.0f;
+    gj[9] = gj[10] = gj[11] = 0.0f;
+    float4* dst = reinterpret_cast<float4*>(rec);
+    dst[0] = make_float4(gi[0], gi[1], gi[2], gi[3]);
+    dst[1] = make_float4(gi[4], gi[5], gi[6], gi[7]);
+    dst[2] = make_float4(gi[8], gi[9], gi[10], gi[11]);
+    dst[3] = make_float4(gj[0], gj[1], gj[2], gj[3]);
+    dst[4] = make_float4(gj[4], gj[5], gj[6], gj[7]);
+    dst[5] = make_float4(gj[8], gj[9], gj[10], gj[11]);
+  }
+  return acos(c);
+}
+
+__device__ inline void rot6(const float* __restrict__ p6, int c, double R[3][3]) {
+  double a1[3], a2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a1[k] = (double)p6[6 * (int64_t)c + k];
+    a2[k] = (double)p6[6 * (int64_t)c + 3 + k];
+  }
+  gs_matrix(gs_forward(a1, a2), R);
+}
+
+__device__ inline void load_rot(const double* __restrict__ rot, int c, double R[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) R[a][b] = rot[9 * (int64_t)c + 3 * a + b];
+}
+
+// ------------------------------------------------------------------ standalone loss + gradient
+
+__global__ __launch_bounds__(kBlock) void k_ra_pair(const float* __restrict__ params, const int32_t* __restrict__ cams,
+                                                    const float* __restrict__ Rrel, int64_t P, double invP,
+                                                    float* __restrict__ contrib, double* __restrict__ part) {
+  __shared__ double lds[kBlock / 64];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gsize = (int64_t)gridDim.x * blockDim.x;
+  double v = 0.0;
+  for (int64_t n = gtid; n < P; n += gsize) {
+    double Ri[3][3], Rj[3][3];
+    rot6(params, cams[2 * n], Ri);
+    rot6(params, cams[2 * n + 1], Rj);
+    v += ra_pair(Ri, Rj, Rrel + 9 * n, invP, contrib + 24 * n);
+  }
+  const double t = block_sum(v, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ra_camera(const float* __restrict__ params,
+                                                      const int32_t* __restrict__ cam_ptr,
+                                                      const int32_t* __restrict__ cam_items,
+                                                      const float* __restrict__ contrib, int32_t N,
+                                                      float* __restrict__ grad) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = gtid >> 4;
+  const int lane = threadIdx.x & 63, l16 = lane & 15;
+  if (c >= N) return;   // whole rows leave together: the row exchanges stay within live rows
+  double acc[12];
+  row_camera_sums(row_list(cam_ptr, cam_items, (int)c, l16), cam_items, contrib, lane, acc);
+  double a1[3], a2[3], g[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a1[k] = (double)params[6 * c + k];
+    a2[k] = (double)params[6 * c + 3 + k];
+  }
+  gs_adjoint(acc, a1, a2, g);
+  if (l16 < 6) grad[6 * c + l16] = (float)pick9(g, l16);
+}
+
+__global__ void k_ra_loss_final(const double* __restrict__ part, int64_t nblocks, double invP, double* __restrict__ loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nblocks; ++b) s += part[b];
+  *loss = s * invP;
+}
+
+// ------------------------------------------------------------------ fused persistent loop
+
+struct RaArgs {
+  float* params;
+  float* m;
+  float* v;
+  const int32_t* cams;
+  const float* Rrel;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  float* contrib;
+  double* rot;
+  double* part;
+  double* trace;
+  unsigned* bar;
+  int64_t P;
+  int32_t N;
+  int32_t K;
+  double invP, lr, log_frac, b1, b2, eps;
+  int64_t lr_step0, lr_total, adam_step0;
+};
+
+// Rotation of camera c from the parameters p0 held by lanes 0..5 of its row,
+// stored by lanes 0..8.
+__device__ inline void ra_store_rot(double* __restrict__ rot, int64_t c, float p0, int base, int l16, bool live) {
+  double a1[3], a2[3], R[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    a1[j] = (double)__shfl(p0, base + j);
+    a2[j] = (double)__shfl(p0, base + 3 + j);
+  }
+  if (!live) a1[0] = a2[1] = 1.0;   // a row without a camera: keep Gram-Schmidt away from 0/0
+  gs_matrix(gs_forward(a1, a2), R);
+  if (live && l16 < 9) {
+    double rv = R[0][0];
+#pragma unroll
+    for (int j = 1; j < 9; ++j) rv = (l16 == j) ? R[j / 3][j % 3] : rv;
+    rot[c * 9 + l16] = rv;
+  }
+}
+
+__global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
+  __shared__ double lds[kSolveBlock / 64];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const int row = lane >> 4, l16 = lane & 15, base = lane & ~15;
+  const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
+  // rotations of the initial parameters
+  for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
+    const int64_t c = c0 + row;
+    const bool live = c < a.N;
+    const float p0 = (live && l16 < 6) ? a.params[6 * c + l16] : 0.0f;
+    ra_store_rot(a.rot, c, p0, base, l16, live);
+  }
+  // static data of this thread's first pair and this row's first camera
+  int ci0 = 0, cj0 = 0;
+  if (gtid < a.P) {
+    ci0 = a.cams[2 * gtid];
+    cj0 = a.cams[2 * gtid + 1];
+  }
+  RowList L0 = {0, 0, {-1, -1, -1, -1}};
+  if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
+  grid_barrier(a.bar);
+  for (int k = 0; k < a.K; ++k) {
+    double v = 0.0;
+    for (int64_t n = gtid; n < a.P; n += gsize) {
+      double Ri[3][3], Rj[3][3];
+      load_rot(a.rot, n == gtid ? ci0 : a.cams[2 * n], Ri);
+      load_rot(a.rot, n == gtid ? cj0 : a.cams[2 * n + 1], Rj);
+      v += ra_pair(Ri, Rj, a.Rrel + 9 * n, a.invP, a.contrib + 24 * n);
+    }
+    if (a.trace) {
+      const double t = block_sum(v, lds);
+      if (threadIdx.x == 0) a.part[blockIdx.x] = t;
+    }
+    grid_barrier(a.bar);
+    if (a.trace && gtid == 0) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += a.part[b];
+      a.trace[k] = s * a.invP;
+    }
+    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
+    const double step = (double)(a.adam_step0 + k + 1);
+    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    // the loop bound is uniform over the wavefront (rows past N idle), so
+    // the row exchanges always run with every lane present
+    for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
+      const int64_t c = c0 + row;
+      const bool live = c < a.N;
+      float p0 = 0.0f, mq = 0.0f, vq = 0.0f;
+      if (live && l16 < 6) {
+        p0 = a.params[6 * c + l16];
+        mq = a.m[6 * c + l16];
+        vq = a.v[6 * c + l16];
+      }
+      double acc[12];
+      const RowList L = c0 == 4 * gwave ? L0 : (live ? row_list(a.cam_ptr, a.cam_items, (int)c, l16)
+                                                     : RowList{0, 0, {-1, -1, -1, -1}});
+      row_camera_sums(L, a.cam_items, a.contrib, lane, acc);
+      double a1[3], a2[3], g[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        a1[j] = (double)__shfl(p0, base + j);
+        a2[j] = (double)__shfl(p0, base + 3 + j);
+      }
+      if (!live) a1[0] = a2[1] = 1.0;
+      gs_adjoint(acc, a1, a2, g);
+      float pq = 0.0f;
+      if (live && l16 < 6) {
+        pq = adam_update(p0, (float)pick9(g, l16), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+        a.params[6 * c + l16] = pq;
+        a.m[6 * c + l16] = mq;
+        a.v[6 * c + l16] = vq;
+      }
+      ra_store_rot(a.rot, c, pq, base, l16, live);
+    }
+    grid_barrier(a.bar);
+  }
+}
+
+fm_status ra_check(fm_ctx* ctx, fm_scene* s, const char* fn) {
+  if (!s) return fm_fail(ctx, FM_EINVAL, "%s: scene is NULL", fn);
+  if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "%s: scene belongs to another context", fn);
+  return FM_OK;
+}
+
+}  // namespace
+
+extern "C" fm_status fm_rotation_loss_grad(fm_ctx* ctx, fm_scene* s, const float* Rrel, const float* params,
+                                           double* loss, float* grad, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ra_check(ctx, s, "fm_rotation_loss_grad");
+  if (rc != FM_OK) return rc;
+  if ((s->P > 0 && !Rrel) || (s->N > 0 && !params)) return fm_fail(ctx, FM_EINVAL, "fm_rotation_loss_grad: NULL argument");
+  if (!loss && !grad) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const double invP = s->P > 0 ? 1.0 / (double)s->P : 0.0;
+  const unsigned gp = grid_for(s->P > 0 ? s->P : 1, kBlock);
+  {
+    fm_timed timer(ctx, FM_K_RA_PAIR, st);
+    hipLaunchKernelGGL(k_ra_pair, dim3(gp), dim3(kBlock), 0, st, params, s->pair_cams, Rrel, s->P, invP, s->contrib,
+                       s->loss_part);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  if (loss) {
+    hipLaunchKernelGGL(k_ra_loss_final, dim3(1), dim3(64), 0, st, s->loss_part, (int64_t)gp, invP, loss);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  if (grad && s->N > 0) {
+    fm_timed timer(ctx, FM_K_RA_CAMERA, st);
+    hipLaunchKernelGGL(k_ra_camera, dim3(grid_for((int64_t)s->N * 16, kBlock)), dim3(kBlock), 0, st, params,
+                       s->cam_ptr, s->cam_items, s->contrib, s->N, grad);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  return FM_OK;
+}
+
+extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rrel, float* params, float* m, float* v,
+                                       int32_t K, const fm_adam_cfg* cfg, double* loss_trace, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ra_check(ctx, s, "fm_rotation_solve");
+  if (rc != FM_OK) return rc;
+  if (!cfg || (s->P > 0 && !Rrel) || (s->N > 0 && (!params || !m || !v)))
+    return fm_fail(ctx, FM_EINVAL, "fm_rotation_solve: NULL argument");
+  if (K < 0) return fm_fail(ctx, FM_EINVAL, "fm_rotation_solve: K < 0");
+  if (cfg->lr_total_steps <= 0 || cfg->lr_step0 < 0 || cfg->adam_step0 < 0 || !(cfg->lr_final_frac > 0.0f) ||
+      !(cfg->lr_rot >= 0.0f) ||
+      !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f && cfg->eps >= 0.0f))
+    return fm_fail(ctx, FM_EINVAL, "fm_rotation_solve: bad Adam configuration");
+  if (K == 0 || s->N == 0) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (s->ra_coop_blocks <= 0) {
+    int per_cu = 0;
+    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ra_solve, kSolveBlock, 0));
+    s->ra_coop_blocks = per_cu * ctx->num_cu;
+    if (s->ra_coop_blocks <= 0) return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative rotation kernel");
+  }
+  // sized like the epipolar loop
+  int64_t want = grid_for(s->P, kSolveBlock);
+  const int64_t want_c = grid_for((int64_t)s->N * 16, kSolveBlock);
+  if (want_c > want) want = want_c;
+  if (want > (s->P < 32768 ? 16 : 192)) want = s->P < 32768 ? 16 : 192;
+  if (cfg->blocks > 0) want = cfg->blocks;
+  if (want < 1) want = 1;
+  if (want > s->ra_coop_blocks) want = s->ra_coop_blocks;
+  if (want > s->loss_part_cap) want = s->loss_part_cap;
+  RaArgs a;
+  a.params = params; a.m = m; a.v = v;
+  a.cams = s->pair_cams; a.Rrel = Rrel; a.cam_ptr = s->cam_ptr; a.cam_items = s->cam_items;
+  a.contrib = s->contrib; a.rot = s->rot; a.part = s->loss_part; a.trace = loss_trace; a.bar = s->bar;
+  a.P = s->P; a.N = s->N; a.K = K;
+  a.invP = s->P > 0 ? 1.0 / (double)s->P : 0.0;
+  a.lr = cfg->lr_rot; a.log_frac = log((double)cfg->lr_final_frac);
+  a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;
+  a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
+  void* args[] = {&a};
+  FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
+  fm_timed timer(ctx, FM_K_RA_SOLVE, st);
+  hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_solve, dim3((unsigned)want), dim3(kSolveBlock), args, 0, st);
+  if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+  return FM_OK;
+}
