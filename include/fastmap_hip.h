@@ -287,6 +287,28 @@ fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* scene, const float* Rrel, flo
                             float* v, int32_t K, const fm_adam_cfg* cfg, double* loss_trace,
                             fm_stream stream);
 
+/* Initial rotations by the column-wise least-squares problems of the
+ * appendix on rotation initialisation:
+ *   first columns  x = the unit vector minimising sum_n |x_j - R^{i->j} x_i|^2
+ *                  over stacked 3-vectors (the eigenvector of the smallest
+ *                  eigenvalue of its 3N x 3N matrix), then x_c / |x_c|;
+ *   second columns the same with the pair term scaled 1/P plus
+ *                  (1/N) sum_c (c1_c . y_c)^2, normalised per camera, made
+ *                  orthogonal to c1_c by Gram-Schmidt;
+ * params [N,6] float32 receives (c1, c2) per camera (the third column is
+ * c1 x c2 by the 6D map).  Each eigenvector comes from `steps` Lanczos steps
+ * (at most 3N) with full reorthogonalisation in one persistent cooperative
+ * launch, started from start[col] ([2, 3N] float64, device; the caller's
+ * random vectors), and the smallest eigenpair of the Lanczos tridiagonal
+ * matrix.  info [4] double (device, NULL = not written): smallest eigenvalue
+ * and steps taken, first then second problem.  The pair graph must be
+ * connected (a camera in no pair makes the first problem's minimiser
+ * meaningless); an empty graph returns FM_ESHAPE.  Uses a per-scene
+ * workspace of (steps + 5) x 3N doubles, grown on demand (the growing call
+ * synchronises the device). */
+fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* scene, const float* Rrel, const double* start,
+                           int32_t steps, float* params, double* info, fm_stream stream);
+
 /* ------------------------------------------------------------------ a9: learned weights */
 
 /* Learned robust weights (an addition to the paper's IRLS, Sec. 3.3): a

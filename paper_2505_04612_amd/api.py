@@ -383,6 +383,19 @@ def rotation_solve(scene: Scene, Rrel: torch.Tensor, params6: torch.Tensor, m: t
         _ptr(loss_trace), _stream()))
 
 
+def rotation_init(scene: Scene, Rrel: torch.Tensor, start: torch.Tensor, steps: int = 300):
+    """(params [N,6] float32, info [4] float64) from the column-wise
+    least-squares initialisation; start [2, 3N] float64 random vectors."""
+    dev = scene.ctx.device
+    _require(Rrel, torch.float32, (scene.num_pairs, 9), "Rrel", dev)
+    _require(start, torch.float64, (2, 3 * scene.num_cams), "start", dev)
+    params = torch.empty((scene.num_cams, 6), dtype=torch.float32, device=dev)
+    info = torch.zeros(4, dtype=torch.float64, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_rotation_init(scene.ctx.handle, scene.handle, _ptr(Rrel), _ptr(start),
+                                                           int(steps), _ptr(params), _ptr(info), _stream()))
+    return params, info
+
+
 # ------------------------------------------------------------------ a9: learned weights
 
 MLP_SHAPES = {"W1": (64, 3), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (1, 64), "b3": (1,)}

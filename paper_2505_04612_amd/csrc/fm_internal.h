@@ -113,6 +113,10 @@ struct fm_scene {
   double* ta_stats = nullptr;     // [ta_runs_cap, 4] centroid and mean norm of each run
   int ta_coop_blocks = 0;         // max co-resident blocks of the translation loop
   int ra_coop_blocks = 0;         // max co-resident blocks of the rotation loop
+  // rotation initialisation workspace (Lanczos basis), grown on demand
+  int64_t lz_cap = 0;             // doubles held by lz
+  double* lz = nullptr;           // basis [m+1, 3N], work vector, dots, tridiagonal, Ritz coefficients
+  int lz_coop_blocks = 0;         // max co-resident blocks of the Lanczos kernel
 };
 
 // Error reporting helpers: set ctx->err and return the status.

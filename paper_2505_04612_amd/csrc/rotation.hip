@@ -12,6 +12,8 @@
 
 namespace {
 
+__device__ inline double pick3d(const double a[3], int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
+
 // One pair's geodesic term and its record, float64.  With Q = R^{i->j},
 // M = R_j^T Q R_i, c = (tr M - 1)/2 and d = arccos(c) (c clipped to
 // [-1, 1]): dd/dc = -1/sqrt(1 - c^2) (0 where |c| = 1), dc/dR_j = Q R_i / 2
@@ -252,6 +254,312 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ initialisation (column-wise least squares)
+
+// The quadratic forms of the appendix on rotation initialisation, as an
+// operator on stacked 3-vectors v [N,3]:
+//   (A v)_c = sum over pairs n = (i, j) containing c of
+//             v_j - Q v_i          (c = j),
+//             Q^T Q v_i - Q^T v_j  (c = i),
+// which is x^T A x = sum_n |x_j - Q x_i|^2; the second-column problem uses
+// alpha A + beta diag(u_c u_c^T) with alpha = 1/P, beta = 1/N and u the
+// first columns.  The smallest eigenvector comes from Lanczos with full
+// (twice applied) classical Gram-Schmidt reorthogonalisation, the smallest
+// eigenpair of the tridiagonal matrix (Sturm bisection, inverse iteration)
+// and the Ritz vector.
+
+struct LzArgs {
+  const int32_t* cams;
+  const float* Rrel;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  const double* start;   // [n]
+  const double* u;       // [n] or null (first columns for the second problem)
+  double* V;             // [m + 1, n]
+  double* w;             // [n]
+  double* h;             // [m + 1] dots of the current step
+  double* part;          // [waves] partial sums
+  double* alpha;         // [m]
+  double* beta;          // [m]
+  double* s;             // [m] Ritz coefficients; also [3m] scratch after it
+  double* out;           // [n] Ritz vector
+  double* info;          // [2]: Ritz value, steps taken
+  unsigned* bar;
+  int64_t n;
+  int32_t N;
+  int32_t m;
+  double op_alpha, op_beta;
+};
+
+// Sum over the grid of one double per thread, returned in every thread
+// (per-wavefront sums, then every workgroup adds them in the same order).
+__device__ inline double grid_allsum(double v, double* part, double* lds1, unsigned* bar, int64_t gwave, int64_t nwaves) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
+  if ((threadIdx.x & 63) == 0) part[gwave] = v;
+  grid_barrier(bar);
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int64_t k = 0; k < nwaves; ++k) t += part[k];
+    lds1[0] = t;
+  }
+  __syncthreads();
+  const double t = lds1[0];
+  __syncthreads();
+  return t;
+}
+
+// y = op(v) for camera c in every lane of its 16-lane row.
+__device__ inline void lz_apply(const LzArgs& a, const double* __restrict__ v, int64_t c, int l16, double y[3]) {
+  y[0] = y[1] = y[2] = 0.0;
+  const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
+  double vc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) vc[k] = v[3 * c + k];
+  for (int q = lo + l16; q < hi; q += 16) {
+    const int item = a.cam_items[q];
+    const int64_t n = item >> 1;
+    const bool is_j = item & 1;
+    const int other = a.cams[2 * n + (is_j ? 0 : 1)];
+    double Q[3][3], vo[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Q[r][k] = (double)a.Rrel[9 * n + 3 * r + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vo[k] = v[3 * (int64_t)other + k];
+    if (is_j) {
+      // v_j - Q v_i
+#pragma unroll
+      for (int r = 0; r < 3; ++r) y[r] += vc[r] - (Q[r][0] * vo[0] + Q[r][1] * vo[1] + Q[r][2] * vo[2]);
+    } else {
+      // Q^T (Q v_i - v_j)
+      double t[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) t[r] = Q[r][0] * vc[0] + Q[r][1] * vc[1] + Q[r][2] * vc[2] - vo[r];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) y[k] += Q[0][k] * t[0] + Q[1][k] * t[1] + Q[2][k] * t[2];
+    }
+  }
+#pragma unroll
+  for (int s = 8; s >= 1; s >>= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y[k] += __shfl_xor(y[k], s);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) y[k] *= a.op_alpha;
+  if (a.u) {
+    double uc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) uc[k] = a.u[3 * c + k];
+    const double d = uc[0] * vc[0] + uc[1] * vc[1] + uc[2] * vc[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) y[k] += a.op_beta * uc[k] * d;
+  }
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (alpha, beta) below x
+// (Sturm sequence of the LDL^T pivots).
+__device__ inline int sturm_count(const double* alpha, const double* beta, int m, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < m; ++i) {
+    const double b2 = i > 0 ? beta[i - 1] * beta[i - 1] : 0.0;
+    d = alpha[i] - x - (i > 0 ? b2 / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Smallest eigenpair of the m x m symmetric tridiagonal matrix (one thread):
+// bisection on the Sturm count, then inverse iteration with a pivoted
+// tridiagonal solve.  s [m] receives the unit eigenvector; scratch [3m].
+__device__ inline double tridiag_smallest(const double* alpha, const double* beta, int m, double* s, double* scratch) {
+  double lo = alpha[0], hi = alpha[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i + 1 < m ? fabs(beta[i]) : 0.0);
+    lo = fmin(lo, alpha[i] - r);
+    hi = fmax(hi, alpha[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(1.0, fabs(lo) + fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(alpha, beta, m, mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  const double theta = 0.5 * (lo + hi);
+  const double sigma = theta - 1e-10 * fmax(1.0, fabs(theta));
+  // (T - sigma I) z = s by Gaussian elimination with partial pivoting
+  // (rows i and i+1 may swap; the factors have up to two superdiagonals)
+  double* u1 = scratch;          // first superdiagonal of U
+  double* u2 = scratch + m;      // second superdiagonal of U
+  double* dd = scratch + 2 * m;  // diagonal of U
+  for (int i = 0; i < m; ++i) s[i] = 1.0;
+  for (int iter = 0; iter < 3; ++iter) {
+    // factor and solve in one sweep: row i holds (dd[i], u1[i], u2[i])
+    double* rhs = s;
+    double cur_d = alpha[0] - sigma, cur_u1 = m > 1 ? beta[0] : 0.0, cur_u2 = 0.0;
+    double cur_r = rhs[0];
+    for (int i = 0; i < m; ++i) {
+      if (i + 1 < m) {
+        const double nb = beta[i];                         // sub-diagonal entry of row i+1
+        const double nd = alpha[i + 1] - sigma, nu1 = i + 2 < m ? beta[i + 1] : 0.0;
+        const double nr = rhs[i + 1];
+        if (fabs(cur_d) >= fabs(nb)) {
+          const double l = nb / (cur_d != 0.0 ? cur_d : 1e-300);
+          dd[i] = cur_d; u1[i] = cur_u1; u2[i] = cur_u2; rhs[i] = cur_r;
+          cur_d = nd - l * cur_u1;
+          cur_u1 = nu1 - l * cur_u2;
+          cur_u2 = 0.0;
+          cur_r = nr - l * cur_r;
+        } else {
+          const double l = cur_d / nb;
+          dd[i] = nb; u1[i] = nd; u2[i] = nu1; rhs[i] = nr;
+          const double od = cur_d, ou1 = cur_u1, ou2 = cur_u2, orr = cur_r;
+          (void)od;
+          cur_d = ou1 - l * nd;
+          cur_u1 = ou2 - l * nu1;
+          cur_u2 = 0.0;
+          cur_r = orr - l * nr;
+        }
+      } else {
+        dd[i] = cur_d != 0.0 ? cur_d : 1e-300; u1[i] = 0.0; u2[i] = 0.0; rhs[i] = cur_r;
+      }
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double t = rhs[i];
+      if (i + 1 < m) t -= u1[i] * s[i + 1];
+      if (i + 2 < m) t -= u2[i] * s[i + 2];
+      s[i] = t / (dd[i] != 0.0 ? dd[i] : 1e-300);
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm += s[i] * s[i];
+    nrm = 1.0 / sqrt(nrm);
+    for (int i = 0; i < m; ++i) s[i] *= nrm;
+  }
+  return theta;
+}
+
+__global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
+  __shared__ double lds1[1];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const int row = lane >> 4, l16 = lane & 15;
+  const int64_t n = a.n;
+  // q0 = start / |start|
+  double acc = 0.0;
+  for (int64_t i = gtid; i < n; i += gsize) acc += a.start[i] * a.start[i];
+  const double inv0 = 1.0 / sqrt(grid_allsum(acc, a.part, lds1, a.bar, gwave, nwaves));
+  for (int64_t i = gtid; i < n; i += gsize) a.V[i] = a.start[i] * inv0;
+  grid_barrier(a.bar);
+  int m = a.m;
+  for (int k = 0; k < a.m; ++k) {
+    const double* q = a.V + (int64_t)k * n;
+    // w = op(q_k)
+    for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += 4 * nwaves) {
+      const int64_t c = c0 + row;
+      if (c < a.N) {   // whole rows: the row exchanges stay within live rows
+        double y[3];
+        lz_apply(a, q, c, l16, y);
+        if (l16 < 3) a.w[3 * c + l16] = pick3d(y, l16);
+      }
+    }
+    grid_barrier(a.bar);
+    // two passes of classical Gram-Schmidt against q_0 .. q_k
+    double alpha_k = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int64_t j = gwave; j <= k; j += nwaves) {
+        const double* vj = a.V + j * n;
+        double d = 0.0;
+        for (int64_t i = lane; i < n; i += 64) d += vj[i] * a.w[i];
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) d += __shfl_xor(d, s);
+        if (lane == 0) a.h[j] = d;
+      }
+      grid_barrier(a.bar);
+      alpha_k += a.h[k];
+      double nrm = 0.0;
+      for (int64_t i = gtid; i < n; i += gsize) {
+        double wi = a.w[i];
+        for (int j = 0; j <= k; ++j) wi -= a.h[j] * a.V[(int64_t)j * n + i];
+        a.w[i] = wi;
+        nrm += wi * wi;
+      }
+      if (pass == 0) {
+        grid_barrier(a.bar);
+      } else {
+        const double b = sqrt(grid_allsum(nrm, a.part, lds1, a.bar, gwave, nwaves));
+        if (gtid == 0) {
+          a.alpha[k] = alpha_k;
+          a.beta[k] = b;
+        }
+        // an invariant subspace: the basis so far spans the answer
+        if (!(b > 1e-12 * fmax(1.0, fabs(alpha_k))) || k + 1 == a.m) {
+          m = k + 1;
+          break;
+        }
+        const double inv = 1.0 / b;
+        double* qn = a.V + (int64_t)(k + 1) * n;
+        for (int64_t i = gtid; i < n; i += gsize) qn[i] = a.w[i] * inv;
+      }
+    }
+    if (m == k + 1) break;
+    grid_barrier(a.bar);
+  }
+  grid_barrier(a.bar);
+  if (gtid == 0) {
+    const double theta = tridiag_smallest(a.alpha, a.beta, m, a.s, a.s + a.m);
+    a.info[0] = theta;
+    a.info[1] = (double)m;
+  }
+  grid_barrier(a.bar);
+  for (int64_t i = gtid; i < n; i += gsize) {
+    double x = 0.0;
+    for (int j = 0; j < m; ++j) x += a.s[j] * a.V[(int64_t)j * n + i];
+    a.out[i] = x;
+  }
+}
+
+// c1 = x_c / |x_c| per camera (first columns); also copied to u for the
+// second problem.
+__global__ __launch_bounds__(kBlock) void k_ra_unit_rows(const double* __restrict__ x, int32_t N, double* __restrict__ u) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const double a = x[3 * c], b = x[3 * c + 1], d = x[3 * c + 2];
+  const double r = 1.0 / sqrt(a * a + b * b + d * d);
+  u[3 * c] = a * r;
+  u[3 * c + 1] = b * r;
+  u[3 * c + 2] = d * r;
+}
+
+// Second columns: y_c normalised, made orthogonal to c1 (Gram-Schmidt) and
+// normalised again; the parameters are (c1, c2), the rotation's first two
+// columns (its third is c1 x c2 by the 6D map).
+__global__ __launch_bounds__(kBlock) void k_ra_finish(const double* __restrict__ c1, const double* __restrict__ y,
+                                                      int32_t N, float* __restrict__ params) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  double v[3], e[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[k] = y[3 * c + k];
+    e[k] = c1[3 * c + k];
+  }
+  double r = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] *= r;
+  const double d = v[0] * e[0] + v[1] * e[1] + v[2] * e[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] -= d * e[k];
+  r = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    params[6 * c + k] = (float)e[k];
+    params[6 * c + 3 + k] = (float)(v[k] * r);
+  }
+}
+
 fm_status ra_check(fm_ctx* ctx, fm_scene* s, const char* fn) {
   if (!s) return fm_fail(ctx, FM_EINVAL, "%s: scene is NULL", fn);
   if (s->ctx != ctx) return fm_fail(ctx, FM_EINVAL, "%s: scene belongs to another context", fn);
@@ -334,5 +642,84 @@ extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rr
   fm_timed timer(ctx, FM_K_RA_SOLVE, st);
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_solve, dim3((unsigned)want), dim3(kSolveBlock), args, 0, st);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+  return FM_OK;
+}
+
+extern "C" fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* s, const float* Rrel, const double* start,
+                                      int32_t steps, float* params, double* info, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  fm_status rc = ra_check(ctx, s, "fm_rotation_init");
+  if (rc != FM_OK) return rc;
+  if (s->N == 0) return FM_OK;
+  if (!start || !params || (s->P > 0 && !Rrel)) return fm_fail(ctx, FM_EINVAL, "fm_rotation_init: NULL argument");
+  if (steps < 1) return fm_fail(ctx, FM_EINVAL, "fm_rotation_init: steps must be >= 1");
+  if (s->P == 0) return fm_fail(ctx, FM_ESHAPE, "fm_rotation_init: the pair graph is empty");
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = 3 * (int64_t)s->N;
+  const int32_t m = steps < n ? steps : (int32_t)n;
+  if (s->lz_coop_blocks <= 0) {
+    int per_cu = 0;
+    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ra_lanczos, kSolveBlock, 0));
+    s->lz_coop_blocks = per_cu * ctx->num_cu;
+    if (s->lz_coop_blocks <= 0) return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative Lanczos kernel");
+  }
+  // about one 16-lane row per camera, at most 16 workgroups (the solve is a
+  // chain of grid-wide reductions), at the co-resident limit
+  int64_t want = grid_for(n / 3 * 16, kSolveBlock);
+  if (want > 16) want = 16;
+  if (want < 1) want = 1;
+  if (want > s->lz_coop_blocks) want = s->lz_coop_blocks;
+  const int64_t waves = want * (kSolveBlock / 64);
+  // layout: V [(m+1) n] | w [n] | out [n] | c1 [n] | y [n] | h [m+1] | part [waves] | alpha [m] | beta [m] |
+  //         s [4m] | info [4]
+  const int64_t need = (int64_t)(m + 1) * n + 4 * n + (m + 1) + waves + 2 * (int64_t)m + 4 * (int64_t)m + 4;
+  if (need > s->lz_cap) {
+    FM_HIP_TRY(ctx, hipDeviceSynchronize());
+    (void)hipFree(s->lz);
+    s->lz = nullptr;
+    s->lz_cap = 0;
+    if (hipMalloc(&s->lz, sizeof(double) * need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fm_fail(ctx, FM_ENOMEM, "fm_rotation_init: workspace of %lld doubles", (long long)need);
+    }
+    s->lz_cap = need;
+  }
+  double* V = s->lz;
+  double* w = V + (int64_t)(m + 1) * n;
+  double* out = w + n;
+  double* c1 = out + n;
+  double* y = c1 + n;
+  double* h = y + n;
+  double* part = h + (m + 1);
+  double* alpha = part + waves;
+  double* beta = alpha + m;
+  double* sv = beta + m;
+  double* inf = sv + 4 * (int64_t)m;
+  LzArgs a;
+  a.cams = s->pair_cams; a.Rrel = Rrel; a.cam_ptr = s->cam_ptr; a.cam_items = s->cam_items;
+  a.V = V; a.w = w; a.h = h; a.part = part; a.alpha = alpha; a.beta = beta; a.s = sv; a.bar = s->bar;
+  a.n = n; a.N = s->N; a.m = m;
+  fm_timed timer(ctx, FM_K_RA_INIT, st);
+  for (int col = 0; col < 2; ++col) {
+    a.start = start + col * n;
+    a.u = col == 0 ? nullptr : c1;
+    a.op_alpha = col == 0 ? 1.0 : 1.0 / (double)s->P;
+    a.op_beta = col == 0 ? 0.0 : 1.0 / (double)s->N;
+    a.out = col == 0 ? out : y;
+    a.info = inf + 2 * col;
+    void* args[] = {&a};
+    FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_lanczos, dim3((unsigned)want), dim3(kSolveBlock), args,
+                                              0, st);
+    if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+    if (col == 0) {
+      hipLaunchKernelGGL(k_ra_unit_rows, dim3(grid_for(s->N, kBlock)), dim3(kBlock), 0, st, out, s->N, c1);
+      FM_CHECK_LAUNCH(ctx);
+    }
+  }
+  hipLaunchKernelGGL(k_ra_finish, dim3(grid_for(s->N, kBlock)), dim3(kBlock), 0, st, c1, y, s->N, params);
+  FM_CHECK_LAUNCH(ctx);
+  if (info) FM_HIP_TRY(ctx, hipMemcpyAsync(info, inf, sizeof(double) * 4, hipMemcpyDeviceToDevice, st));
   return FM_OK;
 }

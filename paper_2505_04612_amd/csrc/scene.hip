@@ -246,6 +246,7 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->ta_rec);
   (void)hipFree(s->ta_part);
   (void)hipFree(s->ta_stats);
+  (void)hipFree(s->lz);
   delete s;
 }
 

@@ -134,3 +134,72 @@ def test_empty_graph():
     api.rotation_solve(s, Q, th, torch.zeros_like(th), torch.zeros_like(th), 10, 1e-2, 1e-2)
     assert torch.equal(before, th)
     assert s.barrier_failures() == 0
+
+
+def _init_gpu(ctx, s, Q32, N, steps, seed=0):
+    from paper_2505_04612_amd import api
+    start = np.random.default_rng(seed).normal(size=(2, 3 * N))
+    p, info = api.rotation_init(s, _dev(ctx, Q32), _dev(ctx, start), steps)
+    assert s.barrier_failures() == 0
+    return p.cpu().numpy(), info.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,steps", [("tiny", 300), ("medium", 300), ("medium", 150)])
+def test_initialisation_parity(name, steps):
+    ctx = _ctx()
+    sc = helpers.scene(name)
+    inp = synth.rotation_inputs(sc)
+    N = sc.R_gt.shape[0]
+    s = _graph_scene(ctx, N, sc.pairs)
+    Q = inp.R_rel.reshape(-1, 9).astype(np.float32)
+    got, info = _init_gpu(ctx, s, Q, N, steps)
+    R_or, oinfo = ra.initialise(sc.pairs, _f32(Q).reshape(-1, 3, 3), N)
+    # both problems' smallest eigenvalues (tiny: 3N = 60 steps span the space)
+    w1 = np.linalg.eigvalsh(oinfo["A"])[0]
+    w2 = np.linalg.eigvalsh(oinfo["B"])[0]
+    assert abs(info[0] - w1) <= 1e-10 * w1 and abs(info[2] - w2) <= 1e-8 * w2, (info, w1, w2)
+    assert info[1] == min(steps, 3 * N)
+    # the rotations, up to the sign of each eigenvector (a global rotation):
+    # float32 parameters, so ~1e-7 rad, plus the arccos floor of the metric
+    e = ra.relative_rotation_errors(ra.rotations(_f32(got)), R_or, sc.pairs)
+    assert e.max() < 1e-3, e.max()
+
+
+def test_initialisation_noise_free_is_exact():
+    ctx = _ctx()
+    sc = helpers.scene("tiny")
+    inp = synth.rotation_inputs(sc, sigma_deg=0.0, outlier_frac=0.0)
+    N = sc.R_gt.shape[0]
+    s = _graph_scene(ctx, N, sc.pairs)
+    got, info = _init_gpu(ctx, s, inp.R_rel.reshape(-1, 9).astype(np.float32), N, 300)
+    # the minimiser is any vector of the three-dimensional null space: each
+    # gives the truth up to a global rotation
+    assert abs(info[0]) < 1e-6
+    e = ra.relative_rotation_errors(ra.rotations(_f32(got)), sc.R_gt, sc.pairs)
+    assert e.max() < 1e-3, e.max()
+
+
+def test_whole_stage_initialise_then_solve():
+    from paper_2505_04612_amd import api
+    ctx = _ctx()
+    sc = helpers.scene("medium")
+    inp = synth.rotation_inputs(sc)
+    N = sc.R_gt.shape[0]
+    s = _graph_scene(ctx, N, sc.pairs)
+    Q = inp.R_rel.reshape(-1, 9).astype(np.float32)
+    p0, _ = _init_gpu(ctx, s, Q, N, 300)
+    got, _ = _solve_gpu(ctx, s, Q, p0, 500, 1e-2, 1e-2)
+    R0, _ = ra.initialise(sc.pairs, _f32(Q).reshape(-1, 3, 3), N)
+    want, _ = ra.solve(_params(R0), sc.pairs, _f32(Q).reshape(-1, 3, 3), 500, 1e-2, 1e-2)
+    e = ra.relative_rotation_errors(ra.rotations(_f32(got)), ra.rotations(want), sc.pairs)
+    assert e.max() < 0.05 and np.median(e) < 0.005, (e.max(), np.median(e))
+
+
+def test_initialisation_rejects_an_empty_graph():
+    from paper_2505_04612_amd import api
+    from paper_2505_04612_amd._lib import FastMapError
+    ctx = _ctx()
+    s = _graph_scene(ctx, 3, np.zeros((0, 2), np.int32))
+    with pytest.raises(FastMapError):
+        api.rotation_init(s, torch.zeros((0, 9), dtype=torch.float32, device=ctx.device),
+                          torch.ones((2, 9), dtype=torch.float64, device=ctx.device))
