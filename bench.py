@@ -26,7 +26,14 @@ Reported (one JSON line):
                   in one persistent launch of 1,000 Adam steps, the merge,
                   and a final 1,000-step loop; device time per iteration,
                   accuracy against the true centres, and the FP64 oracle's
-                  iteration rate on a bounded sample.
+                  iteration rate on a bounded sample;
+  rotation_averaging
+                  the first pose stage on the same pair graph (Sec. 3.3,
+                  Global Rotation): the column-wise least-squares
+                  initialisation (two Lanczos eigenvector solves) and 500
+                  Adam steps on the geodesic objective; device times,
+                  accuracy against the true rotations, and the FP64 oracle
+                  (dense eigendecomposition, iterations) on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -204,6 +211,68 @@ def bench_translation(ctx, s, sc, runs: int = 4, iters: int = 1000, final_iters:
     }
 
 
+def bench_rotation(ctx, s, sc, steps: int = 300, iters: int = 500, cpu_budget: float = 3.0) -> dict:
+    """Global rotation averaging on the scene's pair graph: noisy relative
+    rotations (2 deg, 10 % outlier pairs) from the true poses, the
+    column-wise least-squares initialisation and the geodesic Adam loop."""
+    import numpy as np
+    import torch
+
+    from paper_2505_04612_amd import _lib, api, rotation, synth
+    dev = ctx.device
+    inp = synth.rotation_inputs(sc)
+    Q = torch.from_numpy(inp.R_rel.reshape(-1, 9).astype(np.float32)).to(dev)
+    sched = rotation.RotationSchedule(lanczos_steps=steps, iters=iters)
+    rotation.average(s, Q, sched)          # warm-up
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    p, info = rotation.average(s, Q, sched)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    init_ms, _ = ctx.profile_read(_lib.K_RA_INIT)
+    solve_ms, _ = ctx.profile_read(_lib.K_RA_SOLVE)
+    ctx.profile(False)
+    bar_fail = s.barrier_failures()
+    from oracle import rotation as ra
+    P = sc.num_pairs
+    e_init = ra.relative_rotation_errors(ra.rotations(info["init"].cpu().numpy().astype(np.float64)), sc.R_gt,
+                                         sc.pairs)
+    e_fin = ra.relative_rotation_errors(ra.rotations(p.cpu().numpy().astype(np.float64)), sc.R_gt, sc.pairs)
+    lz = info["lanczos"].cpu().numpy()
+    # the oracle as it stands: its dense initialisation, then Adam steps
+    Q64 = inp.R_rel.astype(np.float32).astype(np.float64)
+    t = time.perf_counter()
+    R0, _ = ra.initialise(sc.pairs, Q64, sc.num_cams)
+    t_init = time.perf_counter() - t
+    th = np.concatenate([R0[:, :, 0], R0[:, :, 1]], 1)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    n_it, t_it = 0, 0.0
+    while t_it < cpu_budget or n_it < 5:
+        t = time.perf_counter()
+        _, g = ra.loss_grad(th, sc.pairs, Q64)
+        th, m, v = ra.adam_step(th, g, m, v, n_it + 1, ra.lr_at(sched.lr, sched.lr_final_frac, iters, n_it))
+        t_it += time.perf_counter() - t
+        n_it += 1
+    return {
+        "kernels": "k_ra_lanczos (2 persistent launches, one per column) + k_ra_solve (persistent geodesic "
+                   "loss + adjoint + Adam)",
+        "pairs": P, "cameras": sc.num_cams, "lanczos_steps": [int(lz[1]), int(lz[3])], "iters": iters,
+        "init_ms": init_ms, "us_per_lanczos_step": init_ms * 1e3 / max(lz[1] + lz[3], 1),
+        "iters_per_s": iters / (solve_ms / 1e3), "us_per_iter": solve_ms * 1e3 / iters,
+        "stage_wall_ms": wall * 1e3,
+        "bound": "latency (Lanczos: 6 grid barriers per step; solve: 2 per iteration)",
+        "rel_rot_err_vs_truth_deg": {"init_median": float(np.median(e_init)), "init_max": float(e_init.max()),
+                                     "final_median": float(np.median(e_fin)), "final_max": float(e_fin.max())},
+        "inputs": "relative rotations from the true poses, 2 deg noise, 10 % random-rotation outlier pairs",
+        "barrier_failures": bar_fail,
+        "cpu_baseline": {"init_ms": t_init * 1e3, "iters_per_s": n_it / t_it, "kind": "oracle",
+                         "sample": f"dense 3N x 3N eigendecompositions (numpy.linalg.eigh) and {n_it} FP64 "
+                                   f"loss+gradient+Adam steps over {P} pairs"},
+    }
+
+
 def traffic_entry(alg_bytes: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current Gram kernel source."""
@@ -224,6 +293,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-translation", action="store_true", help="skip the translation-averaging leg")
+    ap.add_argument("--no-rotation", action="store_true", help="skip the rotation-averaging leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
@@ -329,6 +399,9 @@ def main() -> int:
     if not args.no_translation:
         log("[bench] translation averaging on the same pair graph")
         out["translation_averaging"] = bench_translation(ctx, s, sc)
+    if not args.no_rotation:
+        log("[bench] rotation averaging on the same pair graph")
+        out["rotation_averaging"] = bench_rotation(ctx, s, sc)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc, coords, theta0, sd, args.cpu_budget)

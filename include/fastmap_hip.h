@@ -296,18 +296,20 @@ fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* scene, const float* Rrel, flo
  *                  (1/N) sum_c (c1_c . y_c)^2, normalised per camera, made
  *                  orthogonal to c1_c by Gram-Schmidt;
  * params [N,6] float32 receives (c1, c2) per camera (the third column is
- * c1 x c2 by the 6D map).  Each eigenvector comes from `steps` Lanczos steps
- * (at most 3N) with full reorthogonalisation in one persistent cooperative
- * launch, started from start[col] ([2, 3N] float64, device; the caller's
- * random vectors), and the smallest eigenpair of the Lanczos tridiagonal
- * matrix.  info [4] double (device, NULL = not written): smallest eigenvalue
+ * c1 x c2 by the 6D map).  Each eigenvector comes from at most `steps`
+ * Lanczos steps (at most 3N and 4096) with full reorthogonalisation in one
+ * persistent cooperative launch of `blocks` workgroups of 512 threads
+ * (0 = automatic), started from start[col] ([2, 3N] float64, device; the
+ * caller's random vectors), and the smallest eigenpair of the Lanczos
+ * tridiagonal matrix; the steps end early once the Ritz pair's residual
+ * bound |beta_k s_k| is below 1e-11 of |T| (checked every 10 steps).  info [4] double (device, NULL = not written): smallest eigenvalue
  * and steps taken, first then second problem.  The pair graph must be
  * connected (a camera in no pair makes the first problem's minimiser
  * meaningless); an empty graph returns FM_ESHAPE.  Uses a per-scene
  * workspace of (steps + 5) x 3N doubles, grown on demand (the growing call
  * synchronises the device). */
 fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* scene, const float* Rrel, const double* start,
-                           int32_t steps, float* params, double* info, fm_stream stream);
+                           int32_t steps, int32_t blocks, float* params, double* info, fm_stream stream);
 
 /* ------------------------------------------------------------------ a9: learned weights */
 

@@ -88,7 +88,7 @@ _SIGNATURES = {
     "fm_translation_merge": (_S, [_P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "fm_rotation_loss_grad": (_S, [_P, _P, _P, _P, _P, _P, _P]),
     "fm_rotation_solve": (_S, [_P, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _P, _P]),
-    "fm_rotation_init": (_S, [_P, _P, _P, _P, _I32, _P, _P, _P]),
+    "fm_rotation_init": (_S, [_P, _P, _P, _P, _I32, _I32, _P, _P, _P]),
 }
 
 _lib = None

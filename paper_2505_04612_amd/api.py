@@ -383,7 +383,7 @@ def rotation_solve(scene: Scene, Rrel: torch.Tensor, params6: torch.Tensor, m: t
         _ptr(loss_trace), _stream()))
 
 
-def rotation_init(scene: Scene, Rrel: torch.Tensor, start: torch.Tensor, steps: int = 300):
+def rotation_init(scene: Scene, Rrel: torch.Tensor, start: torch.Tensor, steps: int = 300, blocks: int = 0):
     """(params [N,6] float32, info [4] float64) from the column-wise
     least-squares initialisation; start [2, 3N] float64 random vectors."""
     dev = scene.ctx.device
@@ -392,7 +392,8 @@ def rotation_init(scene: Scene, Rrel: torch.Tensor, start: torch.Tensor, steps: 
     params = torch.empty((scene.num_cams, 6), dtype=torch.float32, device=dev)
     info = torch.zeros(4, dtype=torch.float64, device=dev)
     check(scene.ctx.handle, scene.ctx.lib.fm_rotation_init(scene.ctx.handle, scene.handle, _ptr(Rrel), _ptr(start),
-                                                           int(steps), _ptr(params), _ptr(info), _stream()))
+                                                           int(steps), int(blocks), _ptr(params), _ptr(info),
+                                                           _stream()))
     return params, info
 
 

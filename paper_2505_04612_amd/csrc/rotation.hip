@@ -439,14 +439,21 @@ __device__ inline double tridiag_smallest(const double* alpha, const double* bet
   return theta;
 }
 
+// Lanczos steps between convergence checks, and the relative residual
+// bound |beta_k s_k| / |T| below which the Ritz pair is taken as converged.
+constexpr int kLzCheck = 10;
+constexpr int kLzMaxSteps = 4096;
+constexpr double kLzTol = 1e-11;
+
 __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
-  __shared__ double lds1[1];
+  extern __shared__ double hs[];   // [m + 1] dots of the current step, then [1] broadcast
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
   const int lane = threadIdx.x & 63;
   const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
   const int row = lane >> 4, l16 = lane & 15;
   const int64_t n = a.n;
+  double* lds1 = hs + a.m + 1;
   // q0 = start / |start|
   double acc = 0.0;
   for (int64_t i = gtid; i < n; i += gsize) acc += a.start[i] * a.start[i];
@@ -454,6 +461,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
   for (int64_t i = gtid; i < n; i += gsize) a.V[i] = a.start[i] * inv0;
   grid_barrier(a.bar);
   int m = a.m;
+  bool have_s = false;
   for (int k = 0; k < a.m; ++k) {
     const double* q = a.V + (int64_t)k * n;
     // w = op(q_k)
@@ -468,24 +476,46 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
     grid_barrier(a.bar);
     // two passes of classical Gram-Schmidt against q_0 .. q_k
     double alpha_k = 0.0;
+    bool stop = false;
     for (int pass = 0; pass < 2; ++pass) {
       for (int64_t j = gwave; j <= k; j += nwaves) {
         const double* vj = a.V + j * n;
-        double d = 0.0;
-        for (int64_t i = lane; i < n; i += 64) d += vj[i] * a.w[i];
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int64_t i = lane;
+        for (; i + 192 < n; i += 256) {
+          d0 += vj[i] * a.w[i];
+          d1 += vj[i + 64] * a.w[i + 64];
+          d2 += vj[i + 128] * a.w[i + 128];
+          d3 += vj[i + 192] * a.w[i + 192];
+        }
+        for (; i < n; i += 64) d0 += vj[i] * a.w[i];
+        double d = (d0 + d1) + (d2 + d3);
 #pragma unroll
         for (int s = 32; s >= 1; s >>= 1) d += __shfl_xor(d, s);
         if (lane == 0) a.h[j] = d;
       }
       grid_barrier(a.bar);
-      alpha_k += a.h[k];
+      for (int j = threadIdx.x; j <= k; j += blockDim.x) hs[j] = a.h[j];
+      __syncthreads();
+      alpha_k += hs[k];
+      // w_i -= sum_j h_j V[j][i], eight basis entries in flight per thread
       double nrm = 0.0;
       for (int64_t i = gtid; i < n; i += gsize) {
-        double wi = a.w[i];
-        for (int j = 0; j <= k; ++j) wi -= a.h[j] * a.V[(int64_t)j * n + i];
+        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int j = 0;
+        for (; j + 8 <= k + 1; j += 8) {
+          double v8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v8[u] = a.V[(int64_t)(j + u) * n + i];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) s8[u] += hs[j + u] * v8[u];
+        }
+        for (; j <= k; ++j) s8[0] += hs[j] * a.V[(int64_t)j * n + i];
+        const double wi = a.w[i] - (((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7])));
         a.w[i] = wi;
         nrm += wi * wi;
       }
+      __syncthreads();   // hs is rewritten by the next pass
       if (pass == 0) {
         grid_barrier(a.bar);
       } else {
@@ -494,23 +524,39 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
           a.alpha[k] = alpha_k;
           a.beta[k] = b;
         }
-        // an invariant subspace: the basis so far spans the answer
+        // an invariant subspace, the last step, or a converged Ritz pair
+        // (checked every kLzCheck steps by one thread; the verdict is read
+        // by all after a barrier)
         if (!(b > 1e-12 * fmax(1.0, fabs(alpha_k))) || k + 1 == a.m) {
-          m = k + 1;
-          break;
+          stop = true;
+        } else if ((k + 1) % kLzCheck == 0) {
+          grid_barrier(a.bar);   // alpha, beta of this step visible
+          if (gtid == 0) {
+            const double theta = tridiag_smallest(a.alpha, a.beta, k + 1, a.s, a.s + a.m);
+            double tn = 0.0;
+            for (int i = 0; i <= k; ++i) tn = fmax(tn, fabs(a.alpha[i]) + 2.0 * fabs(a.beta[i]));
+            a.info[0] = theta;
+            a.h[a.m] = (fabs(b * a.s[k]) <= kLzTol * fmax(tn, 1e-300)) ? 1.0 : 0.0;
+          }
+          grid_barrier(a.bar);
+          stop = a.h[a.m] != 0.0;
+          have_s = stop;
         }
-        const double inv = 1.0 / b;
-        double* qn = a.V + (int64_t)(k + 1) * n;
-        for (int64_t i = gtid; i < n; i += gsize) qn[i] = a.w[i] * inv;
+        if (stop) {
+          m = k + 1;
+        } else {
+          const double inv = 1.0 / b;
+          double* qn = a.V + (int64_t)(k + 1) * n;
+          for (int64_t i = gtid; i < n; i += gsize) qn[i] = a.w[i] * inv;
+        }
       }
     }
-    if (m == k + 1) break;
+    if (stop) break;
     grid_barrier(a.bar);
   }
   grid_barrier(a.bar);
   if (gtid == 0) {
-    const double theta = tridiag_smallest(a.alpha, a.beta, m, a.s, a.s + a.m);
-    a.info[0] = theta;
+    if (!have_s) a.info[0] = tridiag_smallest(a.alpha, a.beta, m, a.s, a.s + a.m);
     a.info[1] = (double)m;
   }
   grid_barrier(a.bar);
@@ -646,21 +692,24 @@ extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rr
 }
 
 extern "C" fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* s, const float* Rrel, const double* start,
-                                      int32_t steps, float* params, double* info, fm_stream stream) {
+                                      int32_t steps, int32_t blocks, float* params, double* info, fm_stream stream) {
   if (!ctx) return FM_EINVAL;
   fm_status rc = ra_check(ctx, s, "fm_rotation_init");
   if (rc != FM_OK) return rc;
   if (s->N == 0) return FM_OK;
   if (!start || !params || (s->P > 0 && !Rrel)) return fm_fail(ctx, FM_EINVAL, "fm_rotation_init: NULL argument");
   if (steps < 1) return fm_fail(ctx, FM_EINVAL, "fm_rotation_init: steps must be >= 1");
+  if (blocks < 0) return fm_fail(ctx, FM_EINVAL, "fm_rotation_init: blocks < 0");
   if (s->P == 0) return fm_fail(ctx, FM_ESHAPE, "fm_rotation_init: the pair graph is empty");
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = 3 * (int64_t)s->N;
   const int32_t m = steps < n ? steps : (int32_t)n;
+  if (m > kLzMaxSteps) return fm_fail(ctx, FM_EINVAL, "fm_rotation_init: steps above %d", kLzMaxSteps);
+  const size_t lds_bytes = sizeof(double) * (kLzMaxSteps + 2);
   if (s->lz_coop_blocks <= 0) {
     int per_cu = 0;
-    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ra_lanczos, kSolveBlock, 0));
+    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ra_lanczos, kSolveBlock, lds_bytes));
     s->lz_coop_blocks = per_cu * ctx->num_cu;
     if (s->lz_coop_blocks <= 0) return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative Lanczos kernel");
   }
@@ -668,12 +717,13 @@ extern "C" fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* s, const float* Rre
   // chain of grid-wide reductions), at the co-resident limit
   int64_t want = grid_for(n / 3 * 16, kSolveBlock);
   if (want > 16) want = 16;
+  if (blocks > 0) want = blocks;
   if (want < 1) want = 1;
   if (want > s->lz_coop_blocks) want = s->lz_coop_blocks;
   const int64_t waves = want * (kSolveBlock / 64);
-  // layout: V [(m+1) n] | w [n] | out [n] | c1 [n] | y [n] | h [m+1] | part [waves] | alpha [m] | beta [m] |
-  //         s [4m] | info [4]
-  const int64_t need = (int64_t)(m + 1) * n + 4 * n + (m + 1) + waves + 2 * (int64_t)m + 4 * (int64_t)m + 4;
+  // layout: V [(m+1) n] | w [n] | out [n] | c1 [n] | y [n] | h [m+2] | part [waves] | alpha [m] | beta [m] |
+  //         s [4m] | info [4]  (h [m+2]: the last slot carries the convergence verdict)
+  const int64_t need = (int64_t)(m + 1) * n + 4 * n + (m + 2) + waves + 2 * (int64_t)m + 4 * (int64_t)m + 4;
   if (need > s->lz_cap) {
     FM_HIP_TRY(ctx, hipDeviceSynchronize());
     (void)hipFree(s->lz);
@@ -691,7 +741,7 @@ extern "C" fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* s, const float* Rre
   double* c1 = out + n;
   double* y = c1 + n;
   double* h = y + n;
-  double* part = h + (m + 1);
+  double* part = h + (m + 2);
   double* alpha = part + waves;
   double* beta = alpha + m;
   double* sv = beta + m;
@@ -711,7 +761,7 @@ extern "C" fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* s, const float* Rre
     void* args[] = {&a};
     FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_lanczos, dim3((unsigned)want), dim3(kSolveBlock), args,
-                                              0, st);
+                                              lds_bytes, st);
     if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
     if (col == 0) {
       hipLaunchKernelGGL(k_ra_unit_rows, dim3(grid_for(s->N, kBlock)), dim3(kBlock), 0, st, out, s->N, c1);

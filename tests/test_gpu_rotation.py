@@ -158,7 +158,8 @@ def test_initialisation_parity(name, steps):
     w1 = np.linalg.eigvalsh(oinfo["A"])[0]
     w2 = np.linalg.eigvalsh(oinfo["B"])[0]
     assert abs(info[0] - w1) <= 1e-10 * w1 and abs(info[2] - w2) <= 1e-8 * w2, (info, w1, w2)
-    assert info[1] == min(steps, 3 * N)
+    # Lanczos stops once its residual bound is below 1e-11 of |T|
+    assert 1 <= info[1] <= min(steps, 3 * N)
     # the rotations, up to the sign of each eigenvector (a global rotation):
     # float32 parameters, so ~1e-7 rad, plus the arccos floor of the metric
     e = ra.relative_rotation_errors(ra.rotations(_f32(got)), R_or, sc.pairs)
