@@ -253,6 +253,25 @@ fm_status fm_translation_merge(fm_ctx* ctx, fm_scene* scene, const float* dirs, 
                                const float* centres, float* merged, int32_t* choice, double* cam_loss,
                                fm_stream stream);
 
+/* Relative-translation grid search (appendix on global translation,
+ * "Relative Translation"), before translation averaging: for every pair,
+ * with R_ij = R_j R_i^T from the rotations of params [N,9] float32 (a1, a2;
+ * t ignored), the candidate t among cand [C,3] float64 (unit vectors,
+ * device) with the lowest mean squared algebraic epipolar error
+ *     t^T A_n t / |Q_n|,  A_n = B^T W_n B,  B[:, k] = flatten([e_k]_x R_ij)
+ * (the squared residual x2~^T [t]_x R_ij x1~ averaged over the pair's
+ * matches, from its Gram W36 [P,36] float64 as fm_build_pair_grams writes
+ * it; |Q_n| from the scene's offsets).  The lowest candidate index wins among
+ * equal errors.  The error is even in t, so the winner is negated when its
+ * dot product with t_prior[n] ([P,3] float32) is negative; a pair without
+ * matches keeps t_prior.  Float64 arithmetic.
+ *   t_out   [P,3] float32 (required);
+ *   best    [P] int32 winning candidate (-1: kept prior), NULL = not written;
+ *   err_min [P] double its error, NULL = not written. */
+fm_status fm_translation_search(fm_ctx* ctx, fm_scene* scene, const double* W36, const float* params,
+                                const double* cand, int32_t C, const float* t_prior, float* t_out,
+                                int32_t* best, double* err_min, fm_stream stream);
+
 /* ------------------------------------------------------------------ rotation averaging */
 
 /* Global rotation averaging, the first pose stage (Sec. 3.3 "Global
@@ -362,7 +381,8 @@ fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_m
  *   (persistent translation loop), FM_K_TA_PAIR 7 and FM_K_TA_CAMERA 8 (the
  *   two kernels of fm_translation_loss_grad), FM_K_RA_SOLVE 9 (persistent
  *   rotation loop), FM_K_RA_PAIR 10 and FM_K_RA_CAMERA 11 (the two kernels of
- *   fm_rotation_loss_grad), FM_K_RA_INIT 12 (rotation initialisation).
+ *   fm_rotation_loss_grad), FM_K_RA_INIT 12 (rotation initialisation),
+ *   FM_K_TS_SEARCH 13 (relative-translation grid search).
  * fm_profile_enable synchronises the device and clears earlier records;
  * fm_profile_read waits for the recorded events and returns the summed
  * elapsed milliseconds and the launch count of one kernel (host outputs). */

@@ -349,6 +349,35 @@ def translation_merge(scene: Scene, dirs: torch.Tensor, centres: torch.Tensor):
     return merged, choice, cam
 
 
+def fibonacci_sphere(C: int, device) -> torch.Tensor:
+    """C near-uniform unit vectors (golden-angle spiral) [C,3] float64 on
+    `device`: the default candidate set of translation_search."""
+    k = torch.arange(C, dtype=torch.float64, device=device)
+    z = 1.0 - 2.0 * (k + 0.5) / C
+    r = torch.sqrt(torch.clamp(1.0 - z * z, min=0.0))
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    return torch.stack([r * torch.cos(phi), r * torch.sin(phi), z], dim=1).contiguous()
+
+
+def translation_search(scene: Scene, W36: torch.Tensor, params: torch.Tensor, cand: torch.Tensor,
+                       t_prior: torch.Tensor):
+    """(t [P,3] float32, best [P] int32, err_min [P] float64): the candidate
+    with the lowest mean squared epipolar error per pair, signed like t_prior."""
+    dev, P = scene.ctx.device, scene.num_pairs
+    _require(W36, torch.float64, (P, 36), "W36", dev)
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    C = int(cand.shape[0])
+    _require(cand, torch.float64, (C, 3), "cand", dev)
+    _require(t_prior, torch.float32, (P, 3), "t_prior", dev)
+    t = torch.empty((P, 3), dtype=torch.float32, device=dev)
+    best = torch.empty(P, dtype=torch.int32, device=dev)
+    err = torch.empty(P, dtype=torch.float64, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_translation_search(
+        scene.ctx.handle, scene.handle, _ptr(W36), _ptr(params), _ptr(cand), C, _ptr(t_prior), _ptr(t), _ptr(best),
+        _ptr(err), _stream()))
+    return t, best, err
+
+
 # ------------------------------------------------------------------ rotation averaging
 
 def rotation_loss_grad(scene: Scene, Rrel: torch.Tensor, params6: torch.Tensor, want_loss: bool = True,

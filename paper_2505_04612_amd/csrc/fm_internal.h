@@ -35,7 +35,7 @@ constexpr int kKeptSlots = 256;
 // Kernel identifiers of the optional launch timing (fm_profile_*).
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
        FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_RA_SOLVE = 9, FM_K_RA_PAIR = 10,
-       FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_COUNT = 13 };
+       FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_TS_SEARCH = 13, FM_K_COUNT = 14 };
 
 struct fm_timing {
   int kernel;
