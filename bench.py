@@ -27,6 +27,12 @@ Reported (one JSON line):
                   and a final 1,000-step loop; device time per iteration,
                   accuracy against the true centres, and the FP64 oracle's
                   iteration rate on a bounded sample;
+  translation_search
+                  the relative-translation grid search on the same scene
+                  (appendix on global translation): 4,096 candidates per
+                  pair against each pair's Gram; candidate evaluations per
+                  second against the FP64 vector peak, accuracy against the
+                  true directions, and the FP64 oracle's rate;
   rotation_averaging
                   the first pose stage on the same pair graph (Sec. 3.3,
                   Global Rotation): the column-wise least-squares
@@ -211,6 +217,71 @@ def bench_translation(ctx, s, sc, runs: int = 4, iters: int = 1000, final_iters:
     }
 
 
+FP64_PEAK_T = 78.6    # TFLOP/s, FP64 vector (MI355X)
+
+
+def bench_search(ctx, s, sc, C: int = 4096, reps: int = 20, cpu_pairs: int = 200) -> dict:
+    """Grid search of the unit relative translation of every pair over C
+    Fibonacci-lattice candidates, from the Grams of the matches an upstream
+    two-view estimate keeps (the generator's inliers: weight 1, outliers 0)
+    and the true rotations; the prior sign is the true direction's."""
+    import numpy as np
+    import torch
+
+    from paper_2505_04612_amd import _lib, api
+    dev = ctx.device
+    keep = torch.from_numpy((~sc.outlier).astype(np.float32)).to(dev)
+    W64, _ = api.build_pair_grams(s, keep, f32=False)
+    params = np.concatenate([sc.R_gt[:, :, 0], sc.R_gt[:, :, 1], sc.t_gt], 1).astype(np.float32)
+    o = -np.einsum("nba,nb->na", sc.R_gt, sc.t_gt)
+    i, j = sc.pairs[:, 0], sc.pairs[:, 1]
+    t_true = np.einsum("pab,pb->pa", sc.R_gt[j], o[i] - o[j])
+    t_true /= np.linalg.norm(t_true, axis=1, keepdims=True)
+    p_dev = torch.from_numpy(params).to(dev)
+    prior = torch.from_numpy(t_true.astype(np.float32)).to(dev)
+    cand = api.fibonacci_sphere(C, dev)
+    api.translation_search(s, W64, p_dev, cand, prior)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        t, best, err = api.translation_search(s, W64, p_dev, cand, prior)
+    ms, n = ctx.profile_read(_lib.K_TS_SEARCH)
+    ctx.profile(False)
+    per = ms / 1e3 / max(n, 1)
+    P = sc.num_pairs
+    evals = P * C / per
+    # 6 products of the monomials by the form, 5 additions, 6 monomial
+    # products: 17 FP64 flops per candidate and pair
+    flops = 17.0 * evals
+    ang = np.degrees(np.arccos(np.clip(np.sum(t.cpu().numpy().astype(np.float64) * t_true, axis=1), -1, 1)))
+    from oracle import grid_search as gs
+    W = W64[:cpu_pairs].cpu().numpy()
+    full = np.empty((cpu_pairs, 9, 9))
+    q = {(0, 0): 0, (0, 1): 1, (1, 0): 1, (1, 1): 2, (0, 2): 3, (2, 0): 3, (1, 2): 4, (2, 1): 4, (2, 2): 5}
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                for d in range(3):
+                    full[:, 3 * a + b, 3 * c + d] = W[:, 6 * q[(a, c)] + q[(b, d)]]
+    Rij = gs.relative_rotations(params.astype(np.float64), sc.pairs[:cpu_pairs])
+    cand_np = gs.fibonacci_sphere(C)
+    t0 = time.perf_counter()
+    gs.grid_search(full, np.diff(sc.offsets)[:cpu_pairs], Rij, cand_np, t_true[:cpu_pairs])
+    t_cpu = time.perf_counter() - t0
+    return {
+        "kernel": "k_ts_search (per-pair 3x3 form from the Gram, candidates in LDS, argmin over lane slices)",
+        "pairs": P, "candidates": C, "us_per_launch": per * 1e6, "evals_per_s": evals,
+        "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": FP64_PEAK_T, "unit": "TFLOP/s",
+                     "frac": flops / 1e12 / FP64_PEAK_T, "flops_per_eval": 17},
+        "angle_to_truth_deg": {"median": float(np.median(ang)), "p90": float(np.quantile(ang, 0.9)),
+                               "max": float(ang.max())},
+        "inputs": "Grams of the inlier matches (the outliers an upstream two-view estimate removes have weight 0), "
+                  "true rotations, true direction as sign prior",
+        "cpu_baseline": {"evals_per_s": cpu_pairs * C / t_cpu, "kind": "oracle",
+                         "sample": f"errors of all {C} candidates for {cpu_pairs} pairs ({t_cpu:.1f} s)"},
+    }
+
+
 def bench_rotation(ctx, s, sc, steps: int = 300, iters: int = 500, cpu_budget: float = 3.0) -> dict:
     """Global rotation averaging on the scene's pair graph: noisy relative
     rotations (2 deg, 10 % outlier pairs) from the true poses, the
@@ -294,6 +365,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-translation", action="store_true", help="skip the translation-averaging leg")
     ap.add_argument("--no-rotation", action="store_true", help="skip the rotation-averaging leg")
+    ap.add_argument("--no-search", action="store_true", help="skip the relative-translation grid-search leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
@@ -402,6 +474,9 @@ def main() -> int:
     if not args.no_rotation:
         log("[bench] rotation averaging on the same pair graph")
         out["rotation_averaging"] = bench_rotation(ctx, s, sc)
+    if not args.no_search:
+        log("[bench] relative-translation grid search on the same scene")
+        out["translation_search"] = bench_search(ctx, s, sc)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc, coords, theta0, sd, args.cpu_budget)

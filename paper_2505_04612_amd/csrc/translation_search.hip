@@ -17,6 +17,7 @@
 namespace {
 
 constexpr int kTsTile = 2048;   // candidates per LDS tile (48 KB of float64)
+constexpr int kTsBlock = 512;   // threads per workgroup (each stages every candidate once)
 
 // A = B^T W B from the compact Gram (W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)])
 // and R = R_ij, as its six distinct entries (A00, A11, A22, A01, A02, A12).
@@ -57,7 +58,7 @@ __device__ inline void pair_form(const double* __restrict__ w36, const double R[
   A6[5] = A[1][2] + A[2][1];
 }
 
-__global__ __launch_bounds__(kBlock) void k_ts_search(const double* __restrict__ W36, const float* __restrict__ params,
+__global__ __launch_bounds__(kTsBlock) void k_ts_search(const double* __restrict__ W36, const float* __restrict__ params,
                                                       const int32_t* __restrict__ cams,
                                                       const int64_t* __restrict__ offsets,
                                                       const double* __restrict__ cand, int32_t C,
@@ -146,13 +147,15 @@ extern "C" fm_status fm_translation_search(fm_ctx* ctx, fm_scene* s, const doubl
   if (!W36 || !params || !cand || !t_prior || !t_out)
     return fm_fail(ctx, FM_EINVAL, "fm_translation_search: NULL argument");
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  // lanes per pair: enough (pair, slice) lanes to give every SIMD a few
-  // wavefronts (256 CUs x 4 SIMDs x 4 wavefronts x 64 lanes), at most 64
+  // lanes per pair: enough (pair, slice) lanes for about two wavefronts per
+  // SIMD (256 CUs x 4 SIMDs x 2 x 64 lanes), at most 64 (measured on the
+  // medium graph, 4,096 candidates: 36.5 us; four wavefronts per SIMD with
+  // 256-thread workgroups 39.7 us, one with 1,024-thread workgroups 56.6 us)
   int S = 1;
-  while (S < 64 && s->P * S < (int64_t)256 * 4 * 4 * 64 && S < C) S <<= 1;
+  while (S < 64 && s->P * S < (int64_t)256 * 4 * 2 * 64 && S < C) S <<= 1;
   const int64_t lanes = s->P * S;
   fm_timed timer(ctx, FM_K_TS_SEARCH, (hipStream_t)stream);
-  hipLaunchKernelGGL(k_ts_search, dim3(grid_for(lanes, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, W36, params,
+  hipLaunchKernelGGL(k_ts_search, dim3(grid_for(lanes, kTsBlock)), dim3(kTsBlock), 0, (hipStream_t)stream, W36, params,
                      s->pair_cams, s->offsets, cand, C, t_prior, s->P, S, t_out, best, err_min);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
