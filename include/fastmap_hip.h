@@ -194,6 +194,28 @@ fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dt
  * the cooperative launch makes every workgroup resident. */
 fm_status fm_solve_barrier_failures(fm_ctx* ctx, fm_scene* scene, int64_t* failures);
 
+/* ------------------------------------------------------------------ focal refinement */
+
+/* Focal lengths refined inside epipolar adjustment (Sec. 3.3, the remark
+ * after the IRLS paragraph: the focal lengths are built into the essential
+ * matrices, which then are fundamental matrices).  The stored coordinates
+ * are normalised by a focal estimate per camera; phi [N] float32 is the log
+ * of each camera's refined focal over that estimate, S_i = diag(e^-phi_i,
+ * e^-phi_i, 1), and F_n = S_j E_n S_i acts on the stored coordinates.  Each
+ * pair's term is normalised by |F_n|_F^2 (without it, growing the scales
+ * shrinks F toward a trivial zero of the algebraic loss; with unit relative
+ * translation |E_n|_F^2 = 2, so at phi = 0 the loss is half the epipolar
+ * one):
+ *     L = inv_Z * sum_n f_n^T W_n f_n / f_n^T f_n,  f_n = flatten(F_n).
+ * W36, wdtype, params, inv_Z, Z_dev as for fm_epipolar_loss_grad;
+ *   loss [1] double, grad [N,9] float32 (dL/dparams), gphi [N] float32
+ *   (dL/dphi); each NULL = not written.  A pair with |t_ij| = 0 adds
+ *   nothing.  Float64 pair arithmetic, float32 records, fixed-order sums. */
+fm_status fm_epipolar_focal_loss_grad(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dtype wdtype,
+                                      const float* params, const float* phi, double inv_Z,
+                                      const int64_t* Z_dev, double* loss, float* grad, float* gphi,
+                                      fm_stream stream);
+
 /* ------------------------------------------------------------------ translation averaging */
 
 /* Global translation averaging, the stage before epipolar adjustment
@@ -382,7 +404,8 @@ fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_m
  *   two kernels of fm_translation_loss_grad), FM_K_RA_SOLVE 9 (persistent
  *   rotation loop), FM_K_RA_PAIR 10 and FM_K_RA_CAMERA 11 (the two kernels of
  *   fm_rotation_loss_grad), FM_K_RA_INIT 12 (rotation initialisation),
- *   FM_K_TS_SEARCH 13 (relative-translation grid search).
+ *   FM_K_TS_SEARCH 13 (relative-translation grid search), FM_K_FO_PAIR 14 and
+ *   FM_K_FO_CAMERA 15 (the two kernels of fm_epipolar_focal_loss_grad).
  * fm_profile_enable synchronises the device and clears earlier records;
  * fm_profile_read waits for the recorded events and returns the summed
  * elapsed milliseconds and the launch count of one kernel (host outputs). */

@@ -281,6 +281,29 @@ def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: tor
         ctypes.byref(cfg), float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss_trace), _stream()))
 
 
+# ------------------------------------------------------------------ focal refinement
+
+def epipolar_focal_loss_grad(scene: Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.Tensor,
+                             inv_Z: float | None = None, Z: torch.Tensor | None = None):
+    """(loss [1] float64, grad [N,9] float32, gphi [N] float32) of the epipolar
+    loss with per-camera log focal scales phi (fundamental matrices)."""
+    dev = scene.ctx.device
+    _require(W36, W36.dtype, (scene.num_pairs, 36), "W36", dev)
+    _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
+    _require(phi, torch.float32, (scene.num_cams,), "phi", dev)
+    if Z is not None:
+        _require(Z, torch.int64, (1,), "Z", dev)
+    elif inv_Z is None:
+        raise ValueError("give inv_Z or Z")
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty((scene.num_cams, 9), dtype=torch.float32, device=dev)
+    gphi = torch.empty(scene.num_cams, dtype=torch.float32, device=dev)
+    check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_focal_loss_grad(
+        scene.ctx.handle, scene.handle, _ptr(W36), _wdtype(W36), _ptr(params), _ptr(phi),
+        float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss), _ptr(grad), _ptr(gphi), _stream()))
+    return loss, grad, gphi
+
+
 # ------------------------------------------------------------------ translation averaging
 
 def _runs_of(scene: Scene, centres: torch.Tensor) -> int:

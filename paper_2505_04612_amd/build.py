@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastmap_hip.so")
-SOURCES = ["scene.hip", "gram.hip", "iterate.hip", "mlp.hip", "translation.hip", "rotation.hip", "translation_search.hip"]
+SOURCES = ["scene.hip", "gram.hip", "iterate.hip", "mlp.hip", "translation.hip", "rotation.hip", "translation_search.hip", "focal.hip"]
 ARCH = "gfx950"
 
 
@@ -48,7 +48,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
         return obj
 
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

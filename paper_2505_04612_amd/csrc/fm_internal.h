@@ -35,7 +35,8 @@ constexpr int kKeptSlots = 256;
 // Kernel identifiers of the optional launch timing (fm_profile_*).
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
        FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_RA_SOLVE = 9, FM_K_RA_PAIR = 10,
-       FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_TS_SEARCH = 13, FM_K_COUNT = 14 };
+       FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_TS_SEARCH = 13, FM_K_FO_PAIR = 14, FM_K_FO_CAMERA = 15,
+       FM_K_COUNT = 16 };
 
 struct fm_timing {
   int kernel;
@@ -99,6 +100,7 @@ struct fm_scene {
   float* partials = nullptr;      // [n_big, 36]
   double* ess = nullptr;          // [P, 9] essential matrices (reweight)
   float* contrib = nullptr;       // [P, 24] per-pair gradient records
+  float* fo_rec = nullptr;        // [P, 2] per-pair focal-scale gradient records (side i, side j)
   double* loss_part = nullptr;    // [loss_part_cap]
   double* rot = nullptr;          // [N, 9] rotations of the current poses (fused solve)
   int64_t loss_part_cap = 0;
@@ -206,6 +208,47 @@ __device__ inline double pair_essential(const double Ri[3][3], const double ti[3
     for (int b = 0; b < 3; ++b)
       E[a][b] = T[a][0] * Rij[0][b] + T[a][1] * Rij[1][b] + T[a][2] * Rij[2][b];
   return ns;
+}
+
+// Adjoint of E = [th]_x R_ij (th = s/|s|, s = t_j - R_ij t_i, R_ij = R_j R_i^T)
+// from G = dL/dE to the pair's record [dL/dR_i (3x3 row-major), dL/dt_i,
+// dL/dR_j, dL/dt_j] (float32); ns = |s| > 0.
+__device__ inline void essential_adjoint(const double G[3][3], const double th[3], double ns, const double Rij[3][3],
+                                         const double Ri[3][3], const double Rj[3][3], const double ti[3],
+                                         float* __restrict__ rec) {
+  const double T[3][3] = {{0.0, -th[2], th[1]}, {th[2], 0.0, -th[0]}, {-th[1], th[0], 0.0}};
+  double A[3][3], dRij[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      A[a][b] = G[a][0] * Rij[b][0] + G[a][1] * Rij[b][1] + G[a][2] * Rij[b][2];
+      dRij[a][b] = T[0][a] * G[0][b] + T[1][a] * G[1][b] + T[2][a] * G[2][b];
+    }
+  // through T = [th]_x, th = s/|s|, s = t_j - R_ij t_i
+  double gth[3] = {A[2][1] - A[1][2], A[0][2] - A[2][0], A[1][0] - A[0][1]};
+  const double dp = th[0] * gth[0] + th[1] * gth[1] + th[2] * gth[2];
+  const double rns = 1.0 / ns;
+  double gs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gs[k] = (gth[k] - dp * th[k]) * rns;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) dRij[a][b] -= gs[a] * ti[b];
+  // R_ij = R_j R_i^T: dR_j = dRij R_i, dR_i = dRij^T R_j
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      rec[12 + 3 * a + b] = (float)(dRij[a][0] * Ri[0][b] + dRij[a][1] * Ri[1][b] + dRij[a][2] * Ri[2][b]);
+      rec[3 * a + b] = (float)(dRij[0][a] * Rj[0][b] + dRij[1][a] * Rj[1][b] + dRij[2][a] * Rj[2][b]);
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    rec[21 + a] = (float)gs[a];
+    rec[9 + a] = (float)(-(Rij[0][a] * gs[0] + Rij[1][a] * gs[1] + Rij[2][a] * gs[2]));
+  }
 }
 
 // Symmetric monomial index q(a, c) of x~[a] x~[c] in p = (u^2, uv, v^2, u, v, 1).

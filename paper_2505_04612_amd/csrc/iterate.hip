@@ -85,39 +85,7 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) G[a][b] = two_inv_Z * g[a][b];
-  const double T[3][3] = {{0.0, -th[2], th[1]}, {th[2], 0.0, -th[0]}, {-th[1], th[0], 0.0}};
-  double A[3][3], dRij[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      A[a][b] = G[a][0] * Rij[b][0] + G[a][1] * Rij[b][1] + G[a][2] * Rij[b][2];
-      dRij[a][b] = T[0][a] * G[0][b] + T[1][a] * G[1][b] + T[2][a] * G[2][b];
-    }
-  // through T = [th]_x, th = s/|s|, s = t_j - R_ij t_i
-  double gth[3] = {A[2][1] - A[1][2], A[0][2] - A[2][0], A[1][0] - A[0][1]};
-  const double dp = th[0] * gth[0] + th[1] * gth[1] + th[2] * gth[2];
-  const double rns = 1.0 / ns;
-  double gs[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) gs[k] = (gth[k] - dp * th[k]) * rns;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) dRij[a][b] -= gs[a] * ti[b];
-  // R_ij = R_j R_i^T: dR_j = dRij R_i, dR_i = dRij^T R_j
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      rec[12 + 3 * a + b] = (float)(dRij[a][0] * Ri[0][b] + dRij[a][1] * Ri[1][b] + dRij[a][2] * Ri[2][b]);
-      rec[3 * a + b] = (float)(dRij[0][a] * Rj[0][b] + dRij[1][a] * Rj[1][b] + dRij[2][a] * Rj[2][b]);
-    }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    rec[21 + a] = (float)gs[a];
-    rec[9 + a] = (float)(-(Rij[0][a] * gs[0] + Rij[1][a] * gs[1] + Rij[2][a] * gs[2]));
-  }
+  essential_adjoint(G, th, ns, Rij, Ri, Rj, ti, rec);
   return loss;
 }
 

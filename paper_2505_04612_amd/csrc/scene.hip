@@ -240,6 +240,7 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->partials);
   (void)hipFree(s->ess);
   (void)hipFree(s->contrib);
+  (void)hipFree(s->fo_rec);
   (void)hipFree(s->loss_part);
   (void)hipFree(s->rot);
   (void)hipFree(s->bar);
@@ -400,6 +401,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_partials > 0 ? s->n_partials : 1)));
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
+  SCENE_TRY(hipMalloc(&s->fo_rec, sizeof(float) * 2 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
   SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * (N > 0 ? N : 1)));
   SCENE_TRY(hipMalloc(&s->bar, sizeof(unsigned) * 128));

@@ -1,0 +1,97 @@
+"""Focal refinement inside epipolar adjustment on the GPU (Sec. 3.3: focal
+lengths in the essential matrices) against the FP64 oracle on the same
+Grams, and against the library's own epipolar loss at unit scales."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import focal as fo
+from paper_2505_04612_amd import synth
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx():
+    from paper_2505_04612_amd import api
+    return api.default_context()
+
+
+def _dev(ctx, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(ctx.device)
+
+
+def _setup(name, kappa=1.0, weights=None):
+    from paper_2505_04612_amd import api
+    ctx = _ctx()
+    sc = helpers.scene(name)
+    dt = torch.float64 if name == "tiny" else torch.float32
+    s = api.Scene.from_numpy(ctx, sc.num_cams, sc.pairs, sc.offsets, sc.uv * kappa, dt)
+    W64, W32 = api.build_pair_grams(s, weights)
+    theta = np.concatenate([sc.R_init[:, :, 0], sc.R_init[:, :, 1], sc.t_init], 1).astype(np.float32)
+    return ctx, sc, s, W64, W32, theta
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_unit_scales_give_half_the_epipolar_loss_and_gradient(name):
+    from paper_2505_04612_amd import api
+    ctx, sc, s, W64, W32, theta = _setup(name)
+    p = _dev(ctx, theta)
+    phi = torch.zeros(sc.num_cams, dtype=torch.float32, device=ctx.device)
+    iz = 1.0 / sc.num_matches
+    L, g, gp = api.epipolar_focal_loss_grad(s, W64, p, phi, iz)
+    Le, ge = api.epipolar_loss_grad(s, W64, p, iz)
+    assert abs(L.item() - Le.item() / 2) <= 1e-9 * Le.item()
+    ge = ge.cpu().numpy()
+    np.testing.assert_allclose(g.cpu().numpy(), ge / 2, rtol=1e-4, atol=1e-5 * np.abs(ge).max())
+
+
+@pytest.mark.parametrize("name,wdt", [("tiny", "f64"), ("medium", "f64"), ("medium", "f32")])
+def test_parity_with_the_oracle(name, wdt):
+    from paper_2505_04612_amd import api
+    ctx, sc, s, W64, W32, theta = _setup(name)
+    W = W64 if wdt == "f64" else W32
+    phi = (0.05 * np.random.default_rng(4).normal(size=sc.num_cams)).astype(np.float32)
+    iz = 1.0 / sc.num_matches
+    L, g, gp = api.epipolar_focal_loss_grad(s, W, _dev(ctx, theta), _dev(ctx, phi), iz)
+    Wf = helpers.expand36(W.to(torch.float64).cpu().numpy())
+    wL, wg, wgp = fo.loss_grad(theta.astype(np.float64), phi.astype(np.float64), sc.pairs, Wf, iz)
+    assert abs(L.item() - wL) <= 1e-9 * wL
+    # float32 records summed in float64, float64 Gram-Schmidt adjoint
+    np.testing.assert_allclose(g.cpu().numpy(), wg, rtol=1e-4, atol=1e-5 * np.abs(wg).max())
+    np.testing.assert_allclose(gp.cpu().numpy(), wgp, rtol=1e-4, atol=1e-5 * np.abs(wgp).max())
+
+
+def test_recovers_a_ten_percent_focal_error_with_poses_held():
+    from paper_2505_04612_amd import focal
+    ctx = _ctx()
+    clean = synth.noise_free(synth.tiny)
+    from paper_2505_04612_amd import api
+    kappa = 1.1
+    s = api.Scene.from_numpy(ctx, clean.num_cams, clean.pairs, clean.offsets, clean.uv * kappa, torch.float64)
+    W64, _ = api.build_pair_grams(s, f32=False)
+    theta = np.concatenate([clean.R_gt[:, :, 0], clean.R_gt[:, :, 1], clean.t_gt], 1).astype(np.float32)
+    p = _dev(ctx, theta)
+    phi = torch.zeros(clean.num_cams, dtype=torch.float32, device=ctx.device)
+    tr = focal.solve(s, W64, p, phi, 1.0 / clean.num_matches,
+                     focal.FocalSchedule(iters=400, lr_rot=0.0, lr_t=0.0, lr_phi=1e-2), trace=True)
+    # float32 gradients leave Adam jittering at the last rate (1e-4): the
+    # scales land within it, the loss five orders below its start
+    np.testing.assert_allclose(phi.cpu().numpy(), np.log(kappa), atol=1e-4)
+    assert tr[-1] < 1e-5 * tr[0]
+    # the oracle's steps from the same start land in the same place
+    _, wphi, _ = fo.solve(theta.astype(np.float64), np.zeros(clean.num_cams), clean.pairs,
+                          helpers.expand36(W64.cpu().numpy()), 1.0 / clean.num_matches, 400, lr_rot=0.0, lr_t=0.0,
+                          lr_phi=1e-2)
+    np.testing.assert_allclose(phi.cpu().numpy(), wphi, atol=1e-4)
+
+
+def test_empty_graph():
+    from paper_2505_04612_amd import api
+    ctx = _ctx()
+    s = api.Scene.from_numpy(ctx, 3, np.zeros((0, 2), np.int32), np.zeros(1, np.int64), np.zeros((0, 4)),
+                             torch.float32)
+    W = torch.zeros((0, 36), dtype=torch.float64, device=ctx.device)
+    p = _dev(ctx, np.tile(np.array([1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32), (3, 1)))
+    L, g, gp = api.epipolar_focal_loss_grad(s, W, p, torch.zeros(3, dtype=torch.float32, device=ctx.device), 1.0)
+    assert L.item() == 0.0 and np.all(g.cpu().numpy() == 0) and np.all(gp.cpu().numpy() == 0)
