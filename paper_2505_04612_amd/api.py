@@ -284,9 +284,9 @@ def epipolar_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, m: tor
 # ------------------------------------------------------------------ focal refinement
 
 def epipolar_focal_loss_grad(scene: Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.Tensor,
-                             inv_Z: float | None = None, Z: torch.Tensor | None = None):
-    """(loss [1] float64, grad [N,9] float32, gphi [N] float32) of the epipolar
-    loss with per-camera log focal scales phi (fundamental matrices)."""
+                             inv_Z: float | None = None, Z: torch.Tensor | None = None, want_loss: bool = True):
+    """(loss [1] float64 | None, grad [N,9] float32, gphi [N] float32) of the
+    epipolar loss with per-camera log focal scales phi (fundamental matrices)."""
     dev = scene.ctx.device
     _require(W36, W36.dtype, (scene.num_pairs, 36), "W36", dev)
     _require(params, torch.float32, (scene.num_cams, 9), "params", dev)
@@ -295,7 +295,7 @@ def epipolar_focal_loss_grad(scene: Scene, W36: torch.Tensor, params: torch.Tens
         _require(Z, torch.int64, (1,), "Z", dev)
     elif inv_Z is None:
         raise ValueError("give inv_Z or Z")
-    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev) if want_loss else None
     grad = torch.empty((scene.num_cams, 9), dtype=torch.float32, device=dev)
     gphi = torch.empty(scene.num_cams, dtype=torch.float32, device=dev)
     check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_focal_loss_grad(

@@ -44,7 +44,7 @@ def solve(scene: api.Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.
         f = sched.lr_final_frac ** (k / sched.iters)
         lr_p.copy_(torch.from_numpy(lr0 * np.float32(f)))
         lr_f.fill_(float(sched.lr_phi * f))
-        loss, g, gp = api.epipolar_focal_loss_grad(scene, W36, params, phi, inv_Z)
+        loss, g, gp = api.epipolar_focal_loss_grad(scene, W36, params, phi, inv_Z, want_loss=trace)
         if trace:
             out.append(loss)
         api.adam_step(ctx, params.view(-1), g.view(-1), mp.view(-1), vp.view(-1), k + 1, lr_p, sched.beta1,
