@@ -294,6 +294,13 @@ fm_status fm_translation_search(fm_ctx* ctx, fm_scene* scene, const double* W36,
                                 const double* cand, int32_t C, const float* t_prior, float* t_out,
                                 int32_t* best, double* err_min, fm_stream stream);
 
+/* Epipolar parameters from the averaging stages' results: params9 [N,9]
+ * float32 = (a1, a2, t = -R o) per camera, with (a1, a2) = params6 [N,6]
+ * (rotation averaging's parameters) and o = centres [N,3] (translation
+ * averaging's camera centres); R by Gram-Schmidt in float64. */
+fm_status fm_poses_from_centres(fm_ctx* ctx, int32_t N, const float* params6, const float* centres,
+                                float* params9, fm_stream stream);
+
 /* ------------------------------------------------------------------ rotation averaging */
 
 /* Global rotation averaging, the first pose stage (Sec. 3.3 "Global

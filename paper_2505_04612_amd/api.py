@@ -401,6 +401,18 @@ def translation_search(scene: Scene, W36: torch.Tensor, params: torch.Tensor, ca
     return t, best, err
 
 
+def poses_from_centres(ctx: Context, params6: torch.Tensor, centres: torch.Tensor) -> torch.Tensor:
+    """(a1, a2, t = -R o) [N,9] float32 from rotation parameters [N,6] and
+    camera centres [N,3]."""
+    N = int(params6.shape[0])
+    _require(params6, torch.float32, (N, 6), "params6", ctx.device)
+    _require(centres, torch.float32, (N, 3), "centres", ctx.device)
+    out = torch.empty((N, 9), dtype=torch.float32, device=ctx.device)
+    check(ctx.handle, ctx.lib.fm_poses_from_centres(ctx.handle, N, _ptr(params6), _ptr(centres), _ptr(out),
+                                                    _stream()))
+    return out
+
+
 # ------------------------------------------------------------------ rotation averaging
 
 def rotation_loss_grad(scene: Scene, Rrel: torch.Tensor, params6: torch.Tensor, want_loss: bool = True,

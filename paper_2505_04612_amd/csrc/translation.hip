@@ -415,6 +415,29 @@ __global__ __launch_bounds__(kBlock) void k_ta_merge(const float* __restrict__ c
   if (choice && l16 == 0) choice[c] = best;
 }
 
+// ------------------------------------------------------------------ poses from centres
+
+// (a1, a2, t = -R o) per camera: the epipolar parameters of rotations given
+// as 6D parameters and camera centres o (R by Gram-Schmidt, float64).
+__global__ __launch_bounds__(kBlock) void k_poses_from_centres(const float* __restrict__ p6,
+                                                               const float* __restrict__ centres, int32_t N,
+                                                               float* __restrict__ p9) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  double a1[3], a2[3], R[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a1[k] = (double)p6[6 * c + k];
+    a2[k] = (double)p6[6 * c + 3 + k];
+  }
+  gs_matrix(gs_forward(a1, a2), R);
+  const double o[3] = {(double)centres[3 * c], (double)centres[3 * c + 1], (double)centres[3 * c + 2]};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p9[9 * c + k] = p6[6 * c + k];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p9[9 * c + 6 + a] = (float)(-(R[a][0] * o[0] + R[a][1] * o[1] + R[a][2] * o[2]));
+}
+
 // ------------------------------------------------------------------ host side
 
 fm_status ta_check(fm_ctx* ctx, fm_scene* s, const char* fn) {
@@ -581,6 +604,19 @@ extern "C" fm_status fm_translation_merge(fm_ctx* ctx, fm_scene* s, const float*
   hipLaunchKernelGGL(k_ta_merge, dim3(grid_for((int64_t)s->N * 16, kBlock)), dim3(kBlock), 0, st, centres,
                      s->pair_cams, dirs, s->cam_ptr, s->cam_items, s->ta_stats, s->N, (int)runs, cam_loss, choice,
                      merged);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
+}
+
+extern "C" fm_status fm_poses_from_centres(fm_ctx* ctx, int32_t N, const float* params6, const float* centres,
+                                           float* params9, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  if (N < 0) return fm_fail(ctx, FM_ESHAPE, "fm_poses_from_centres: N < 0");
+  if (N == 0) return FM_OK;
+  if (!params6 || !centres || !params9) return fm_fail(ctx, FM_EINVAL, "fm_poses_from_centres: NULL argument");
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_poses_from_centres, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, params6,
+                     centres, N, params9);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
 }
