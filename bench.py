@@ -38,6 +38,11 @@ Reported (one JSON line):
                   same scene with coordinates normalised by a focal 5 % off:
                   device time of one loss + gradient evaluation and the
                   recovered focal scales after 300 Adam steps;
+  pose_pipeline   the stages in sequence on the same scene (rotation
+                  averaging, grid search, translation averaging, then the
+                  epipolar solve from their poses): wall time and accuracy
+                  against the true poses after the averaging stages and
+                  after epipolar adjustment;
   rotation_averaging
                   the first pose stage on the same pair graph (Sec. 3.3,
                   Global Rotation): the column-wise least-squares
@@ -223,6 +228,41 @@ def bench_translation(ctx, s, sc, runs: int = 4, iters: int = 1000, final_iters:
 
 
 FP64_PEAK_T = 78.6    # TFLOP/s, FP64 vector (MI355X)
+
+
+def bench_pipeline(ctx, s, sc) -> dict:
+    """The pose stages in sequence from noisy relative rotations (2 deg, 10 %
+    outlier pairs), the scene's inlier matches and the true directions as
+    translation sign priors."""
+    import numpy as np
+    import torch
+
+    from oracle import ea
+    from paper_2505_04612_amd import pipeline, synth
+    dev = ctx.device
+    rin = synth.rotation_inputs(sc)
+    Q = torch.from_numpy(rin.R_rel.reshape(-1, 9).astype(np.float32)).to(dev)
+    o = -np.einsum("nba,nb->na", sc.R_gt, sc.t_gt)
+    i, j = sc.pairs[:, 0], sc.pairs[:, 1]
+    prior = np.einsum("pab,pb->pa", sc.R_gt[j], o[i] - o[j])
+    prior = torch.from_numpy((prior / np.linalg.norm(prior, axis=1, keepdims=True)).astype(np.float32)).to(dev)
+    keep = torch.from_numpy((~sc.outlier).astype(np.float32)).to(dev)
+    pipeline.run(s, Q, prior, keep)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, stages = pipeline.run(s, Q, prior, keep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gt = np.concatenate([sc.R_gt[:, :, 0], sc.R_gt[:, :, 1], sc.t_gt], 1)
+    out = {"wall_ms": wall * 1e3, "barrier_failures": s.barrier_failures()}
+    for name, th in (("after_averaging", stages["averaged"]), ("after_epipolar_adjustment", params)):
+        rot, tra = ea.relative_pose_errors(th.cpu().numpy().astype(np.float64), gt, sc.pairs)
+        out[name] = {"rot_median_deg": float(np.median(rot)), "rot_p90_deg": float(np.quantile(rot, 0.9)),
+                     "rot_max_deg": float(rot.max()), "t_median_deg": float(np.median(tra)),
+                     "t_p90_deg": float(np.quantile(tra, 0.9)), "t_max_deg": float(tra.max())}
+    out["inputs"] = ("relative rotations from the true poses with 2 deg noise and 10 % outlier pairs; Grams of "
+                     "the inlier matches; true directions as the sign priors of the grid search")
+    return out
 
 
 def bench_focal(ctx, sc, kappa: float = 1.05, iters: int = 300, reps: int = 50) -> dict:
@@ -426,6 +466,7 @@ def main() -> int:
     ap.add_argument("--no-rotation", action="store_true", help="skip the rotation-averaging leg")
     ap.add_argument("--no-search", action="store_true", help="skip the relative-translation grid-search leg")
     ap.add_argument("--no-focal", action="store_true", help="skip the focal-refinement leg")
+    ap.add_argument("--no-pipeline", action="store_true", help="skip the pose-pipeline leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
@@ -540,6 +581,9 @@ def main() -> int:
     if not args.no_focal:
         log("[bench] focal refinement on the same scene")
         out["focal_refinement"] = bench_focal(ctx, sc)
+    if not args.no_pipeline:
+        log("[bench] the pose stages in sequence")
+        out["pose_pipeline"] = bench_pipeline(ctx, s, sc)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc, coords, theta0, sd, args.cpu_budget)
