@@ -16,7 +16,7 @@
 
 namespace {
 
-constexpr int kTsTile = 2048;   // candidates per LDS tile (48 KB of float64)
+constexpr int kTsTile = 1024;   // candidates per LDS tile: six monomials each (48 KB of float64)
 constexpr int kTsBlock = 512;   // threads per workgroup (each stages every candidate once)
 
 // A = B^T W B from the compact Gram (W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)])
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kTsBlock) void k_ts_search(const double* __restrict
                                                       const float* __restrict__ t_prior, int64_t P, int S,
                                                       float* __restrict__ t_out, int32_t* __restrict__ best_out,
                                                       double* __restrict__ err_out) {
-  __shared__ double tile[kTsTile * 3];
+  __shared__ double tile[kTsTile * 6];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = gtid / S;
   const int slice = (int)(gtid % S);
@@ -90,13 +90,23 @@ __global__ __launch_bounds__(kTsBlock) void k_ts_search(const double* __restrict
   for (int base = 0; base < C; base += kTsTile) {
     const int len = C - base < kTsTile ? C - base : kTsTile;
     __syncthreads();
-    for (int k = threadIdx.x; k < 3 * len; k += blockDim.x) tile[k] = cand[3 * (int64_t)base + k];
+    // each candidate's monomials (x^2, y^2, z^2, xy, xz, yz), once per tile
+    for (int k = threadIdx.x; k < len; k += blockDim.x) {
+      const double x = cand[3 * (int64_t)(base + k)], y = cand[3 * (int64_t)(base + k) + 1],
+                   z = cand[3 * (int64_t)(base + k) + 2];
+      double* m = tile + 6 * k;
+      m[0] = x * x;
+      m[1] = y * y;
+      m[2] = z * z;
+      m[3] = x * y;
+      m[4] = x * z;
+      m[5] = y * z;
+    }
     __syncthreads();
     if (live) {
       for (int c = slice; c < len; c += S) {
-        const double x = tile[3 * c], y = tile[3 * c + 1], z = tile[3 * c + 2];
-        const double q = A6[0] * x * x + A6[1] * y * y + A6[2] * z * z + A6[3] * x * y + A6[4] * x * z +
-                         A6[5] * y * z;
+        const double* m = tile + 6 * c;
+        const double q = A6[0] * m[0] + A6[1] * m[1] + A6[2] * m[2] + A6[3] * m[3] + A6[4] * m[4] + A6[5] * m[5];
         if (q < best_v) {
           best_v = q;
           best_i = base + c;
