@@ -1,8 +1,13 @@
 /*
  * fastmap_hip.h - C ABI of the MI355X (gfx950) epipolar-adjustment library.
  *
- * The operations follow FastMap (arXiv 2505.04612), Sec. 3.3 "Epipolar
- * Adjustment" and App. B.6:
+ * Besides epipolar adjustment it holds the pose stages that feed it (further
+ * below): global rotation averaging and its initialisation, the
+ * relative-translation grid search, global translation averaging, and
+ * focal-length refinement inside epipolar adjustment.
+ *
+ * The epipolar operations follow FastMap (arXiv 2505.04612), Sec. 3.3
+ * "Epipolar Adjustment" and App. B.6:
  *
  *   pairs      P = {(i_n, j_n)}, i_n is the first image of pair n, j_n the second;
  *   matches    Q_n = {(x1_nm, x2_nm)}, normalised coordinates, homogeneous
