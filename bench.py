@@ -343,9 +343,10 @@ def bench_search(ctx, s, sc, C: int = 4096, reps: int = 20, cpu_pairs: int = 200
     per = ms / 1e3 / max(n, 1)
     P = sc.num_pairs
     evals = P * C / per
-    # 6 products of the monomials by the form, 5 additions, 6 monomial
-    # products: 17 FP64 flops per candidate and pair
-    flops = 17.0 * evals
+    # per candidate and pair: 6 products of the form's entries by the
+    # candidate's monomials and 5 additions (the monomials are per candidate,
+    # shared by all pairs): 11 FP64 flops
+    flops = 11.0 * evals
     ang = np.degrees(np.arccos(np.clip(np.sum(t.cpu().numpy().astype(np.float64) * t_true, axis=1), -1, 1)))
     from oracle import grid_search as gs
     W = W64[:cpu_pairs].cpu().numpy()
@@ -365,7 +366,7 @@ def bench_search(ctx, s, sc, C: int = 4096, reps: int = 20, cpu_pairs: int = 200
         "kernel": "k_ts_search (per-pair 3x3 form from the Gram, candidates in LDS, argmin over lane slices)",
         "pairs": P, "candidates": C, "us_per_launch": per * 1e6, "evals_per_s": evals,
         "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": FP64_PEAK_T, "unit": "TFLOP/s",
-                     "frac": flops / 1e12 / FP64_PEAK_T, "flops_per_eval": 17},
+                     "frac": flops / 1e12 / FP64_PEAK_T, "flops_per_eval": 11},
         "angle_to_truth_deg": {"median": float(np.median(ang)), "p90": float(np.quantile(ang, 0.9)),
                                "max": float(ang.max())},
         "inputs": "Grams of the inlier matches (the outliers an upstream two-view estimate removes have weight 0), "
