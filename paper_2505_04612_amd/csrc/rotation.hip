@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
           a.beta[k] = b;
         }
         // an invariant subspace, the last step, or a converged Ritz pair
-        // (checked every kLzCheck steps by one thread; the verdict is read
+        // (checked every kLzCheck steps by one thread; the decision is read
         // by all after a barrier)
         if (!(b > 1e-12 * fmax(1.0, fabs(alpha_k))) || k + 1 == a.m) {
           stop = true;
@@ -722,7 +722,7 @@ extern "C" fm_status fm_rotation_init(fm_ctx* ctx, fm_scene* s, const float* Rre
   if (want > s->lz_coop_blocks) want = s->lz_coop_blocks;
   const int64_t waves = want * (kSolveBlock / 64);
   // layout: V [(m+1) n] | w [n] | out [n] | c1 [n] | y [n] | h [m+2] | part [waves] | alpha [m] | beta [m] |
-  //         s [4m] | info [4]  (h [m+2]: the last slot carries the convergence verdict)
+  //         s [4m] | info [4]  (h [m+2]: the last slot carries the convergence decision)
   const int64_t need = (int64_t)(m + 1) * n + 4 * n + (m + 2) + waves + 2 * (int64_t)m + 4 * (int64_t)m + 4;
   if (need > s->lz_cap) {
     FM_HIP_TRY(ctx, hipDeviceSynchronize());
