@@ -177,13 +177,17 @@ typedef struct {
   int64_t adam_step0;    /* Adam steps already taken on m, v (0 after a reset) */
   int32_t blocks;        /* workgroups (512 threads each) of the persistent
                             kernel (0 = automatic; capped at the co-resident
-                            limit)                                            */
+                            limit; > 0 also forces the pair-by-pair loop)     */
 } fm_adam_cfg;
 
 /* K iterations of {loss + gradient (as fm_epipolar_loss_grad), Adam update of
- * params} in ONE persistent cooperative kernel; the iteration's two phases
- * (per pair, per camera) are separated by grid-wide barriers, so no host
- * round trip happens between iterations.  params, m, v [N,9] float32 are
+ * params} in ONE persistent cooperative kernel, with no host round trip
+ * between iterations.  Two loops, same results up to the order of the float64
+ * sums: pair by pair (a per-pair phase writes the records, a per-camera phase
+ * sums them and steps Adam, grid-wide barriers between the two), or, for
+ * graphs below 131,072 pairs when cfg->blocks is 0, camera by camera (one
+ * wavefront per camera evaluates each of its pairs, so every pair is
+ * evaluated from both ends, and one grid barrier per iteration).  params, m, v [N,9] float32 are
  * updated in place.  loss_trace [K] double receives L before each update
  * (NULL = not written).  `cfg` is a host pointer. */
 fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dtype wdtype,
@@ -255,13 +259,15 @@ fm_status fm_translation_loss_grad(fm_ctx* ctx, fm_scene* scene, const float* di
                                    const float* centres, double* loss, float* grad, fm_stream stream);
 
 /* K iterations of {gradient as fm_translation_loss_grad, Adam update of the
- * centres} for every run, in ONE persistent cooperative kernel (grid
- * barriers between the per-pair and per-camera phases, as fm_epipolar_solve).
- * centres, m, v [runs,N,3] float32 are updated in place.  `cfg` (host) as for
+ * centres} for every run, in ONE persistent cooperative kernel, by the same
+ * two loops as fm_epipolar_solve (camera by camera when cfg->blocks is 0 and
+ * the graph has fewer than 131,072 pairs, else pair by pair).  centres, m, v
+ * [runs,N,3] float32 are updated in place.  `cfg` (host) as for
  * fm_epipolar_solve, with lr_t the centres' initial rate (lr_rot unused).
  * loss_trace [runs,K] double receives L_t of each run before each update
  * (NULL = not written; tracing adds a workgroup reduction per run and
- * iteration).  The centres do not depend on cfg->blocks. */
+ * iteration).  Within the pair loop the centres do not depend on a forced
+ * cfg->blocks; the two loops agree up to the order of their float64 sums. */
 fm_status fm_translation_solve(fm_ctx* ctx, fm_scene* scene, const float* dirs, int32_t runs,
                                float* centres, float* m, float* v, int32_t K, const fm_adam_cfg* cfg,
                                double* loss_trace, fm_stream stream);
@@ -331,8 +337,9 @@ fm_status fm_rotation_loss_grad(fm_ctx* ctx, fm_scene* scene, const float* Rrel,
                                 double* loss, float* grad, fm_stream stream);
 
 /* K iterations of {gradient as fm_rotation_loss_grad, Adam update of params}
- * in ONE persistent cooperative kernel (as fm_epipolar_solve; the rotations
- * of the current parameters are kept between the two phases).  params, m, v
+ * in ONE persistent cooperative kernel, by the same two loops as
+ * fm_epipolar_solve (the rotations of the current parameters are kept from
+ * one iteration to the next).  params, m, v
  * [N,6] float32 are updated in place.  `cfg` (host) as for fm_epipolar_solve
  * with lr_rot the initial rate (lr_t unused).  loss_trace [K] double receives
  * L_R before each update (NULL = not written). */

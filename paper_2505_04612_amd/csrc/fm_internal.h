@@ -102,7 +102,8 @@ struct fm_scene {
   float* contrib = nullptr;       // [P, 24] per-pair gradient records
   float* fo_rec = nullptr;        // [P, 2] per-pair focal-scale gradient records (side i, side j)
   double* loss_part = nullptr;    // [loss_part_cap]
-  double* rot = nullptr;          // [N, 9] rotations of the current poses (fused solve)
+  double* rot = nullptr;          // [2, N, 9] rotations of the current poses (fused solve; two buffers)
+  float* params_alt = nullptr;    // [N, 9] second parameter buffer of the camera-centric fused loop
   int64_t loss_part_cap = 0;
   unsigned* bar = nullptr;        // [128] solve grid barrier, one 128-B line each: arrival count, generation,
                                   // failure flag of the running launch, failure total since the last query
@@ -111,7 +112,8 @@ struct fm_scene {
   int32_t ta_runs_cap = 0;        // runs the workspace holds
   int64_t ta_part_cap = 0;        // loss partials per run
   void* ta_rec = nullptr;         // [ta_runs_cap, P] float4 per-pair records: dL/ds and the pair's L1 term
-  double* ta_part = nullptr;      // [ta_runs_cap, ta_part_cap] per-workgroup loss partials
+  double* ta_part = nullptr;      // [2, ta_runs_cap, ta_part_cap] per-workgroup loss partials
+  float* ta_alt = nullptr;        // [ta_runs_cap, N, 3] second centre buffer of the camera loop
   double* ta_stats = nullptr;     // [ta_runs_cap, 4] centroid and mean norm of each run
   int ta_coop_blocks = 0;         // max co-resident blocks of the translation loop
   int ra_coop_blocks = 0;         // max co-resident blocks of the rotation loop
@@ -435,6 +437,18 @@ __device__ inline float adam_update(float p, float g, float& m, float& v, double
 // and the scene's failure total are raised, every later barrier of the
 // launch returns at once and the host reads the total with
 // fm_solve_barrier_failures.
+// Pair count below which the persistent loops (epipolar, translation) run
+// camera by camera when the caller leaves the grid automatic: one wavefront
+// per camera evaluates each of its pairs, so every pair is evaluated twice
+// but an iteration needs one grid barrier and no record round trip.  Above
+// it, where one wavefront per camera leaves the high-degree cameras'
+// wavefronts long and the rest idle, the pair loop wins.  Measured with the
+// epipolar loop, float64 Grams, per iteration (camera vs pair loop): 200
+// cameras / 4.9k pairs 10.5 vs 16.1 us; banded graphs 1,000 / 24.7k 12.3 vs
+// 33.4, 2,500 / 124k 34.3 vs 39.9, 5,000 / 249k 47.1 vs 50.7; the 5,000-camera
+// street graph (185k pairs, uneven degrees) 44.3 vs 41.0.
+constexpr int64_t kCamLoopMaxPairs = 131072;
+
 constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
 
 __device__ inline void grid_barrier(unsigned* __restrict__ bar) {

@@ -384,12 +384,148 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   }
 }
 
+// Camera-centric variant of the fused loop: one wavefront per camera; each
+// lane evaluates one of the camera's pairs (its loss and the adjoint for the
+// camera's own side, so every pair is evaluated twice, once from each end),
+// the wavefront sums them in a fixed order and lanes 0..8 take the Adam
+// step.  With no pair records to exchange, an iteration needs one grid
+// barrier instead of two; the parameters and rotations a wavefront reads of
+// other cameras are double-buffered by iteration parity so that each camera
+// updates its own without a second barrier.
+struct CamSolveArgs {
+  float* params;       // buffer 0 (the caller's)
+  float* params_alt;   // buffer 1 [N, 9]
+  float* m;
+  float* v;
+  const int32_t* cams;
+  const void* W36;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  double* rot;         // [2, N, 9]
+  double* loss_part;   // [2, gridDim.x]
+  double* loss_trace;
+  unsigned* bar;
+  const int64_t* Z_dev;
+  double inv_Z;
+  int64_t P;
+  int32_t N;
+  int32_t K;
+  double lr_rot, lr_t, log_frac;
+  double b1, b2, eps;
+  int64_t lr_step0, lr_total, adam_step0;
+};
+
+// Rotation of the parameters p0 held by lanes 0..5 of the wavefront, stored
+// by lanes 0..8 at rot[c].
+__device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float p0, int lane) {
+  double a1[3], a2[3], R[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    a1[j] = (double)__shfl(p0, j);
+    a2[j] = (double)__shfl(p0, 3 + j);
+  }
+  gs_matrix(gs_forward(a1, a2), R);
+  if (lane < 9) {
+    double rv = R[0][0];
+#pragma unroll
+    for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
+    rot[c * 9 + lane] = rv;
+  }
+}
+
+template <typename WT>
+__global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
+  __shared__ double lds[kSolveBlock / 64];
+  const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const int kq = lane < 9 ? lane : 8;
+  const WT* W36 = reinterpret_cast<const WT*>(a.W36);
+  const int64_t NR = (int64_t)a.N * 9;
+  // rotations of the initial parameters (buffer 0)
+  for (int64_t c = gwave; c < a.N; c += nwaves) {
+    const float p0 = a.params[c * 9 + kq];
+    cam_store_rot(a.rot, c, p0, lane);
+  }
+  grid_barrier(a.bar);
+  for (int k = 0; k < a.K; ++k) {
+    const int rb = k & 1;
+    const float* pr = rb ? a.params_alt : a.params;
+    float* pw = rb ? a.params : a.params_alt;
+    const double* rr = a.rot + rb * NR;
+    double* rw = a.rot + (rb ^ 1) * NR;
+    const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
+    const double step = (double)(a.adam_step0 + k + 1);
+    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    double lsum = 0.0;
+    // the loop bound is uniform over the wavefront, so the wavefront sums
+    // run with every lane present
+    for (int64_t c = gwave; c < a.N; c += nwaves) {
+      const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
+      // the camera's own parameters and moments (lanes 9..63 read entry 8)
+      const float p0 = pr[c * 9 + kq];
+      float mq = a.m[c * 9 + kq], vq = a.v[c * 9 + kq];
+      double acc[12];
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+      for (int q = lo + lane; q < hi; q += 64) {
+        const int item = a.cam_items[q];
+        const int64_t n = item >> 1;
+        const int side = item & 1;
+        float rec[24];
+        const double l = pair_loss_adjoint(pr, rr, a.cams[2 * n], a.cams[2 * n + 1], W36, n, 2.0 * iz, rec);
+        if (side == 0) lsum += l;   // each pair's loss once, from its first camera
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);
+      }
+      wave_sum12(acc, lane);
+      double a1[3], a2[3], g[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        a1[j] = (double)__shfl(p0, j);
+        a2[j] = (double)__shfl(p0, 3 + j);
+      }
+      gs_adjoint(acc, a1, a2, g);
+      const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
+      const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+      if (lane < 9) {
+        pw[c * 9 + lane] = pq;
+        a.m[c * 9 + lane] = mq;
+        a.v[c * 9 + lane] = vq;
+      }
+      cam_store_rot(rw, c, pq, lane);
+    }
+    if (a.loss_trace) {
+      const double t = block_sum(lsum, lds);
+      if (threadIdx.x == 0) a.loss_part[rb * gridDim.x + blockIdx.x] = t;
+    }
+    grid_barrier(a.bar);
+    if (a.loss_trace && gtid == 0) {
+      double sum = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) sum += a.loss_part[rb * gridDim.x + b];
+      a.loss_trace[k] = sum * iz;
+    }
+  }
+  // after an odd number of iterations the latest parameters are in buffer 1
+  if (a.K & 1) {
+    for (int64_t c = gwave; c < a.N; c += nwaves)
+      if (lane < 9) a.params[c * 9 + lane] = a.params_alt[c * 9 + lane];
+  }
+}
+
 int fm_solve_coop_blocks(fm_ctx* ctx) {
   int per_cu64 = 0, per_cu32 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_solve<double>, kSolveBlock, 0) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, k_solve<float>, kSolveBlock, 0) != hipSuccess) return 0;
-  const int per_cu = per_cu64 < per_cu32 ? per_cu64 : per_cu32;
+  int per_cu = per_cu64 < per_cu32 ? per_cu64 : per_cu32;
+  int pc64 = 0, pc32 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc64, k_solve_cam<double>, kSolveBlock, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc32, k_solve_cam<float>, kSolveBlock, 0) != hipSuccess) return 0;
+  if (pc64 < per_cu) per_cu = pc64;
+  if (pc32 < per_cu) per_cu = pc32;
   return per_cu * ctx->num_cu;
 }
 
@@ -435,6 +571,30 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   void* args[] = {&a};
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, s->bar);
   FM_CHECK_LAUNCH(ctx);
+  // automatic grid below kCamLoopMaxPairs: the camera-centric loop, one
+  // barrier per iteration; a forced workgroup count or a larger graph runs
+  // the pair loop
+  int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
+  if (want_cam > s->coop_blocks) want_cam = s->coop_blocks;
+  if (cfg->blocks <= 0 && s->P < kCamLoopMaxPairs && 2 * want_cam <= s->loss_part_cap) {
+    CamSolveArgs ca;
+    ca.params = params; ca.params_alt = s->params_alt; ca.m = m; ca.v = v;
+    ca.cams = s->pair_cams; ca.W36 = W36; ca.cam_ptr = s->cam_ptr; ca.cam_items = s->cam_items;
+    ca.rot = s->rot; ca.loss_part = s->loss_part; ca.loss_trace = loss_trace; ca.bar = s->bar; ca.Z_dev = Z_dev;
+    ca.inv_Z = inv_Z; ca.P = s->P; ca.N = s->N; ca.K = K;
+    ca.lr_rot = a.lr_rot; ca.lr_t = a.lr_t; ca.log_frac = a.log_frac;
+    ca.b1 = a.b1; ca.b2 = a.b2; ca.eps = a.eps;
+    ca.lr_step0 = a.lr_step0; ca.lr_total = a.lr_total; ca.adam_step0 = a.adam_step0;
+    void* cargs[] = {&ca};
+    fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
+    hipError_t e = wdt == FM_F64
+                       ? hipLaunchCooperativeKernel((const void*)k_solve_cam<double>, dim3((unsigned)want_cam),
+                                                    dim3(kSolveBlock), cargs, 0, (hipStream_t)stream)
+                       : hipLaunchCooperativeKernel((const void*)k_solve_cam<float>, dim3((unsigned)want_cam),
+                                                    dim3(kSolveBlock), cargs, 0, (hipStream_t)stream);
+    if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+    return FM_OK;
+  }
   fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
   hipError_t e = wdt == FM_F64 ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want),
                                                            dim3(kSolveBlock), args, 0, (hipStream_t)stream)

@@ -254,6 +254,110 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
   }
 }
 
+// Camera-by-camera variant of the loop (the automatic choice below
+// kCamLoopMaxPairs pairs): one wavefront per camera; each lane evaluates one
+// of the camera's pairs and keeps its own side of the record (float32, as
+// the records are), the wavefront sums them in a fixed order and lanes 0..5
+// take the Adam steps.  No records are exchanged, so an iteration needs one
+// grid barrier; the parameters and rotations other wavefronts read are
+// double-buffered by iteration parity.
+struct RaCamArgs {
+  float* params;       // buffer 0 [N, 6] (the caller's)
+  float* alt;          // buffer 1 [N, 6]
+  float* m;
+  float* v;
+  const int32_t* cams;
+  const float* Rrel;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  double* rot;         // [2, N, 9]
+  double* part;        // [2, gridDim.x]
+  double* trace;
+  unsigned* bar;
+  int64_t P;
+  int32_t N;
+  int32_t K;
+  double invP, lr, log_frac, b1, b2, eps;
+  int64_t lr_step0, lr_total, adam_step0;
+};
+
+__global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
+  __shared__ double lds[kSolveBlock / 64];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const int kq = lane < 6 ? lane : 5;
+  const int64_t NR = (int64_t)a.N * 9;
+  // rotations of the initial parameters (buffer 0)
+  for (int64_t c = gwave; c < a.N; c += nwaves) ra_store_rot(a.rot, c, a.params[6 * c + kq], 0, lane, true);
+  grid_barrier(a.bar);
+  for (int k = 0; k < a.K; ++k) {
+    const int rb = k & 1;
+    const float* pr = rb ? a.alt : a.params;
+    float* pw = rb ? a.params : a.alt;
+    const double* rr = a.rot + rb * NR;
+    double* rw = a.rot + (rb ^ 1) * NR;
+    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
+    const double step = (double)(a.adam_step0 + k + 1);
+    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    double lsum = 0.0;
+    // the loop bound is uniform over the wavefront, so the wavefront sums
+    // run with every lane present
+    for (int64_t c = gwave; c < a.N; c += nwaves) {
+      const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
+      const float p0 = pr[6 * c + kq];
+      float mq = a.m[6 * c + kq], vq = a.v[6 * c + kq];
+      double acc[12];
+#pragma unroll
+      for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+      for (int q = lo + lane; q < hi; q += 64) {
+        const int item = a.cam_items[q];
+        const int64_t n = item >> 1;
+        const int side = item & 1;
+        double Ri[3][3], Rj[3][3];
+        load_rot(rr, a.cams[2 * n], Ri);
+        load_rot(rr, a.cams[2 * n + 1], Rj);
+        float rec[24];
+        const double d = ra_pair(Ri, Rj, a.Rrel + 9 * n, a.invP, rec);
+        if (side == 0) lsum += d;   // each pair's term once, from its first camera
+#pragma unroll
+        for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);
+      }
+      wave_sum12(acc, lane);
+      double a1[3], a2[3], g[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        a1[j] = (double)__shfl(p0, j);
+        a2[j] = (double)__shfl(p0, 3 + j);
+      }
+      gs_adjoint(acc, a1, a2, g);
+      const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+      if (lane < 6) {
+        pw[6 * c + lane] = pq;
+        a.m[6 * c + lane] = mq;
+        a.v[6 * c + lane] = vq;
+      }
+      ra_store_rot(rw, c, pq, 0, lane, true);
+    }
+    if (a.trace) {
+      const double t = block_sum(lsum, lds);
+      if (threadIdx.x == 0) a.part[rb * gridDim.x + blockIdx.x] = t;
+    }
+    grid_barrier(a.bar);
+    if (a.trace && gtid == 0) {
+      double t = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) t += a.part[rb * gridDim.x + b];
+      a.trace[k] = t * a.invP;
+    }
+  }
+  // after an odd number of iterations the latest parameters are in buffer 1
+  if (a.K & 1) {
+    for (int64_t c = gwave; c < a.N; c += nwaves)
+      if (lane < 6) a.params[6 * c + lane] = a.alt[6 * c + lane];
+  }
+}
+
 // ------------------------------------------------------------------ initialisation (column-wise least squares)
 
 // The quadratic forms of the appendix on rotation initialisation, as an
@@ -662,6 +766,9 @@ extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rr
   if (s->ra_coop_blocks <= 0) {
     int per_cu = 0;
     FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ra_solve, kSolveBlock, 0));
+    int per_cu_cam = 0;
+    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_cam, k_ra_solve_cam, kSolveBlock, 0));
+    if (per_cu_cam < per_cu) per_cu = per_cu_cam;
     s->ra_coop_blocks = per_cu * ctx->num_cu;
     if (s->ra_coop_blocks <= 0) return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative rotation kernel");
   }
@@ -685,6 +792,25 @@ extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rr
   a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
   void* args[] = {&a};
   FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
+  // automatic grid on a graph below kCamLoopMaxPairs: the camera loop, one
+  // wavefront per camera up to the co-resident limit
+  int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
+  if (want_cam > s->ra_coop_blocks) want_cam = s->ra_coop_blocks;
+  if (cfg->blocks <= 0 && s->P < kCamLoopMaxPairs && 2 * want_cam <= s->loss_part_cap) {
+    RaCamArgs ca;
+    ca.params = params; ca.alt = s->params_alt; ca.m = m; ca.v = v;
+    ca.cams = s->pair_cams; ca.Rrel = Rrel; ca.cam_ptr = s->cam_ptr; ca.cam_items = s->cam_items;
+    ca.rot = s->rot; ca.part = s->loss_part; ca.trace = loss_trace; ca.bar = s->bar;
+    ca.P = s->P; ca.N = s->N; ca.K = K;
+    ca.invP = a.invP; ca.lr = a.lr; ca.log_frac = a.log_frac; ca.b1 = a.b1; ca.b2 = a.b2; ca.eps = a.eps;
+    ca.lr_step0 = a.lr_step0; ca.lr_total = a.lr_total; ca.adam_step0 = a.adam_step0;
+    void* cargs[] = {&ca};
+    fm_timed timer(ctx, FM_K_RA_SOLVE, st);
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_solve_cam, dim3((unsigned)want_cam),
+                                              dim3(kSolveBlock), cargs, 0, st);
+    if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+    return FM_OK;
+  }
   fm_timed timer(ctx, FM_K_RA_SOLVE, st);
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_solve, dim3((unsigned)want), dim3(kSolveBlock), args, 0, st);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));

@@ -243,10 +243,12 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->fo_rec);
   (void)hipFree(s->loss_part);
   (void)hipFree(s->rot);
+  (void)hipFree(s->params_alt);
   (void)hipFree(s->bar);
   (void)hipFree(s->ta_rec);
   (void)hipFree(s->ta_part);
   (void)hipFree(s->ta_stats);
+  (void)hipFree(s->ta_alt);
   (void)hipFree(s->lz);
   delete s;
 }
@@ -397,13 +399,14 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
     return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative solve kernel");
   }
   s->loss_part_cap = (int64_t)grid_for(P, kBlock);   // also covers k_pair_phase's blocks
-  if (s->loss_part_cap < s->coop_blocks) s->loss_part_cap = s->coop_blocks;
+  if (s->loss_part_cap < 2 * (int64_t)s->coop_blocks) s->loss_part_cap = 2 * (int64_t)s->coop_blocks;   // the camera loop double-buffers its partials
   SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_partials > 0 ? s->n_partials : 1)));
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->fo_rec, sizeof(float) * 2 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
-  SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * (N > 0 ? N : 1)));
+  SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * 2 * (N > 0 ? N : 1)));
+  SCENE_TRY(hipMalloc(&s->params_alt, sizeof(float) * 9 * (N > 0 ? N : 1)));
   SCENE_TRY(hipMalloc(&s->bar, sizeof(unsigned) * 128));
   SCENE_TRY(hipMemsetAsync(s->bar, 0, sizeof(unsigned) * 128, st));
   SCENE_TRY(hipStreamSynchronize(st));

@@ -338,6 +338,158 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
   }
 }
 
+// Camera-by-camera variant of the fused loop (the automatic choice): one
+// wavefront per camera; each lane evaluates one of the camera's pairs for a
+// group of runs and keeps its own side of dL/ds, rounded to float32 as the
+// pair records are; the wavefront sums them in a fixed order and lanes
+// 0 .. 3G-1 take the Adam steps.  Every pair is evaluated from both of its
+// cameras, so no records are exchanged and an iteration needs one grid
+// barrier; the centres other wavefronts read are double-buffered by
+// iteration parity.
+struct TaCamArgs {
+  float* centres;    // buffer 0 [runs, N, 3] (the caller's)
+  float* alt;        // buffer 1 [runs, N, 3]
+  float* m;
+  float* v;
+  const int32_t* cams;
+  const float* dirs;
+  const int32_t* cam_ptr;
+  const int32_t* cam_items;
+  double* part;      // [2, runs, part_stride]
+  int64_t part_stride;
+  double* trace;
+  unsigned* bar;
+  int64_t P;
+  int32_t N;
+  int32_t runs;
+  int32_t K;
+  double invP, lr, log_frac, b1, b2, eps;
+  int64_t lr_step0, lr_total, adam_step0;
+};
+
+// One camera for runs r0 .. r0 + G - 1 (G <= 4, so the 3G sums fit the
+// 12-value wave reduction).  `wl` (the wavefront's loss row in LDS, or NULL)
+// gathers the L1 terms of the pairs whose first camera this is, so each
+// pair's term is counted once.
+template <int G>
+__device__ inline void ta_cam_group(const TaCamArgs& a, const float* __restrict__ pr, float* __restrict__ pw,
+                                    int64_t c, int lo, int hi, int lane, int r0, double lr, double bc1, double bc2,
+                                    double* wl) {
+  const int64_t run_stride = (int64_t)a.N * 3;
+  // this lane's own coordinate (lanes past 3G repeat the last one)
+  const int l3 = lane < 3 * G ? lane : 3 * G - 1;
+  const int64_t own = (r0 + l3 / 3) * run_stride + c * 3 + l3 % 3;
+  const float p0 = pr[own];
+  float mq = a.m[own], vq = a.v[own];
+  double acc[12], ls[G];
+#pragma unroll
+  for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) ls[g] = 0.0;
+  for (int q = lo + lane; q < hi; q += 64) {
+    const int item = a.cam_items[q];
+    const int64_t n = item >> 1;
+    const int ci = a.cams[2 * n], cj = a.cams[2 * n + 1];
+    double d[3];
+    load_dir(a.dirs, n, d);
+    float oi[G][3], oj[G][3];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        oi[g][k] = pr[(r0 + g) * run_stride + 3 * (int64_t)ci + k];
+        oj[g][k] = pr[(r0 + g) * run_stride + 3 * (int64_t)cj + k];
+      }
+    const double sgn = (item & 1) ? 1.0 : -1.0;
+    const double first = (item & 1) ? 0.0 : 1.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      double sv[3], gr[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sv[k] = (double)oj[g][k] - (double)oi[g][k];
+      const double term = ta_term(sv, d, a.invP, gr);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[3 * g + k] += sgn * (double)(float)gr[k];
+      ls[g] += first * (double)(float)term;
+    }
+  }
+  wave_sum12(acc, lane);
+  double gl = acc[0];
+#pragma unroll
+  for (int j = 1; j < 3 * G; ++j) gl = (l3 == j) ? acc[j] : gl;
+  const float pq = adam_update(p0, (float)gl, mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+  if (lane < 3 * G) {
+    pw[own] = pq;
+    a.m[own] = mq;
+    a.v[own] = vq;
+  }
+  if (wl) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      double t = ls[g];
+#pragma unroll
+      for (int sh = 32; sh >= 1; sh >>= 1) t += __shfl_xor(t, sh);
+      if (lane == 0) wl[r0 + g] += t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
+  __shared__ double wloss[kSolveBlock / 64][kTaMaxRuns];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
+  const int64_t RS = (int64_t)a.runs * a.part_stride;
+  double* wl = a.trace ? wloss[wv] : nullptr;
+  for (int k = 0; k < a.K; ++k) {
+    const int rb = k & 1;
+    const float* pr = rb ? a.alt : a.centres;
+    float* pw = rb ? a.centres : a.alt;
+    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
+    const double step = (double)(a.adam_step0 + k + 1);
+    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    if (wl) wl[lane] = 0.0;   // kTaMaxRuns == 64: one entry per lane
+    // the loop bound is uniform over the wavefront, so the wavefront sums
+    // run with every lane present
+    for (int64_t c = gwave; c < a.N; c += nwaves) {
+      const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
+      int r0 = 0;
+      for (; r0 + 4 <= a.runs; r0 += 4) ta_cam_group<4>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl);
+      if (r0 + 2 <= a.runs) {
+        ta_cam_group<2>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl);
+        r0 += 2;
+      }
+      if (r0 < a.runs) ta_cam_group<1>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl);
+    }
+    if (a.trace) {
+      __syncthreads();
+      if ((int)threadIdx.x < a.runs) {
+        double t = 0.0;
+        for (int w = 0; w < kSolveBlock / 64; ++w) t += wloss[w][threadIdx.x];
+        a.part[rb * RS + threadIdx.x * a.part_stride + blockIdx.x] = t;
+      }
+    }
+    grid_barrier(a.bar);
+    if (a.trace && gtid == 0) {
+      for (int r = 0; r < a.runs; ++r) {
+        double t = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) t += a.part[rb * RS + r * a.part_stride + b];
+        a.trace[(int64_t)r * a.K + k] = t * a.invP;
+      }
+    }
+  }
+  // after an odd number of iterations the latest centres are in buffer 1
+  if (a.K & 1) {
+    const int64_t run_stride = (int64_t)a.N * 3;
+    for (int64_t c = gwave; c < a.N; c += nwaves)
+      for (int i = lane; i < 3 * a.runs; i += 64) {
+        const int64_t idx = (i / 3) * run_stride + c * 3 + i % 3;
+        a.centres[idx] = a.alt[idx];
+      }
+  }
+}
+
 // ------------------------------------------------------------------ merge of runs
 
 // Centroid and mean distance to it of each run's centres (one workgroup per
@@ -457,6 +609,9 @@ fm_status ta_reserve(fm_ctx* ctx, fm_scene* s, int runs) {
   if (s->ta_coop_blocks <= 0) {
     int per_cu = 0;
     FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ta_solve, kSolveBlock, 0));
+    int per_cu_cam = 0;
+    FM_HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_cam, k_ta_solve_cam, kSolveBlock, 0));
+    if (per_cu_cam < per_cu) per_cu = per_cu_cam;
     s->ta_coop_blocks = per_cu * ctx->num_cu;
     if (s->ta_coop_blocks <= 0) return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative translation kernel");
   }
@@ -467,14 +622,19 @@ fm_status ta_reserve(fm_ctx* ctx, fm_scene* s, int runs) {
   (void)hipFree(s->ta_rec);
   (void)hipFree(s->ta_part);
   (void)hipFree(s->ta_stats);
+  (void)hipFree(s->ta_alt);
   s->ta_rec = nullptr;
   s->ta_part = nullptr;
   s->ta_stats = nullptr;
+  s->ta_alt = nullptr;
   s->ta_runs_cap = 0;
   const int64_t P1 = s->P > 0 ? s->P : 1;
+  const int64_t N1 = s->N > 0 ? s->N : 1;
+  // loss partials: two sets (the camera loop alternates them by iteration)
   if (hipMalloc(&s->ta_rec, sizeof(float4) * runs * P1) != hipSuccess ||
-      hipMalloc(&s->ta_part, sizeof(double) * runs * part) != hipSuccess ||
-      hipMalloc(&s->ta_stats, sizeof(double) * 4 * runs) != hipSuccess) {
+      hipMalloc(&s->ta_part, sizeof(double) * 2 * runs * part) != hipSuccess ||
+      hipMalloc(&s->ta_stats, sizeof(double) * 4 * runs) != hipSuccess ||
+      hipMalloc(&s->ta_alt, sizeof(float) * 3 * runs * N1) != hipSuccess) {
     (void)hipGetLastError();
     return fm_fail(ctx, FM_ENOMEM, "translation workspace for %d runs: allocation failed", runs);
   }
@@ -580,6 +740,27 @@ extern "C" fm_status fm_translation_solve(fm_ctx* ctx, fm_scene* s, const float*
   a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
   void* args[] = {&a};
   FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
+  if (cfg->blocks <= 0 && s->P < kCamLoopMaxPairs) {
+    // automatic grid on a graph below kCamLoopMaxPairs: the camera loop, one
+    // wavefront per camera up to the co-resident limit (cameras strided
+    // beyond it)
+    int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
+    if (want_cam > s->ta_coop_blocks) want_cam = s->ta_coop_blocks;
+    if (want_cam > s->ta_part_cap) want_cam = s->ta_part_cap;
+    TaCamArgs ca;
+    ca.centres = centres; ca.alt = s->ta_alt; ca.m = m; ca.v = v;
+    ca.cams = s->pair_cams; ca.dirs = dirs; ca.cam_ptr = s->cam_ptr; ca.cam_items = s->cam_items;
+    ca.part = s->ta_part; ca.part_stride = s->ta_part_cap; ca.trace = loss_trace; ca.bar = s->bar;
+    ca.P = s->P; ca.N = s->N; ca.runs = runs; ca.K = K;
+    ca.invP = a.invP; ca.lr = a.lr; ca.log_frac = a.log_frac; ca.b1 = a.b1; ca.b2 = a.b2; ca.eps = a.eps;
+    ca.lr_step0 = a.lr_step0; ca.lr_total = a.lr_total; ca.adam_step0 = a.adam_step0;
+    void* cargs[] = {&ca};
+    fm_timed timer(ctx, FM_K_TA_SOLVE, st);
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_ta_solve_cam, dim3((unsigned)want_cam),
+                                              dim3(kSolveBlock), cargs, 0, st);
+    if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
+    return FM_OK;
+  }
   fm_timed timer(ctx, FM_K_TA_SOLVE, st);
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_ta_solve, dim3((unsigned)want), dim3(kSolveBlock), args, 0, st);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));

@@ -318,6 +318,36 @@ def test_fused_solve_grid_invariance(fm, ctx, name):
         assert torch.equal(p, results[0][1]) and torch.equal(m, results[0][2]) and torch.equal(v, results[0][3]), blocks
 
 
+@pytest.mark.parametrize("name", ["tiny", "medium"])
+def test_camera_loop_matches_pair_loop(fm, ctx, name):
+    """Small graphs run the fused loop camera by camera (every pair evaluated
+    from both of its cameras, one grid barrier per iteration) unless a
+    workgroup count is forced, which runs it pair by pair.  Both sum each
+    camera's records in float64 from the same float32 records, in different
+    orders, so they agree to rounding; the camera loop is deterministic."""
+    sc = scene(name)
+    s = _scene_on_gpu(fm, ctx, sc, torch.float64 if name == "tiny" else torch.float32)
+    W64, _ = fm.build_pair_grams(s)
+    th = torch.from_numpy(_theta(sc)).to(ctx.device)
+    out = []
+    for blocks in (0, 0, 16):
+        p = th.clone()
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        tr = torch.zeros(30, dtype=torch.float64, device=ctx.device)
+        fm.epipolar_solve(s, W64, p, m, v, 30, 3e-3, 1e-2, 1e-3, 0, 30, 0, inv_Z=1.0 / sc.num_matches,
+                          blocks=blocks, loss_trace=tr)
+        out.append((p, m, v, tr))
+    assert s.barrier_failures() == 0
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    p0, m0, v0, t0 = out[0]
+    p1, m1, v1, t1 = out[2]
+    torch.testing.assert_close(t0, t1, rtol=1e-9, atol=0)
+    torch.testing.assert_close(p0, p1, rtol=0, atol=2e-6)
+    torch.testing.assert_close(m0, m1, rtol=1e-3, atol=1e-6 * float(m1.abs().max()))
+
+
 def _oracle_sched(s):
     return ea.Schedule(iters=s.iters, round_len=s.round_len, lr_rot=f32(s.lr_rot), lr_t=f32(s.lr_t),
                        lr_final_frac=f32(s.lr_final_frac), beta1=f32(s.beta1), beta2=f32(s.beta2),

@@ -97,6 +97,27 @@ def test_fused_solve_grid_invariance():
         assert np.array_equal(got, ref), b
 
 
+@pytest.mark.parametrize("K", [60, 59])
+def test_camera_loop_matches_pair_loop(K):
+    """The automatic grid runs the loop camera by camera (every pair evaluated
+    from both of its cameras, one grid barrier per iteration); a forced
+    workgroup count runs it pair by pair.  Both sum the same float32 records
+    in float64, in different orders, so they agree to rounding; the camera
+    loop is deterministic.  An odd K ends in the second parameter buffer."""
+    ctx = _ctx()
+    sc = helpers.scene("medium")
+    inp = synth.rotation_inputs(sc)
+    s = _graph_scene(ctx, sc.R_gt.shape[0], sc.pairs)
+    Q = inp.R_rel.reshape(-1, 9).astype(np.float32)
+    th = _perturbed(sc, 6)
+    a, ta_ = _solve_gpu(ctx, s, Q, th, K, 1e-2, 1e-2, trace=True)
+    b, tb = _solve_gpu(ctx, s, Q, th, K, 1e-2, 1e-2, trace=True)
+    c, tc = _solve_gpu(ctx, s, Q, th, K, 1e-2, 1e-2, trace=True, blocks=16)
+    assert np.array_equal(a, b) and np.array_equal(ta_, tb)
+    np.testing.assert_allclose(a, c, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(ta_, tc, rtol=1e-9)
+
+
 @pytest.mark.parametrize("name", ["tiny", "medium"])
 def test_solve_endpoint_from_the_oracle_initialisation(name):
     ctx = _ctx()

@@ -166,6 +166,27 @@ def test_fused_solve_grid_invariance(tiny):
         assert np.array_equal(got, ref), b
 
 
+@pytest.mark.parametrize("runs,K", [(5, 50), (3, 49)])
+def test_camera_loop_matches_pair_loop(tiny, runs, K):
+    """The automatic grid runs the fused loop camera by camera (every pair
+    evaluated from both of its cameras, one grid barrier per iteration); a
+    forced workgroup count runs it pair by pair.  Both sum the same float32
+    values in float64, in different orders, so they agree to rounding; the
+    camera loop is deterministic.  5 runs take the groups of 4 and 1, 3 runs
+    those of 2 and 1; an odd K ends in the second centre buffer."""
+    ctx = _ctx()
+    inp = _inputs(tiny, runs)
+    s = _scene_of(ctx, tiny)
+    dirs = ta.target_directions(tiny.R_gt, inp.t_rel, tiny.pairs).astype(np.float32)
+    cen = inp.init.astype(np.float32)
+    a, ta_ = _solve_gpu(ctx, s, dirs, cen, K, 3e-2, 1e-2, trace=True)
+    b, tb = _solve_gpu(ctx, s, dirs, cen, K, 3e-2, 1e-2, trace=True)
+    c, tc = _solve_gpu(ctx, s, dirs, cen, K, 3e-2, 1e-2, trace=True, blocks=16)
+    assert np.array_equal(a, b) and np.array_equal(ta_, tb)
+    np.testing.assert_allclose(a, c, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(ta_, tc, rtol=1e-6)
+
+
 def test_merge_parity_on_gpu_runs(medium):
     from paper_2505_04612_amd import api
     ctx = _ctx()
