@@ -71,7 +71,6 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "medium_oracle.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "gram_medium_traffic.json")
 GRAM_SRC = os.path.join(ROOT, "paper_2505_04612_amd", "csrc", "gram.hip")
 HBM_PEAK_GBPS = 8000.0
-CAM_LOOP_MAX_PAIRS = 131072   # the library's automatic camera-loop limit (kCamLoopMaxPairs, fm_internal.h)
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12     # lane-instructions per second, non-packed
 VALU_PER_MATCH_BF16 = 65                       # IRLS Gram pass, BF16 coordinates
 
@@ -210,18 +209,15 @@ def bench_translation(ctx, s, sc, runs: int = 4, iters: int = 1000, final_iters:
         n_it += 1
     P = sc.num_pairs
     return {
-        "kernel": ("k_ta_solve_cam (persistent, one wavefront per camera: each pair's L1 term + adjoint from "
-                   "both cameras, Adam, 1 grid barrier)" if P < CAM_LOOP_MAX_PAIRS else
-                   "k_ta_solve (persistent: per-pair L1 term + adjoint, per-camera sum + Adam, 2 grid barriers)"),
+        "kernel": "k_ta_solve_cam (persistent, one wavefront per camera: each pair's L1 term + adjoint from "
+                  "both cameras, Adam, 1 grid barrier)",
         "pairs": P, "cameras": sc.num_cams, "runs": runs, "iters": iters, "final_iters": final_iters,
         "run_iters_per_s": runs * iters / (ms_runs / 1e3),
         "us_per_iter_all_runs": ms_runs * 1e3 / iters,
         "us_per_iter_one_run": ms_final * 1e3 / final_iters,
         "stage_wall_ms": wall * 1e3,
-        "bound": ("latency (one grid barrier per iteration; each pair read from both cameras: "
-                  "2 x %d B per pair and run through L2)" % (8 + 12 + 24) if P < CAM_LOOP_MAX_PAIRS else
-                  "latency (two grid barriers and two dependent memory rounds per iteration; "
-                  "%d B per pair and run moved through L2)" % (24 + 16 + 32)),
+        "bound": "latency (one grid barrier per iteration; each pair read from both cameras: "
+                 "2 x %d B per pair and run through L2)" % (8 + 12 + 24),
         "centre_err_vs_truth": {"median": float(np.median(err)), "max": float(err.max()),
                                 "single_run_max": run_err},
         "inputs": "unit relative translations from the true poses, 2 deg noise, 10 % outlier pairs; "
@@ -431,16 +427,13 @@ def bench_rotation(ctx, s, sc, steps: int = 300, iters: int = 500, cpu_budget: f
         t_it += time.perf_counter() - t
         n_it += 1
     return {
-        "kernels": "k_ra_lanczos (2 persistent launches, one per column) + " + (
-            "k_ra_solve_cam (persistent, one wavefront per camera: geodesic loss + adjoint of each pair from both "
-            "cameras, Adam)" if P < CAM_LOOP_MAX_PAIRS else
-            "k_ra_solve (persistent geodesic loss + adjoint + Adam)"),
+        "kernels": "k_ra_lanczos (2 persistent launches, one per column) + k_ra_solve_cam (persistent, one "
+                   "wavefront per camera: geodesic loss + adjoint of each pair from both cameras, Adam)",
         "pairs": P, "cameras": sc.num_cams, "lanczos_steps": [int(lz[1]), int(lz[3])], "iters": iters,
         "init_ms": init_ms, "us_per_lanczos_step": init_ms * 1e3 / max(lz[1] + lz[3], 1),
         "iters_per_s": iters / (solve_ms / 1e3), "us_per_iter": solve_ms * 1e3 / iters,
         "stage_wall_ms": wall * 1e3,
-        "bound": "latency (Lanczos: 6 grid barriers per step; solve: %d per iteration)" % (
-            1 if P < CAM_LOOP_MAX_PAIRS else 2),
+        "bound": "latency (Lanczos: 6 grid barriers per step; solve: 1 per iteration)",
         "rel_rot_err_vs_truth_deg": {"init_median": float(np.median(e_init)), "init_max": float(e_init.max()),
                                      "final_median": float(np.median(e_fin)), "final_max": float(e_fin.max())},
         "inputs": "relative rotations from the true poses, 2 deg noise, 10 % random-rotation outlier pairs",

@@ -260,8 +260,8 @@ fm_status fm_translation_loss_grad(fm_ctx* ctx, fm_scene* scene, const float* di
 
 /* K iterations of {gradient as fm_translation_loss_grad, Adam update of the
  * centres} for every run, in ONE persistent cooperative kernel, by the same
- * two loops as fm_epipolar_solve (camera by camera when cfg->blocks is 0 and
- * the graph has fewer than 131,072 pairs, else pair by pair).  centres, m, v
+ * two loops as fm_epipolar_solve (camera by camera when cfg->blocks is 0,
+ * at any graph size, else pair by pair).  centres, m, v
  * [runs,N,3] float32 are updated in place.  `cfg` (host) as for
  * fm_epipolar_solve, with lr_t the centres' initial rate (lr_rot unused).
  * loss_trace [runs,K] double receives L_t of each run before each update
@@ -338,8 +338,9 @@ fm_status fm_rotation_loss_grad(fm_ctx* ctx, fm_scene* scene, const float* Rrel,
 
 /* K iterations of {gradient as fm_rotation_loss_grad, Adam update of params}
  * in ONE persistent cooperative kernel, by the same two loops as
- * fm_epipolar_solve (the rotations of the current parameters are kept from
- * one iteration to the next).  params, m, v
+ * fm_epipolar_solve (camera by camera when cfg->blocks is 0, at any graph
+ * size; the rotations of the current parameters are kept from one iteration
+ * to the next).  params, m, v
  * [N,6] float32 are updated in place.  `cfg` (host) as for fm_epipolar_solve
  * with lr_rot the initial rate (lr_t unused).  loss_trace [K] double receives
  * L_R before each update (NULL = not written). */

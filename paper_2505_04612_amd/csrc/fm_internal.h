@@ -437,8 +437,9 @@ __device__ inline float adam_update(float p, float g, float& m, float& v, double
 // and the scene's failure total are raised, every later barrier of the
 // launch returns at once and the host reads the total with
 // fm_solve_barrier_failures.
-// Pair count below which the persistent loops (epipolar, translation) run
-// camera by camera when the caller leaves the grid automatic: one wavefront
+// Pair count below which the epipolar persistent loop runs camera by camera
+// when the caller leaves the grid automatic (the translation and rotation
+// loops, whose pair terms are cheaper, always do): one wavefront
 // per camera evaluates each of its pairs, so every pair is evaluated twice
 // but an iteration needs one grid barrier and no record round trip.  Above
 // it, where one wavefront per camera leaves the high-degree cameras'
