@@ -225,6 +225,21 @@ fm_status fm_epipolar_focal_loss_grad(fm_ctx* ctx, fm_scene* scene, const void* 
                                       const int64_t* Z_dev, double* loss, float* grad, float* gphi,
                                       fm_stream stream);
 
+/* K Adam steps on the poses and the log focal scales of the loss above in
+ * ONE persistent cooperative kernel, by the camera loop of
+ * fm_epipolar_solve (one wavefront per camera evaluates each of its pairs,
+ * one grid barrier per iteration).  params, m, v [N,9] and phi, m_phi,
+ * v_phi [N] float32 are updated in place.  `cfg` (host) as for
+ * fm_epipolar_solve (cfg->blocks ignored); lr_phi is the scales' initial
+ * rate, decayed like the others.  W36, wdtype, inv_Z, Z_dev as for
+ * fm_epipolar_focal_loss_grad.  loss_trace [K] double receives L before each
+ * update (NULL = not written). */
+fm_status fm_epipolar_focal_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dtype wdtype,
+                                  float* params, float* phi, float* m, float* v, float* m_phi,
+                                  float* v_phi, int32_t K, const fm_adam_cfg* cfg, float lr_phi,
+                                  double inv_Z, const int64_t* Z_dev, double* loss_trace,
+                                  fm_stream stream);
+
 /* ------------------------------------------------------------------ translation averaging */
 
 /* Global translation averaging, the stage before epipolar adjustment
@@ -425,7 +440,8 @@ fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_m
  *   rotation loop), FM_K_RA_PAIR 10 and FM_K_RA_CAMERA 11 (the two kernels of
  *   fm_rotation_loss_grad), FM_K_RA_INIT 12 (rotation initialisation),
  *   FM_K_TS_SEARCH 13 (relative-translation grid search), FM_K_FO_PAIR 14 and
- *   FM_K_FO_CAMERA 15 (the two kernels of fm_epipolar_focal_loss_grad).
+ *   FM_K_FO_CAMERA 15 (the two kernels of fm_epipolar_focal_loss_grad),
+ *   FM_K_FO_SOLVE 16 (persistent focal loop).
  * fm_profile_enable synchronises the device and clears earlier records;
  * fm_profile_read waits for the recorded events and returns the summed
  * elapsed milliseconds and the launch count of one kernel (host outputs). */

@@ -27,10 +27,10 @@ EXPORTS = [
     "fm_match_features", "fm_mlp_forward", "fm_mlp_backward",
     "fm_translation_directions", "fm_translation_loss_grad", "fm_translation_solve", "fm_translation_merge",
     "fm_rotation_loss_grad", "fm_rotation_solve", "fm_rotation_init", "fm_translation_search",
-    "fm_epipolar_focal_loss_grad", "fm_poses_from_centres",
+    "fm_epipolar_focal_loss_grad", "fm_epipolar_focal_solve", "fm_poses_from_centres",
 ]
 (K_GRAM, K_SOLVE, K_ESSENTIALS, K_FINALIZE, K_PAIR, K_CAMERA, K_TA_SOLVE, K_TA_PAIR, K_TA_CAMERA,
- K_RA_SOLVE, K_RA_PAIR, K_RA_CAMERA, K_RA_INIT, K_TS_SEARCH, K_FO_PAIR, K_FO_CAMERA) = range(16)
+ K_RA_SOLVE, K_RA_PAIR, K_RA_CAMERA, K_RA_INIT, K_TS_SEARCH, K_FO_PAIR, K_FO_CAMERA, K_FO_SOLVE) = range(17)
 
 
 class FastMapError(RuntimeError):
@@ -92,6 +92,8 @@ _SIGNATURES = {
     "fm_rotation_init": (_S, [_P, _P, _P, _P, _I32, _I32, _P, _P, _P]),
     "fm_translation_search": (_S, [_P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P]),
     "fm_epipolar_focal_loss_grad": (_S, [_P, _P, _P, _S, _P, _P, _D, _P, _P, _P, _P, _P]),
+    "fm_epipolar_focal_solve": (_S, [_P, _P, _P, _S, _P, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _F, _D,
+                                     _P, _P, _P]),
     "fm_poses_from_centres": (_S, [_P, _I32, _P, _P, _P, _P]),
 }
 

@@ -304,6 +304,35 @@ def epipolar_focal_loss_grad(scene: Scene, W36: torch.Tensor, params: torch.Tens
     return loss, grad, gphi
 
 
+def epipolar_focal_solve(scene: Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.Tensor,
+                         m: torch.Tensor, v: torch.Tensor, m_phi: torch.Tensor, v_phi: torch.Tensor, K: int,
+                         lr_rot: float, lr_t: float, lr_phi: float, lr_final_frac: float, lr_step0: int = 0,
+                         lr_total: int | None = None, adam_step0: int = 0, beta1: float = 0.9,
+                         beta2: float = 0.999, eps: float = 1e-12, inv_Z: float | None = None,
+                         Z: torch.Tensor | None = None, loss_trace: torch.Tensor | None = None) -> None:
+    """K fused Adam steps on poses [N,9] and log focal scales [N] (one
+    persistent kernel); params, phi and their moments are updated in place;
+    loss_trace [K] float64 optional."""
+    dev = scene.ctx.device
+    _require(W36, W36.dtype, (scene.num_pairs, 36), "W36", dev)
+    for name, t in (("params", params), ("m", m), ("v", v)):
+        _require(t, torch.float32, (scene.num_cams, 9), name, dev)
+    for name, t in (("phi", phi), ("m_phi", m_phi), ("v_phi", v_phi)):
+        _require(t, torch.float32, (scene.num_cams,), name, dev)
+    if loss_trace is not None:
+        _require(loss_trace, torch.float64, (K,), "loss_trace", dev)
+    if Z is not None:
+        _require(Z, torch.int64, (1,), "Z", dev)
+    elif inv_Z is None:
+        raise ValueError("give inv_Z or Z")
+    cfg = _lib.AdamCfg(lr_rot, lr_t, lr_final_frac, beta1, beta2, eps, lr_step0,
+                       K if lr_total is None else lr_total, adam_step0, 0)
+    check(scene.ctx.handle, scene.ctx.lib.fm_epipolar_focal_solve(
+        scene.ctx.handle, scene.handle, _ptr(W36), _wdtype(W36), _ptr(params), _ptr(phi), _ptr(m), _ptr(v),
+        _ptr(m_phi), _ptr(v_phi), int(K), ctypes.byref(cfg), float(lr_phi),
+        float(inv_Z if inv_Z is not None else 0.0), _ptr(Z), _ptr(loss_trace), _stream()))
+
+
 # ------------------------------------------------------------------ translation averaging
 
 def _runs_of(scene: Scene, centres: torch.Tensor) -> int:

@@ -36,7 +36,8 @@ constexpr int kKeptSlots = 256;
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
        FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_RA_SOLVE = 9, FM_K_RA_PAIR = 10,
        FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_TS_SEARCH = 13, FM_K_FO_PAIR = 14, FM_K_FO_CAMERA = 15,
-       FM_K_COUNT = 16 };
+       FM_K_FO_SOLVE = 16,
+       FM_K_COUNT = 17 };
 
 struct fm_timing {
   int kernel;
@@ -103,7 +104,7 @@ struct fm_scene {
   float* fo_rec = nullptr;        // [P, 2] per-pair focal-scale gradient records (side i, side j)
   double* loss_part = nullptr;    // [loss_part_cap]
   double* rot = nullptr;          // [2, N, 9] rotations of the current poses (fused solve; two buffers)
-  float* params_alt = nullptr;    // [N, 9] second parameter buffer of the camera-centric fused loop
+  float* params_alt = nullptr;    // [N, 10] second parameter buffer of the camera loops ([N, 9] poses, then [N] focal scales)
   int64_t loss_part_cap = 0;
   unsigned* bar = nullptr;        // [128] solve grid barrier, one 128-B line each: arrival count, generation,
                                   // failure flag of the running launch, failure total since the last query
@@ -116,6 +117,7 @@ struct fm_scene {
   float* ta_alt = nullptr;        // [ta_runs_cap, N, 3] second centre buffer of the camera loop
   double* ta_stats = nullptr;     // [ta_runs_cap, 4] centroid and mean norm of each run
   int ta_coop_blocks = 0;         // max co-resident blocks of the translation loop
+  int fo_coop_blocks = 0;         // max co-resident blocks of the focal loop
   int ra_coop_blocks = 0;         // max co-resident blocks of the rotation loop
   // rotation initialisation workspace (Lanczos basis), grown on demand
   int64_t lz_cap = 0;             // doubles held by lz

@@ -406,7 +406,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMalloc(&s->fo_rec, sizeof(float) * 2 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
   SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * 2 * (N > 0 ? N : 1)));
-  SCENE_TRY(hipMalloc(&s->params_alt, sizeof(float) * 9 * (N > 0 ? N : 1)));
+  SCENE_TRY(hipMalloc(&s->params_alt, sizeof(float) * 10 * (N > 0 ? N : 1)));
   SCENE_TRY(hipMalloc(&s->bar, sizeof(unsigned) * 128));
   SCENE_TRY(hipMemsetAsync(s->bar, 0, sizeof(unsigned) * 128, st));
   SCENE_TRY(hipStreamSynchronize(st));

@@ -1,10 +1,10 @@
 """Focal-length refinement inside epipolar adjustment (FastMap, arXiv
-2505.04612, Sec. 3.3: the focal lengths built into the essential matrices),
-host orchestration of the library's kernels: each Adam step is one
-fm_epipolar_focal_loss_grad (pair and camera kernels) and one fm_adam_step
-over the poses and one over the log focal scales.  The learning rates decay
-exponentially from lr0 to lr0 * frac over the loop; the host only writes the
-step's rates into small device vectors.
+2505.04612, Sec. 3.3: the focal lengths built into the essential matrices).
+By default the whole Adam loop is one persistent launch
+(fm_epipolar_focal_solve); `fused=False` runs it step by step from the host:
+one fm_epipolar_focal_loss_grad (pair and camera kernels), one fm_adam_step
+over the poses and one over the log focal scales per step.  The learning
+rates decay exponentially from lr0 to lr0 * frac over the loop.
 """
 from __future__ import annotations
 
@@ -29,13 +29,19 @@ class FocalSchedule:
 
 
 def solve(scene: api.Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.Tensor, inv_Z: float,
-          sched: FocalSchedule = FocalSchedule(), trace: bool = False):
+          sched: FocalSchedule = FocalSchedule(), trace: bool = False, fused: bool = True):
     """Refine poses [N,9] and log focal scales [N] in place; returns the loss
     trace (host list) if `trace`."""
     ctx = scene.ctx
     N = scene.num_cams
     mp, vp = torch.zeros_like(params), torch.zeros_like(params)
     mf, vf = torch.zeros_like(phi), torch.zeros_like(phi)
+    if fused:
+        tr = torch.empty(sched.iters, dtype=torch.float64, device=params.device) if trace else None
+        api.epipolar_focal_solve(scene, W36, params, phi, mp, vp, mf, vf, sched.iters, sched.lr_rot, sched.lr_t,
+                                 sched.lr_phi, sched.lr_final_frac, beta1=sched.beta1, beta2=sched.beta2,
+                                 eps=sched.eps, inv_Z=inv_Z, loss_trace=tr)
+        return tr.cpu().tolist() if trace else None
     lr0 = np.tile(np.array([sched.lr_rot] * 6 + [sched.lr_t] * 3, np.float32), N)
     lr_p = torch.empty(9 * N, dtype=torch.float32, device=params.device)
     lr_f = torch.empty(1, dtype=torch.float32, device=params.device)

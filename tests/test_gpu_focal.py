@@ -62,6 +62,54 @@ def test_parity_with_the_oracle(name, wdt):
     np.testing.assert_allclose(gp.cpu().numpy(), wgp, rtol=1e-4, atol=1e-5 * np.abs(wgp).max())
 
 
+def test_fused_steps_match_oracle_adam():
+    """Five steps of the persistent focal loop (poses and scales free)
+    against the oracle's Adam on the same Grams."""
+    from paper_2505_04612_amd import api
+    ctx, sc, s, W64, W32, theta = _setup("medium")
+    phi0 = (0.05 * np.random.default_rng(6).normal(size=sc.num_cams)).astype(np.float32)
+    iz = 1.0 / sc.num_matches
+    p, phi = _dev(ctx, theta), _dev(ctx, phi0)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    mf, vf = torch.zeros_like(phi), torch.zeros_like(phi)
+    tr = torch.empty(5, dtype=torch.float64, device=ctx.device)
+    api.epipolar_focal_solve(s, W64, p, phi, m, v, mf, vf, 5, 3e-3, 1e-2, 1e-2, 1e-2, inv_Z=iz, loss_trace=tr)
+    assert s.barrier_failures() == 0
+    Wf = helpers.expand36(W64.cpu().numpy())
+    wth, wphi, wtr = fo.solve(theta.astype(np.float64), phi0.astype(np.float64), sc.pairs, Wf, iz, 5,
+                              lr_rot=float(np.float32(3e-3)), lr_t=float(np.float32(1e-2)),
+                              lr_phi=float(np.float32(1e-2)), frac=float(np.float32(1e-2)))
+    # five steps of at most lr each; float32 parameters, records and moments
+    np.testing.assert_allclose(p.cpu().numpy(), wth, rtol=0, atol=2e-5)
+    np.testing.assert_allclose(phi.cpu().numpy(), wphi, rtol=0, atol=2e-5)
+    assert abs(tr[0].item() - wtr[0]) <= 1e-9 * wtr[0]
+    np.testing.assert_allclose(tr.cpu().numpy(), wtr, rtol=1e-6)
+
+
+@pytest.mark.parametrize("K", [50, 49])
+def test_fused_loop_matches_the_host_loop(K):
+    """The persistent loop (each pair evaluated from both cameras) against
+    the host loop of loss + gradient and Adam launches: the same float32
+    records summed in float64 in different orders, so they agree to
+    rounding; the persistent loop is deterministic.  An odd K ends in the
+    second parameter buffer."""
+    from paper_2505_04612_amd import focal
+    ctx, sc, s, W64, W32, theta = _setup("medium")
+    phi0 = (0.05 * np.random.default_rng(7).normal(size=sc.num_cams)).astype(np.float32)
+    iz = 1.0 / sc.num_matches
+    sched = focal.FocalSchedule(iters=K)
+    out = []
+    for fused in (True, True, False):
+        p, phi = _dev(ctx, theta), _dev(ctx, phi0)
+        tr = focal.solve(s, W64, p, phi, iz, sched, trace=True, fused=fused)
+        out.append((p.cpu().numpy(), phi.cpu().numpy(), np.asarray(tr)))
+    assert s.barrier_failures() == 0
+    assert all(np.array_equal(a, b) for a, b in zip(out[0], out[1]))
+    np.testing.assert_allclose(out[0][0], out[2][0], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(out[0][1], out[2][1], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(out[0][2], out[2][2], rtol=1e-6)
+
+
 def test_recovers_a_ten_percent_focal_error_with_poses_held():
     from paper_2505_04612_amd import focal
     ctx = _ctx()
@@ -95,3 +143,10 @@ def test_empty_graph():
     p = _dev(ctx, np.tile(np.array([1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32), (3, 1)))
     L, g, gp = api.epipolar_focal_loss_grad(s, W, p, torch.zeros(3, dtype=torch.float32, device=ctx.device), 1.0)
     assert L.item() == 0.0 and np.all(g.cpu().numpy() == 0) and np.all(gp.cpu().numpy() == 0)
+    # the persistent loop on a graph without pairs: zero gradients, no moves
+    p2 = p.clone()
+    z = torch.zeros(3, dtype=torch.float32, device=ctx.device)
+    phi = z.clone()
+    api.epipolar_focal_solve(s, W, p2, phi, torch.zeros_like(p), torch.zeros_like(p), z.clone(), z.clone(), 3,
+                             3e-3, 1e-2, 1e-2, 1e-2, inv_Z=1.0)
+    assert torch.equal(p2, p) and torch.equal(phi, z)
