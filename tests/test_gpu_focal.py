@@ -86,8 +86,8 @@ def test_fused_steps_match_oracle_adam():
     np.testing.assert_allclose(tr.cpu().numpy(), wtr, rtol=1e-6)
 
 
-@pytest.mark.parametrize("K", [50, 49])
-def test_fused_loop_matches_the_host_loop(K):
+@pytest.mark.parametrize("K,wdt", [(50, "f64"), (49, "f64"), (49, "f32")])
+def test_fused_loop_matches_the_host_loop(K, wdt):
     """The persistent loop (each pair evaluated from both cameras) against
     the host loop of loss + gradient and Adam launches: the same float32
     records summed in float64 in different orders, so they agree to
@@ -95,13 +95,14 @@ def test_fused_loop_matches_the_host_loop(K):
     second parameter buffer."""
     from paper_2505_04612_amd import focal
     ctx, sc, s, W64, W32, theta = _setup("medium")
+    W = W64 if wdt == "f64" else W32
     phi0 = (0.05 * np.random.default_rng(7).normal(size=sc.num_cams)).astype(np.float32)
     iz = 1.0 / sc.num_matches
     sched = focal.FocalSchedule(iters=K)
     out = []
     for fused in (True, True, False):
         p, phi = _dev(ctx, theta), _dev(ctx, phi0)
-        tr = focal.solve(s, W64, p, phi, iz, sched, trace=True, fused=fused)
+        tr = focal.solve(s, W, p, phi, iz, sched, trace=True, fused=fused)
         out.append((p.cpu().numpy(), phi.cpu().numpy(), np.asarray(tr)))
     assert s.barrier_failures() == 0
     assert all(np.array_equal(a, b) for a, b in zip(out[0], out[1]))

@@ -318,8 +318,8 @@ def test_fused_solve_grid_invariance(fm, ctx, name):
         assert torch.equal(p, results[0][1]) and torch.equal(m, results[0][2]) and torch.equal(v, results[0][3]), blocks
 
 
-@pytest.mark.parametrize("name", ["tiny", "medium"])
-def test_camera_loop_matches_pair_loop(fm, ctx, name):
+@pytest.mark.parametrize("name,wdt", [("tiny", "f64"), ("medium", "f64"), ("medium", "f32")])
+def test_camera_loop_matches_pair_loop(fm, ctx, name, wdt):
     """Small graphs run the fused loop camera by camera (every pair evaluated
     from both of its cameras, one grid barrier per iteration) unless a
     workgroup count is forced, which runs it pair by pair.  Both sum each
@@ -327,7 +327,8 @@ def test_camera_loop_matches_pair_loop(fm, ctx, name):
     orders, so they agree to rounding; the camera loop is deterministic."""
     sc = scene(name)
     s = _scene_on_gpu(fm, ctx, sc, torch.float64 if name == "tiny" else torch.float32)
-    W64, _ = fm.build_pair_grams(s)
+    W64, W32 = fm.build_pair_grams(s)
+    W = W64 if wdt == "f64" else W32
     th = torch.from_numpy(_theta(sc)).to(ctx.device)
     out = []
     for blocks in (0, 0, 16):
@@ -335,7 +336,7 @@ def test_camera_loop_matches_pair_loop(fm, ctx, name):
         m = torch.zeros_like(p)
         v = torch.zeros_like(p)
         tr = torch.zeros(30, dtype=torch.float64, device=ctx.device)
-        fm.epipolar_solve(s, W64, p, m, v, 30, 3e-3, 1e-2, 1e-3, 0, 30, 0, inv_Z=1.0 / sc.num_matches,
+        fm.epipolar_solve(s, W, p, m, v, 30, 3e-3, 1e-2, 1e-3, 0, 30, 0, inv_Z=1.0 / sc.num_matches,
                           blocks=blocks, loss_trace=tr)
         out.append((p, m, v, tr))
     assert s.barrier_failures() == 0
