@@ -350,6 +350,60 @@ def bench_focal(ctx, sc, kappa: float = 1.05, iters: int = 300, reps: int = 50) 
     }
 
 
+MFMA_F16_PEAK_T = 2500.0   # TFLOP/s, dense FP16 MFMA (MI355X)
+
+
+def bench_mlp(ctx, M: int, reps: int = 20) -> dict:
+    """The learned-weight MLP (3 -> 64 -> 64 -> 1) over M matches of seeded
+    random features and weights: forward alone (what a solve runs), forward
+    keeping the activations, and backward.  Flops counted: the 64 x 64 layer
+    on MFMA (2 * 4096 per match per pass; the backward has two such
+    products), against the dense FP16 MFMA peak; bytes: the features and
+    outputs (forward), plus the FP16 activations (kept / backward)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_04612_amd import api
+    dev = ctx.device
+    rng = np.random.default_rng(5)
+    feats = torch.from_numpy(rng.normal(size=(M, 3)).astype(np.float32)).to(dev)
+    w = api.MlpWeights(dev)
+    w.load_numpy({k: rng.normal(scale=0.3, size=sh) for k, sh in api.MLP_SHAPES.items()},
+                 np.zeros(3), np.ones(3))
+    dout = torch.from_numpy(rng.normal(size=M).astype(np.float32)).to(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+
+    t_fwd = timed(lambda: api.mlp_forward(ctx, w, feats))
+    _, act = api.mlp_forward(ctx, w, feats, keep_act=True)
+    t_fwd_act = timed(lambda: api.mlp_forward(ctx, w, feats, keep_act=True))
+    g = api.MlpWeights(dev)
+    t_bwd = timed(lambda: api.mlp_backward(ctx, w, feats, act, dout, g))
+    fl = 2.0 * 64 * 64
+    return {
+        "kernels": "k_mlp_forward (64x64 layer on v_mfma_f32_16x16x16_f16), k_mlp_backward + k_mlp_reduce",
+        "matches": M,
+        "forward_us": t_fwd * 1e6, "forward_matches_per_s": M / t_fwd,
+        "forward_keep_act_us": t_fwd_act * 1e6, "backward_us": t_bwd * 1e6,
+        "roofline_forward": {"mfma_TFLOPs": fl * M / t_fwd / 1e12, "mfma_frac": fl * M / t_fwd / 1e12 / MFMA_F16_PEAK_T,
+                             "hbm_GBps": 16.0 * M / t_fwd / 1e9, "hbm_frac": 16.0 * M / t_fwd / 1e9 / HBM_PEAK_GBPS},
+        "roofline_backward": {"mfma_TFLOPs": 2 * fl * M / t_bwd / 1e12,
+                              "mfma_frac": 2 * fl * M / t_bwd / 1e12 / MFMA_F16_PEAK_T,
+                              "hbm_GBps": (12.0 + 256.0 + 4.0) * M / t_bwd / 1e9,
+                              "hbm_frac": (12.0 + 256.0 + 4.0) * M / t_bwd / 1e9 / HBM_PEAK_GBPS},
+        "inputs": "seeded N(0,1) features and N(0, 0.3^2) weights; as many matches as the scene",
+    }
+
+
 def bench_search(ctx, s, sc, C: int = 4096, reps: int = 20, cpu_pairs: int = 200) -> dict:
     """Grid search of the unit relative translation of every pair over C
     Fibonacci-lattice candidates, from the Grams of the matches an upstream
@@ -505,6 +559,7 @@ def main() -> int:
     ap.add_argument("--no-search", action="store_true", help="skip the relative-translation grid-search leg")
     ap.add_argument("--no-focal", action="store_true", help="skip the focal-refinement leg")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the pose-pipeline leg")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-weight MLP leg")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for HBM byte counters)")
@@ -624,6 +679,9 @@ def main() -> int:
     if not args.no_pipeline:
         log("[bench] the pose stages in sequence")
         out["pose_pipeline"] = bench_pipeline(ctx, s, sc)
+    if not args.no_mlp:
+        log("[bench] learned-weight MLP over the scene's match count")
+        out["learned_mlp"] = bench_mlp(ctx, M)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc, coords, theta0, sd, args.cpu_budget)

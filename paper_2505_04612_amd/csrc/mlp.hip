@@ -341,10 +341,10 @@ static fm_status mlp_ptrs(fm_ctx* ctx, const fm_mlp* w, MlpPtrs& p) {
   return FM_OK;
 }
 
-static unsigned mlp_blocks(fm_ctx* ctx, int64_t M) {
+static unsigned mlp_blocks(fm_ctx* ctx, int64_t M, int per_cu = 2) {
   const int64_t tiles = (M + 15) / 16;
   int64_t b = (tiles + 3) / 4;
-  const int64_t cap = (int64_t)ctx->num_cu * 2;
+  const int64_t cap = (int64_t)ctx->num_cu * per_cu;
   return (unsigned)(b < cap ? (b > 0 ? b : 1) : cap);
 }
 
@@ -358,7 +358,10 @@ extern "C" fm_status fm_mlp_forward(fm_ctx* ctx, int64_t M, const float* feats, 
   if (M == 0) return FM_OK;
   if (!feats || !out) return fm_fail(ctx, FM_EINVAL, "fm_mlp_forward: NULL feats or out");
   FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_blocks(ctx, M)), dim3(256), 0, (hipStream_t)stream, M, feats, p,
+  // four workgroups of four wavefronts per CU: the forward kernel's register
+  // use allows four wavefronts per SIMD, and its per-tile chain (feature load,
+  // layer 1 from LDS, MFMA, epilogue) needs them to hide its latency
+  hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_blocks(ctx, M, 4)), dim3(256), 0, (hipStream_t)stream, M, feats, p,
                      out_scale, out, (_Float16*)act);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
