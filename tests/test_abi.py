@@ -35,3 +35,25 @@ def test_binding_covers_header():
     from paper_2505_04612_amd import _lib
     assert sorted(_lib.EXPORTS) == declared()
     assert sorted(_lib._SIGNATURES) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_every_call_rejects_a_null_context_without_a_device():
+    """Host-side validation comes first: with a NULL context every call that
+    takes one returns FM_EINVAL and touches no device (this runs on the CPU)."""
+    from paper_2505_04612_amd import _lib
+    lib = ctypes.CDLL(LIB)
+    no_ctx = {"fm_create", "fm_destroy", "fm_last_error", "fm_version", "fm_scene_destroy", "fm_scene_work_items"}
+    for name in _lib.EXPORTS:
+        if name in no_ctx:
+            continue
+        restype, argtypes = _lib._SIGNATURES[name]
+        f = getattr(lib, name)
+        f.restype, f.argtypes = restype, argtypes
+        args = [0.0 if a in (ctypes.c_float, ctypes.c_double) else
+                (None if a is ctypes.c_void_p or (isinstance(a, type) and issubclass(a, ctypes._Pointer)) else 0)
+                for a in argtypes]
+        assert f(*args) == _lib.FM_EINVAL, name
+    f = lib.fm_scene_work_items
+    f.restype, f.argtypes = ctypes.c_int64, [ctypes.c_void_p]
+    assert f(None) == -1
