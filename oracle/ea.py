@@ -87,13 +87,6 @@ def pair_grams(uv: np.ndarray, offsets: np.ndarray, weights: np.ndarray | None =
     return out
 
 
-def pair_weight_sums(offsets: np.ndarray, weights: np.ndarray | None, M: int) -> np.ndarray:
-    offsets = np.asarray(offsets, dtype=np.int64)
-    om = np.ones(M) if weights is None else np.asarray(weights, dtype=np.float64)
-    cs = np.concatenate([[0.0], np.cumsum(om)])
-    return cs[offsets[1:]] - cs[offsets[:-1]]
-
-
 # ------------------------------------------------------------------ poses
 
 def rot_from_6d(a1: np.ndarray, a2: np.ndarray) -> np.ndarray:
@@ -209,13 +202,28 @@ def loss_grad(theta: np.ndarray, pairs: np.ndarray, W: np.ndarray, inv_Z: float)
 
 # ------------------------------------------------------------------ residuals and IRLS
 
-def residuals(theta: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.ndarray) -> np.ndarray:
-    """Algebraic epipolar residual r_nm = x2~^T E_n x1~ for every match [M]."""
+def residuals(theta: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.ndarray,
+              block: int = 1 << 22) -> np.ndarray:
+    """Algebraic epipolar residual r_nm = x2~^T E_n x1~ for every match [M].
+
+    The matches are taken in runs of whole pairs of about `block` matches so
+    that scenes of 10^8 matches fit in host memory; each residual is the same
+    three-factor product either way."""
     E = essentials(theta, pairs)
-    counts = np.diff(np.asarray(offsets, dtype=np.int64))
-    En = np.repeat(E, counts, axis=0)
-    x1, x2 = homogeneous(uv)
-    return np.einsum("ma,mab,mb->m", x2, En, x1)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    counts = np.diff(offsets)
+    P = counts.size
+    out = np.zeros(int(offsets[-1]))
+    n0 = 0
+    while n0 < P:
+        n1 = int(np.searchsorted(offsets, offsets[n0] + block, side="right")) - 1
+        n1 = min(max(n1, n0 + 1), P)
+        lo, hi = int(offsets[n0]), int(offsets[n1])
+        En = np.repeat(E[n0:n1], counts[n0:n1], axis=0)
+        x1, x2 = homogeneous(uv[lo:hi])
+        out[lo:hi] = np.einsum("ma,mab,mb->m", x2, En, x1)
+        n0 = n1
+    return out
 
 
 def irls_weights(r: np.ndarray, delta: float, tau: float) -> np.ndarray:
@@ -268,27 +276,36 @@ def tau_at(sched: Schedule, k: int) -> float:
 
 
 def solve(theta0: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.ndarray,
-          sched: Schedule, weights0: np.ndarray | None = None):
+          sched: Schedule, weights0: np.ndarray | None = None, history: list | None = None):
     """Epipolar adjustment: loops of Adam steps on the weighted Gram form, with
     IRLS reweighting and outlier filtering between loops (Sec. 3.3).
 
-    Returns (theta, loss trace, final weights).
+    Returns (theta, loss trace, final weights).  If `history` is a list, one
+    record per optimisation loop is appended to it: the loop index, the
+    filter threshold its weights were computed with (None for unit or given
+    weights), the poses they were computed at (None likewise), and Z.
     """
     theta = np.asarray(theta0, dtype=np.float64).copy()
     M = uv.shape[0]
     weights = weights0
     k_rw = 0
+    rw_tau, rw_theta = None, None
     if weights is None and sched.irls and not sched.first_round_unit_weights:
-        weights = irls_weights(residuals(theta, pairs, offsets, uv), sched.delta, tau_at(sched, k_rw))
+        rw_tau, rw_theta = tau_at(sched, k_rw), theta.copy()
+        weights = irls_weights(residuals(theta, pairs, offsets, uv), sched.delta, rw_tau)
         k_rw += 1
     trace = []
     done = 0
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
     t_adam = 0
+    loop = 0
     while done < sched.iters:
         W = pair_grams(uv, offsets, weights)
         Z = M if weights is None else int(np.count_nonzero(weights))
+        if history is not None:
+            history.append({"loop": loop, "tau": rw_tau, "theta": rw_theta, "Z": Z})
+        loop += 1
         inv_Z = 1.0 / max(Z, 1)
         if sched.reset_adam:
             m = np.zeros_like(theta)
@@ -303,7 +320,8 @@ def solve(theta0: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.nda
                                     sched.beta1, sched.beta2, sched.eps)
         done += K
         if sched.irls and done < sched.iters:
-            weights = irls_weights(residuals(theta, pairs, offsets, uv), sched.delta, tau_at(sched, k_rw))
+            rw_tau, rw_theta = tau_at(sched, k_rw), theta.copy()
+            weights = irls_weights(residuals(theta, pairs, offsets, uv), sched.delta, rw_tau)
             k_rw += 1
     return theta, np.array(trace), weights
 

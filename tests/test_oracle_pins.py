@@ -331,6 +331,78 @@ def test_solve_converges_to_ground_truth_noise_free(tiny_clean):
     assert trace[-1] < 1e-5 * trace[0]
 
 
+@pytest.fixture(scope="module")
+def tiny_outliers():
+    return synth.tiny(sigma=0.0, frac=0.2, init_trans="gt")
+
+
+def test_irls_solve_rejects_outliers(tiny_outliers):
+    """The IRLS branch of the solve (Sec. 3.3, the IRLS and filtering
+    paragraph): on noise-free matches with 20 % outliers, from the true poses
+    with 1 deg rotation noise, reweighting and filtering between loops return
+    the solve to the truth, while the same schedule without reweighting (plain
+    L2 over every match) is pulled far away by the outliers."""
+    s = tiny_outliers
+    assert 0.15 < s.outlier.mean() < 0.25
+    R1, t1 = synth._init_poses(s.R_gt, s.t_gt, 0, rot_deg=1.0, trans="gt")
+    th0 = ea.params_from_poses(R1, t1)
+    th_gt = ea.params_from_poses(s.R_gt, s.t_gt)
+    errs = {}
+    for irls in (True, False):
+        sched = ea.Schedule(iters=1000, round_len=100, lr_rot=3e-3, lr_t=9e-3, lr_final_frac=1e-3, irls=irls)
+        th, _, w = ea.solve(th0, s.pairs, s.offsets, s.uv, sched)
+        errs[irls] = ea.relative_pose_errors(th, th_gt, s.pairs)
+        if irls:
+            # the final filter (tau_min = 0.01) drops most outliers and no inlier
+            assert np.all(w[~s.outlier] > 0)
+            assert np.count_nonzero(w[s.outlier]) < 0.2 * s.outlier.sum()
+    assert errs[True][0].max() < 0.01 and errs[True][1].max() < 0.1
+    assert errs[False][0].max() > 1.0
+
+
+def test_irls_loop_records_against_hand_count(tiny_outliers):
+    """Loop by loop: the first loop's weights come from the initial poses
+    (reading R8), each later loop's from the poses the previous loop ended at;
+    the filter threshold is tau0 halved per reweighting down to tau_min
+    (0.1, 0.05, 0.025, 0.0125, 0.01, 0.01); Z equals a hand count of the
+    matches with |r| <= tau at those poses.  One loop is replayed by hand from
+    the oracle's pinned pieces (Gram, loss gradient, Adam)."""
+    s = tiny_outliers
+    R1, t1 = synth._init_poses(s.R_gt, s.t_gt, 0, rot_deg=2.0, trans="gt")
+    th0 = ea.params_from_poses(R1, t1)
+    sched = ea.Schedule(iters=600, round_len=100, lr_rot=3e-3, lr_t=9e-3, lr_final_frac=1e-3, irls=True)
+    hist = []
+    th, trace, w = ea.solve(th0, s.pairs, s.offsets, s.uv, sched, history=hist)
+    assert [h["loop"] for h in hist] == list(range(6))
+    assert [h["tau"] for h in hist] == [0.1, 0.05, 0.025, 0.0125, 0.01, 0.01]
+    assert np.array_equal(hist[0]["theta"], th0)
+    for h in hist:
+        r = ea.residuals(h["theta"], s.pairs, s.offsets, s.uv)
+        count = 0
+        for x in r.tolist():
+            if abs(x) <= h["tau"]:
+                count += 1
+        assert h["Z"] == count
+    assert np.count_nonzero(w) == hist[-1]["Z"]
+    assert len(trace) == 600
+    # loop 0 by hand: weights at th0, Gram, 100 Adam steps from zero moments
+    w0 = np.where(np.abs(ea.residuals(th0, s.pairs, s.offsets, s.uv)) <= 0.1,
+                  1.0 / np.maximum(np.abs(ea.residuals(th0, s.pairs, s.offsets, s.uv)), 1e-4), 0.0)
+    W = ea.pair_grams(s.uv, s.offsets, w0)
+    x, m, v = th0.copy(), np.zeros_like(th0), np.zeros_like(th0)
+    for k in range(100):
+        L, g = ea.loss_grad(x, s.pairs, W, 1.0 / np.count_nonzero(w0))
+        assert L == trace[k]
+        x, m, v = ea.adam_step(x, g, m, v, k + 1, ea.lr_at(sched, k))
+    assert np.array_equal(x, hist[1]["theta"])
+    # unit weights in the first loop: Z = M there, thresholds start one loop later
+    hist_u = []
+    sched_u = ea.Schedule(iters=300, round_len=100, irls=True, first_round_unit_weights=True)
+    ea.solve(th0, s.pairs, s.offsets, s.uv, sched_u, history=hist_u)
+    assert [h["tau"] for h in hist_u] == [None, 0.1, 0.05]
+    assert hist_u[0]["Z"] == s.num_matches and hist_u[0]["theta"] is None
+
+
 def test_relative_pose_errors_pin():
     """The pose metric sees a known rotation of one camera and ignores a global
     similarity and the global sign of t."""
@@ -388,6 +460,36 @@ def test_pins_catch_planted_mistakes(tiny_clean, monkeypatch):
     brute = float(np.sum(np.einsum("ma,ab,mb->m", x2, E, x1) ** 2))
     assert not math.isclose(float(E.reshape(9) @ W_bad[0] @ E.reshape(9)), brute, rel_tol=1e-6)
     assert np.linalg.norm(good) > 0
+
+
+def test_irls_pins_catch_planted_mistakes(tiny_outliers, monkeypatch):
+    """Plant slips in the IRLS branch (on the CPU): a threshold that never
+    decays and a filter that keeps every match; the loop records then
+    disagree with the hand count / the printed threshold sequence."""
+    s = tiny_outliers
+    th0 = ea.params_from_poses(s.R_gt, s.t_gt)
+    sched = ea.Schedule(iters=300, round_len=100, irls=True)
+
+    def records():
+        hist = []
+        ea.solve(th0, s.pairs, s.offsets, s.uv, sched, history=hist)
+        return hist
+
+    def hand_ok(hist):
+        taus_ok = [h["tau"] for h in hist] == [0.1, 0.05, 0.025]
+        z_ok = all(h["Z"] == int(np.sum(np.abs(ea.residuals(h["theta"], s.pairs, s.offsets, s.uv)) <= tau))
+                   for h, tau in zip(hist, [0.1, 0.05, 0.025]))
+        return taus_ok and z_ok
+
+    assert hand_ok(records())
+    orig_tau = ea.tau_at
+    monkeypatch.setattr(ea, "tau_at", lambda sc, k: sc.tau0)
+    assert not hand_ok(records())                    # threshold never decays
+    monkeypatch.setattr(ea, "tau_at", orig_tau)
+    orig_w = ea.irls_weights
+    monkeypatch.setattr(ea, "irls_weights", lambda r, d, t: 1.0 / np.maximum(np.abs(r), d))
+    assert not hand_ok(records())                    # no outlier filter
+    monkeypatch.setattr(ea, "irls_weights", orig_w)
 
 
 # ----------------------------------------------------------- learned-weight MLP
