@@ -276,7 +276,8 @@ def tau_at(sched: Schedule, k: int) -> float:
 
 
 def solve(theta0: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.ndarray,
-          sched: Schedule, weights0: np.ndarray | None = None, history: list | None = None):
+          sched: Schedule, weights0: np.ndarray | None = None, history: list | None = None,
+          store=None):
     """Epipolar adjustment: loops of Adam steps on the weighted Gram form, with
     IRLS reweighting and outlier filtering between loops (Sec. 3.3).
 
@@ -284,6 +285,10 @@ def solve(theta0: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.nda
     record per optimisation loop is appended to it: the loop index, the
     filter threshold its weights were computed with (None for unit or given
     weights), the poses they were computed at (None likewise), and Z.
+    `store` (None: float64 throughout) is applied to theta after every Adam
+    step: the precision the parameters are kept in between steps, all
+    arithmetic staying float64 (e.g. rounding to float32 measures how far
+    float32 parameter storage alone moves the solve).
     """
     theta = np.asarray(theta0, dtype=np.float64).copy()
     M = uv.shape[0]
@@ -318,6 +323,8 @@ def solve(theta0: np.ndarray, pairs: np.ndarray, offsets: np.ndarray, uv: np.nda
             t_adam += 1
             theta, m, v = adam_step(theta, g, m, v, t_adam, lr_at(sched, done + s),
                                     sched.beta1, sched.beta2, sched.eps)
+            if store is not None:
+                theta = store(theta)
         done += K
         if sched.irls and done < sched.iters:
             rw_tau, rw_theta = tau_at(sched, k_rw), theta.copy()
