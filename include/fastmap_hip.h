@@ -68,7 +68,8 @@ typedef enum {
   FM_EDTYPE = -3,        /* unsupported dtype                                      */
   FM_EHIP = -4,          /* a HIP runtime call failed                              */
   FM_ENOMEM = -5,        /* device allocation failed                               */
-  FM_ECOOP = -6          /* cooperative launch not possible for this size         */
+  FM_EDEVICE_CHECK = -6, /* fm_check: a kernel of the opt-in check mode flagged data */
+  FM_ECOOP = -7          /* cooperative launch not possible for this size         */
 } fm_status;
 
 typedef enum { FM_F64 = 0, FM_F32 = 1, FM_BF16 = 2 } fm_dtype;
@@ -83,6 +84,47 @@ void fm_destroy(fm_ctx* ctx);
 const char* fm_last_error(const fm_ctx* ctx);
 /* Library build string (host, static storage). */
 const char* fm_version(void);
+
+/* ------------------------------------------------------------------ check mode */
+
+/* Data checks on the device (the conventions above: host-side argument
+ * validation is always on; these look at the data the kernels read).  Off by
+ * default.  While on, the calls below also run small scans whose findings
+ * raise bits in a context-owned device flag:
+ *   FM_CHECK_COORDS      a non-finite match coordinate (fm_build_pair_grams,
+ *                        fm_reweight, fm_reweight_build: one extra pass over
+ *                        the matches);
+ *   FM_CHECK_PARAMS      non-finite pose parameters, or parameters whose
+ *                        Gram-Schmidt or E_n is not finite (the IRLS calls
+ *                        and fm_epipolar_loss_grad at their input poses,
+ *                        fm_epipolar_solve at its final poses);
+ *   FM_CHECK_DEGENERATE  a pair whose relative translation t_ij is 0 or at
+ *                        most 1e-7 of |t_i| + |t_j| (below the resolution of
+ *                        float32 parameters, so its direction is rounding
+ *                        noise), at the same poses; a pair with t_ij exactly
+ *                        0 adds 0 to the loss and gradient and gets r = 0;
+ *   FM_CHECK_LOSS        a non-finite loss or gradient (fm_epipolar_loss_grad's
+ *                        outputs, fm_epipolar_solve's loss trace).
+ * The scans are enqueued on the call's stream after its own kernels, so they
+ * see what the call read and wrote.  The calls still return FM_OK: the flag
+ * is read by fm_check. */
+typedef enum {
+  FM_CHECK_COORDS = 1,
+  FM_CHECK_PARAMS = 2,
+  FM_CHECK_DEGENERATE = 4,
+  FM_CHECK_LOSS = 8
+} fm_check_bits;
+
+/* Turn check mode on (enable != 0) or off.  The first enable allocates the
+ * flag (4 bytes of device memory, freed by fm_destroy) and synchronises the
+ * device. */
+fm_status fm_set_check(fm_ctx* ctx, int enable);
+
+/* Synchronise `stream`, read and clear the flag.  Returns FM_OK if no bit is
+ * set (also when check mode was never enabled), else FM_EDEVICE_CHECK with
+ * the checks named in fm_last_error().  flags (host, may be NULL) receives
+ * the FM_CHECK_* bits that were set. */
+fm_status fm_check(fm_ctx* ctx, fm_stream stream, uint32_t* flags);
 
 /* ------------------------------------------------------------------ scene */
 
@@ -177,7 +219,9 @@ typedef struct {
   int64_t adam_step0;    /* Adam steps already taken on m, v (0 after a reset) */
   int32_t blocks;        /* workgroups (512 threads each) of the persistent
                             kernel (0 = automatic; capped at the co-resident
-                            limit; > 0 also forces the pair-by-pair loop)     */
+                            limit; > 0 also forces the pair-by-pair loop;
+                            < 0 forces the camera-by-camera loop at any size,
+                            automatic grid; fm_epipolar_solve only)          */
 } fm_adam_cfg;
 
 /* K iterations of {loss + gradient (as fm_epipolar_loss_grad), Adam update of
@@ -187,7 +231,8 @@ typedef struct {
  * sums them and steps Adam, grid-wide barriers between the two), or, for
  * graphs below 131,072 pairs when cfg->blocks is 0, camera by camera (one
  * wavefront per camera evaluates each of its pairs, so every pair is
- * evaluated from both ends, and one grid barrier per iteration).  params, m, v [N,9] float32 are
+ * evaluated from both ends, and one grid barrier per iteration; cfg->blocks
+ * < 0 selects this loop at any size).  params, m, v [N,9] float32 are
  * updated in place.  loss_trace [K] double receives L before each update
  * (NULL = not written).  `cfg` is a host pointer. */
 fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* scene, const void* W36, fm_dtype wdtype,
@@ -427,6 +472,24 @@ fm_status fm_mlp_forward(fm_ctx* ctx, int64_t M, const float* feats, const fm_ml
 fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
                           const void* act, const float* dout, fm_mlp_grad* g, fm_stream stream);
 
+/* Change of every pair's relative pose between two parameter sets
+ * params_a, params_b [N,9] float32 (the relative-pose error terms of the
+ * paper's evaluation, Sec. 4.1 metrics; used as the convergence test of the
+ * learned-weight form): with R_ij = R_j R_i^T and t_ij = t_j - R_ij t_i at
+ * each set (Gram-Schmidt and all arithmetic in float64),
+ *   rot_out [P] float32  angle of R_ij^a (R_ij^b)^T in degrees (NULL = not written);
+ *   t_out   [P] float32  angle between t_ij^a and +-t_ij^b in degrees, the
+ *                        smaller of the two signs (the epipolar objective
+ *                        cannot tell t from -t); NULL = not written;
+ *   counts  [2] int64    (device, required) the number of pairs whose
+ *                        rotation change exceeds rot_deg, and whose
+ *                        translation-direction change exceeds t_deg.
+ * A pair with t_ij = 0 at either set has no direction and counts as a
+ * translation change of 90 degrees.  Thresholds must be >= 0. */
+fm_status fm_pose_change(fm_ctx* ctx, fm_scene* scene, const float* params_a, const float* params_b,
+                         float rot_deg, float t_deg, float* rot_out, float* t_out, int64_t* counts,
+                         fm_stream stream);
+
 /* ------------------------------------------------------------------ launch timing */
 
 /* Optional device-time measurement of the library's own launches (for
@@ -441,7 +504,10 @@ fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats, const fm_m
  *   fm_rotation_loss_grad), FM_K_RA_INIT 12 (rotation initialisation),
  *   FM_K_TS_SEARCH 13 (relative-translation grid search), FM_K_FO_PAIR 14 and
  *   FM_K_FO_CAMERA 15 (the two kernels of fm_epipolar_focal_loss_grad),
- *   FM_K_FO_SOLVE 16 (persistent focal loop).
+ *   FM_K_FO_SOLVE 16 (persistent focal loop), FM_K_GRAM_CALL 17 (the whole of
+ *   one fm_build_pair_grams, fm_reweight or fm_reweight_build call: events on
+ *   the call's stream before its first and after its last launch, so the
+ *   interval includes the gaps between its kernels).
  * fm_profile_enable synchronises the device and clears earlier records;
  * fm_profile_read waits for the recorded events and returns the summed
  * elapsed milliseconds and the launch count of one kernel (host outputs). */

@@ -12,14 +12,16 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfastmap_hip.so")
 
-FM_OK, FM_EINVAL, FM_ESHAPE, FM_EDTYPE, FM_EHIP, FM_ENOMEM, FM_ECOOP = 0, -1, -2, -3, -4, -5, -6
+FM_OK, FM_EINVAL, FM_ESHAPE, FM_EDTYPE, FM_EHIP, FM_ENOMEM, FM_EDEVICE_CHECK, FM_ECOOP = 0, -1, -2, -3, -4, -5, -6, -7
 FM_F64, FM_F32, FM_BF16 = 0, 1, 2
 STATUS_NAMES = {0: "FM_OK", -1: "FM_EINVAL", -2: "FM_ESHAPE", -3: "FM_EDTYPE", -4: "FM_EHIP",
-                -5: "FM_ENOMEM", -6: "FM_ECOOP"}
+                -5: "FM_ENOMEM", -6: "FM_EDEVICE_CHECK", -7: "FM_ECOOP"}
+# fm_check_bits
+FM_CHECK_COORDS, FM_CHECK_PARAMS, FM_CHECK_DEGENERATE, FM_CHECK_LOSS = 1, 2, 4, 8
 
 # Every symbol include/fastmap_hip.h declares.
 EXPORTS = [
-    "fm_create", "fm_destroy", "fm_last_error", "fm_version",
+    "fm_create", "fm_destroy", "fm_last_error", "fm_version", "fm_set_check", "fm_check",
     "fm_scene_create", "fm_scene_destroy", "fm_scene_work_items",
     "fm_build_pair_grams", "fm_reweight", "fm_reweight_build",
     "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve", "fm_solve_barrier_failures",
@@ -27,10 +29,10 @@ EXPORTS = [
     "fm_match_features", "fm_mlp_forward", "fm_mlp_backward",
     "fm_translation_directions", "fm_translation_loss_grad", "fm_translation_solve", "fm_translation_merge",
     "fm_rotation_loss_grad", "fm_rotation_solve", "fm_rotation_init", "fm_translation_search",
-    "fm_epipolar_focal_loss_grad", "fm_epipolar_focal_solve", "fm_poses_from_centres",
+    "fm_epipolar_focal_loss_grad", "fm_epipolar_focal_solve", "fm_poses_from_centres", "fm_pose_change",
 ]
 (K_GRAM, K_SOLVE, K_ESSENTIALS, K_FINALIZE, K_PAIR, K_CAMERA, K_TA_SOLVE, K_TA_PAIR, K_TA_CAMERA,
- K_RA_SOLVE, K_RA_PAIR, K_RA_CAMERA, K_RA_INIT, K_TS_SEARCH, K_FO_PAIR, K_FO_CAMERA, K_FO_SOLVE) = range(17)
+ K_RA_SOLVE, K_RA_PAIR, K_RA_CAMERA, K_RA_INIT, K_TS_SEARCH, K_FO_PAIR, K_FO_CAMERA, K_FO_SOLVE, K_GRAM_CALL) = range(18)
 
 
 class FastMapError(RuntimeError):
@@ -68,6 +70,8 @@ _SIGNATURES = {
     "fm_destroy": (None, [_P]),
     "fm_last_error": (ctypes.c_char_p, [_P]),
     "fm_version": (ctypes.c_char_p, []),
+    "fm_set_check": (_S, [_P, _S]),
+    "fm_check": (_S, [_P, _P, ctypes.POINTER(ctypes.c_uint32)]),
     "fm_scene_create": (_S, [_P, _I64, _I64, _I32, _P, _P, _P, _S, _P, ctypes.POINTER(_P)]),
     "fm_scene_destroy": (None, [_P]),
     "fm_scene_work_items": (_I64, [_P]),
@@ -95,6 +99,7 @@ _SIGNATURES = {
     "fm_epipolar_focal_solve": (_S, [_P, _P, _P, _S, _P, _P, _P, _P, _P, _P, _I32, ctypes.POINTER(AdamCfg), _F, _D,
                                      _P, _P, _P]),
     "fm_poses_from_centres": (_S, [_P, _I32, _P, _P, _P, _P]),
+    "fm_pose_change": (_S, [_P, _P, _P, _P, _F, _F, _P, _P, _P, _P]),
 }
 
 _lib = None

@@ -59,6 +59,22 @@ class Context:
             self.lib.fm_destroy(self.handle)
             self.handle = None
 
+    def set_check(self, enable: bool) -> None:
+        """Turn the library's device-side data checks on or off (fm_set_check)."""
+        check(self.handle, self.lib.fm_set_check(self.handle, 1 if enable else 0))
+
+    def check(self) -> int:
+        """Synchronise the current stream and read and clear the device check
+        flag (fm_check).  Returns 0, or raises FastMapError(FM_EDEVICE_CHECK)
+        whose `flags` attribute holds the FM_CHECK_* bits that were set."""
+        f = ctypes.c_uint32(0)
+        rc = self.lib.fm_check(self.handle, _stream(), ctypes.byref(f))
+        if rc != _lib.FM_OK:
+            err = FastMapError(rc, self.lib.fm_last_error(self.handle).decode())
+            err.flags = int(f.value)
+            raise err
+        return 0
+
     def profile(self, enable: bool) -> None:
         """Start (clearing earlier records) or stop launch timing."""
         check(self.handle, self.lib.fm_profile_enable(self.handle, 1 if enable else 0))
@@ -87,17 +103,25 @@ def default_context() -> Context:
     return _default_ctx
 
 
+def release_all() -> None:
+    """Destroy every live scene and the default context now (explicitly, at
+    the end of a program, so that no library call runs inside the
+    interpreter's exit); later calls make a new default context."""
+    global _default_ctx
+    for s in list(_live_scenes):
+        s.close()
+    if _default_ctx is not None:
+        _default_ctx.close()
+        _default_ctx = None
+
+
 @atexit.register
 def _shutdown() -> None:
-    """Release scenes and the default context while the HIP runtime is still
-    up (interpreter teardown order is otherwise unspecified)."""
-    global _default_ctx
+    """Release what release_all() would, if the program did not, while the
+    HIP runtime is still up (interpreter teardown order is otherwise
+    unspecified)."""
     try:
-        for s in list(_live_scenes):
-            s.close()
-        if _default_ctx is not None:
-            _default_ctx.close()
-            _default_ctx = None
+        release_all()
     except Exception:
         pass
 
@@ -147,6 +171,15 @@ class Scene:
         n = ctypes.c_int64(0)
         check(self.ctx.handle, self.ctx.lib.fm_solve_barrier_failures(self.ctx.handle, self.handle, ctypes.byref(n)))
         return int(n.value)
+
+    def require_barriers_ok(self) -> None:
+        """Raise FastMapError if a grid barrier of a persistent launch on this
+        scene timed out since the last query (its results are then invalid);
+        synchronises the device."""
+        failed = self.barrier_failures()
+        if failed:
+            raise FastMapError(_lib.FM_EHIP, f"{failed} grid barrier wait(s) of a persistent launch timed out; "
+                                             "its results are invalid")
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -428,6 +461,23 @@ def translation_search(scene: Scene, W36: torch.Tensor, params: torch.Tensor, ca
         scene.ctx.handle, scene.handle, _ptr(W36), _ptr(params), _ptr(cand), C, _ptr(t_prior), _ptr(t), _ptr(best),
         _ptr(err), _stream()))
     return t, best, err
+
+
+def pose_change(scene: Scene, params_a: torch.Tensor, params_b: torch.Tensor, rot_deg: float, t_deg: float,
+                per_pair: bool = False):
+    """Per-pair relative-pose change between two parameter sets (fm_pose_change):
+    returns (counts [2] int64 device tensor: pairs over rot_deg, pairs over
+    t_deg; rot [P] | None; t [P] | None), angles in degrees."""
+    dev, P = scene.ctx.device, scene.num_pairs
+    _require(params_a, torch.float32, (scene.num_cams, 9), "params_a", dev)
+    _require(params_b, torch.float32, (scene.num_cams, 9), "params_b", dev)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    rot = torch.empty(P, dtype=torch.float32, device=dev) if per_pair else None
+    tr = torch.empty(P, dtype=torch.float32, device=dev) if per_pair else None
+    check(scene.ctx.handle, scene.ctx.lib.fm_pose_change(scene.ctx.handle, scene.handle, _ptr(params_a),
+                                                         _ptr(params_b), float(rot_deg), float(t_deg), _ptr(rot),
+                                                         _ptr(tr), _ptr(counts), _stream()))
+    return counts, rot, tr
 
 
 def poses_from_centres(ctx: Context, params6: torch.Tensor, centres: torch.Tensor) -> torch.Tensor:

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastmap_hip.so")
-SOURCES = ["scene.hip", "gram.hip", "iterate.hip", "mlp.hip", "translation.hip", "rotation.hip", "translation_search.hip", "focal.hip"]
+SOURCES = ["scene.hip", "gram.hip", "iterate.hip", "mlp.hip", "translation.hip", "rotation.hip", "translation_search.hip", "focal.hip", "pose_change.hip"]
 ARCH = "gfx950"
 
 

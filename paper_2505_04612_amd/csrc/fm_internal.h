@@ -11,16 +11,20 @@
 
 #include "fastmap_hip.h"
 
-// Matches per Gram work item: one wavefront of 64 lanes, 16 matches per lane.
+// Matches per feature work item: one wavefront of 64 lanes, 16 matches per lane.
 constexpr int kLanes = 64;
 constexpr int kPerLane = 16;
 constexpr int kChunk = kLanes * kPerLane;
-// Pairs with at most kSmall matches share a wavefront (16 lanes x 16 rows).
-constexpr int kSmall = 16 * kPerLane;
-// Rows per lane of a big Gram work item: 32 for BF16 coordinates (2,048
-// matches per wavefront halves the per-wavefront reduction work where the
-// pass is bound by vector ALU issue), 16 otherwise.
-constexpr int big_rows(int dt) { return dt == FM_BF16 ? 2 * kPerLane : kPerLane; }
+// Rows per lane of a Gram work item, for a wavefront on one chunk of a large
+// pair (64 lanes) and for a wavefront on four small pairs (16 lanes each):
+// 64 for BF16 coordinates (the pass is bound by vector ALU issue there, and
+// longer items spread each wavefront's 36-value reduction over more
+// matches), 16 otherwise (the FP32 pass waits on memory, and more, shorter
+// wavefronts hide that better).
+constexpr int big_rows(int dt) { return dt == FM_BF16 ? 4 * kPerLane : kPerLane; }
+constexpr int group_rows(int dt) { return dt == FM_BF16 ? 4 * kPerLane : kPerLane; }
+// Pairs with at most small_max(dt) matches share a wavefront, four at a time.
+constexpr int small_max(int dt) { return 16 * group_rows(dt); }
 // Wavefronts per block of the Gram kernels.
 constexpr int kGramWaves = 4;
 // Threads per block of the per-pair and per-camera kernels.
@@ -36,8 +40,8 @@ constexpr int kKeptSlots = 256;
 enum { FM_K_GRAM = 0, FM_K_SOLVE = 1, FM_K_ESSENTIALS = 2, FM_K_FINALIZE = 3, FM_K_PAIR = 4, FM_K_CAMERA = 5,
        FM_K_TA_SOLVE = 6, FM_K_TA_PAIR = 7, FM_K_TA_CAMERA = 8, FM_K_RA_SOLVE = 9, FM_K_RA_PAIR = 10,
        FM_K_RA_CAMERA = 11, FM_K_RA_INIT = 12, FM_K_TS_SEARCH = 13, FM_K_FO_PAIR = 14, FM_K_FO_CAMERA = 15,
-       FM_K_FO_SOLVE = 16,
-       FM_K_COUNT = 17 };
+       FM_K_FO_SOLVE = 16, FM_K_GRAM_CALL = 17,
+       FM_K_COUNT = 18 };
 
 struct fm_timing {
   int kernel;
@@ -53,6 +57,8 @@ struct fm_ctx {
   std::vector<hipEvent_t> event_pool;
   void* ws = nullptr;                // grow-only workspace (MLP gradient slots)
   size_t ws_bytes = 0;
+  bool check = false;                // opt-in device-side data checks (fm_set_check)
+  unsigned* check_flag = nullptr;    // [1] device: FM_CHECK_* bits raised since the last fm_check
 };
 
 // Timing of one kernel launch when profiling is on.  By default the two
@@ -82,17 +88,17 @@ struct fm_scene {
   int64_t* wi_off = nullptr;      // [P+1] first work item of each pair
   int32_t* wi_pair = nullptr;     // [n_wi] pair of each work item
   // Gram pass plan (built at set-up)
-  int64_t n_big = 0;              // chunk work items of pairs with more than kSmall matches
+  int64_t n_big = 0;              // chunk work items of pairs with more than small_max(dtype) matches
   int32_t* big_pair = nullptr;    // [n_big] pair of each chunk
   int32_t* big_chunk = nullptr;   // [n_big] chunk index within its pair
   int32_t* big_slot = nullptr;    // [n_big] partial slot of the chunk (-1: the chunk is its whole pair)
   int64_t chunk = kChunk;         // matches per big work item (kLanes * big_rows(dtype))
   int64_t n_partials = 0;         // chunk partials of pairs spanning several chunks
-  int64_t n_groups = 0;           // wavefronts of four pairs with 1..kSmall matches
+  int64_t n_groups = 0;           // wavefronts of four pairs with 0..small_max(dtype) matches
   int32_t* groups = nullptr;      // [4 n_groups] pair ids (-1: none)
   int64_t n_multi = 0;            // pairs spanning more than one chunk
-  int64_t n_empty = 0;            // pairs without matches
-  int32_t* multi = nullptr;       // [n_multi + n_empty]: those pairs, then the empty ones
+  int64_t n_empty = 0;            // pairs without matches (in groups, zero rows)
+  int32_t* multi = nullptr;       // [n_multi] pairs spanning several chunks
   int64_t* multi_first = nullptr; // [n_multi] first partial slot of each multi pair
   unsigned long long* kept_slots = nullptr;  // [kKeptSlots * 16] kept-match counters, one per 128-B line
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
@@ -106,8 +112,7 @@ struct fm_scene {
   double* rot = nullptr;          // [2, N, 9] rotations of the current poses (fused solve; two buffers)
   float* params_alt = nullptr;    // [N, 10] second parameter buffer of the camera loops ([N, 9] poses, then [N] focal scales)
   int64_t loss_part_cap = 0;
-  unsigned* bar = nullptr;        // [128] solve grid barrier, one 128-B line each: arrival count, generation,
-                                  // failure flag of the running launch, failure total since the last query
+  unsigned* bar = nullptr;        // [kBarWords] grid barrier of the persistent loops (layout at grid_barrier)
   int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
   // translation averaging workspace, grown on demand by the translation calls
   int32_t ta_runs_cap = 0;        // runs the workspace holds
@@ -124,6 +129,14 @@ struct fm_scene {
   double* lz = nullptr;           // basis [m+1, 3N], work vector, dots, tridiagonal, Ritz coefficients
   int lz_coop_blocks = 0;         // max co-resident blocks of the Lanczos kernel
 };
+
+// Check mode: scans n float32 (f64 = false) or float64 values at p for a
+// non-finite one and raises `bit` in ctx->check_flag (no-op when check mode
+// is off).
+fm_status fm_check_finite(fm_ctx* ctx, hipStream_t st, const void* p, int64_t n, bool f64, unsigned bit);
+// E_n of every pair at `params` into the scene's workspace (gram.hip); in
+// check mode it also flags degenerate pairs and non-finite parameters.
+fm_status fm_launch_essentials(fm_scene* s, const float* params, hipStream_t st);
 
 // Error reporting helpers: set ctx->err and return the status.
 fm_status fm_fail(fm_ctx* ctx, fm_status st, const char* fmt, ...);
@@ -429,16 +442,6 @@ __device__ inline float adam_update(float p, float g, float& m, float& v, double
   return (float)((double)p - lr * (md / bc1) / (sqrt(vd / bc2) + eps));
 }
 
-// Grid barrier of the persistent solves (epipolar and translation loops).
-// Thread 0 of each workgroup makes the workgroup's writes visible
-// (agent-scope release), counts itself in, and waits for the generation word
-// to move; the last to arrive acquires the others' writes, re-arms the
-// counter and moves the generation.  All atomics are relaxed and
-// agent-scoped; the fences carry the ordering.  The wait is bounded: if it
-// expires (the workgroups were not all resident), the launch's failure flag
-// and the scene's failure total are raised, every later barrier of the
-// launch returns at once and the host reads the total with
-// fm_solve_barrier_failures.
 // Pair count below which the epipolar persistent loop runs camera by camera
 // when the caller leaves the grid automatic (the translation and rotation
 // loops, whose pair terms are cheaper, always do): one wavefront
@@ -453,6 +456,20 @@ __device__ inline float adam_update(float p, float g, float& m, float& v, double
 constexpr int64_t kCamLoopMaxPairs = 131072;
 
 constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
+// Words of `bar`: arrival count, generation, failure flag of the running
+// launch, failure total since the last query, one 128-byte line each.
+constexpr int kBarWords = 128;
+
+// Grid barrier of the persistent solves (epipolar and translation loops).
+// Thread 0 of each workgroup makes the workgroup's writes visible
+// (agent-scope release), counts itself in, and waits for the generation word
+// to move; the last to arrive acquires the others' writes, re-arms the
+// counter and moves the generation.  All atomics are relaxed and
+// agent-scoped; the fences carry the ordering.  The wait is bounded: if it
+// expires (the workgroups were not all resident), the launch's failure flag
+// and the scene's failure total are raised, every later barrier of the
+// launch returns at once and the host reads the total with
+// fm_solve_barrier_failures.
 
 __device__ inline void grid_barrier(unsigned* __restrict__ bar) {
   unsigned* count = bar;

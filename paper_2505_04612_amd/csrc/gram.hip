@@ -1,17 +1,20 @@
 // Per-pair Gram build (App. B.6) and IRLS reweighting (Sec. 3.3).
 //
 // The M matches are streamed once.  A work item is either a chunk of up to
-// 1024 (BF16: 2048) consecutive matches of one pair, processed by a whole
+// 1024 (BF16: 4096) consecutive matches of one pair, processed by a whole
 // wavefront (lane l takes matches start + l + 64 r, so every load
 // instruction of the wave reads one contiguous span), or four pairs of at
-// most 256 matches, 16 lanes each.  Each lane forms the monomials
-// p = (u^2, uv, v^2, u, v, 1) of both points and accumulates the 36 sums
-// omega p2[q2] p1[q1] in float32 registers; a reduce-scatter across the
-// lanes of the pair (DPP and lane permutes: 38 exchanges instead of 36 full
-// reductions over a wavefront) leaves one entry per lane.  A pair that one
-// work item covers stores its Gram directly; larger pairs leave chunk
-// partials that a second kernel adds in float64, in chunk order, so the
+// most 256 (BF16: 1024) matches, 16 lanes each.  Each lane forms the
+// monomials p = (u^2, uv, v^2, u, v, 1) of both points and accumulates the
+// 36 sums omega p2[q2] p1[q1] in float32 registers; a reduce-scatter across
+// the lanes of the pair (DPP and lane permutes: 38 exchanges instead of 36
+// full reductions over a wavefront) leaves one entry per lane.  A pair that
+// one work item covers stores its Gram directly; the chunks of a larger pair
+// leave partials that a second kernel adds in float64, in chunk order, so the
 // result does not depend on scheduling: no atomics touch floating point.
+// (Adding them in the pass itself, by whichever chunk of a pair finishes
+// last, needs an agent-scope release per chunk, and on this GPU each such
+// release writes back the whole L2 of the chunk's XCD: measured 5-6x slower.)
 #include "fm_internal.h"
 
 enum { W_UNIT = 0, W_ARRAY = 1, W_IRLS = 2 };
@@ -233,31 +236,32 @@ __device__ inline void row_reduce_scatter36(const float (&a)[36], int lane, floa
 // The Gram pass (work items in dispatch order, longest first, so the
 // wavefronts that wait for a free slot are the short ones).  Work item
 // w < n_big: one wavefront on chunk big_chunk[w] (<= 64 big_rows(DT)
-// matches: 1024, or 2048 for BF16; lanes strided so each load instruction
-// reads one contiguous span)
-// of a pair with more than kSmall matches.  Work item w >= n_big: one
-// wavefront on four pairs of at most kSmall matches, 16 lanes each (groups
-// of pairs with equal row counts, built at set-up).  Each pair's sums are
+// matches: 1024, or 4096 for BF16; lanes strided so each load instruction
+// reads one contiguous span) of a pair with more than small_max(DT) matches.
+// Work item w >= n_big: one wavefront on four pairs of at most small_max(DT)
+// matches, 16 lanes each (groups of pairs with equal row counts, built at
+// set-up; a pair without matches stores zeros).  Each pair's sums are
 // reduced over its lanes in a fixed order; a pair whose matches one
 // wavefront covered stores its Gram directly (float64 of the float32 sum),
 // the others leave chunk partials (slot big_slot[w]) for k_gram_finalize.
+// An IRLS pass adds its wavefronts' kept-match counts into kept_slots.
 template <int DT, int WMODE, bool BUILD, bool WRITE>
 __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
     const void* __restrict__ uv, const int64_t* __restrict__ off, const int32_t* __restrict__ big_pair,
-    const int32_t* __restrict__ big_chunk, const int32_t* __restrict__ big_slot, int64_t n_big,
-    const int32_t* __restrict__ groups, int64_t n_groups,
-    const float* __restrict__ weights, const double* __restrict__ ess, double delta, double tau,
+    const int32_t* __restrict__ big_chunk, const int32_t* __restrict__ big_slot,
+    int64_t n_big, const int32_t* __restrict__ groups, int64_t n_groups, const float* __restrict__ weights, const double* __restrict__ ess, double delta, double tau,
     float* __restrict__ partials, double* __restrict__ W64, float* __restrict__ W32, float* __restrict__ w_out,
     float* __restrict__ r_out, unsigned long long* __restrict__ kept_slots) {
   // rows loaded per batch (measured on the medium scene, FP32: 1 row
   // 13.6-13.9 us, 2 rows 14.4-14.9, 4 rows 15.6, 8 rows 17.0; BF16 is bound
-  // by vector ALU issue and loads all 16 rows of a batch at once)
+  // by vector ALU issue and loads 16 rows of a batch at once)
   constexpr int kBatch = (DT == FM_F64) ? 4 : (DT == FM_F32 ? 1 : kPerLane);
   const int lane = threadIdx.x & (kLanes - 1);
   // wave-uniform work item (scalar registers: the big path's pair data and
   // E_n are then scalar loads)
   const int64_t w = (int64_t)blockIdx.x * kGramWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= n_big + n_groups) return;  // whole wavefront
+  const int64_t items = n_big + n_groups;
+  if (w >= items) return;  // whole wavefront
   const float fdelta = (float)delta;
   float acc[36];
 #pragma unroll
@@ -281,8 +285,8 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
       }
     }
     stream_rows<DT, WMODE, BUILD, WRITE, kLanes, kBatch, kRows>(uv, start, count, lane, (count + kLanes - 1) / kLanes,
-                                                         count / kLanes, E, fdelta, tau, weights, w_out, r_out, acc,
-                                                         nkept);
+                                                               count / kLanes, E, fdelta, tau, weights, w_out, r_out,
+                                                               acc, nkept);
     if constexpr (BUILD) {
       int slot;
       const float v = wave_reduce_scatter36(acc, lane, slot);
@@ -296,24 +300,28 @@ __global__ __launch_bounds__(kGramWaves * kLanes) void k_gram_pass(
       }
     }
   } else {
+    constexpr int kGRows = group_rows(DT);
     const int l16 = lane & 15;
     const int64_t n = groups[(w - n_big) * 4 + (lane >> 4)];
     const bool have = n >= 0;
     const int64_t start = have ? off[n] : 0;
     const int count = have ? (int)(off[n + 1] - start) : 0;
     // the four pairs of a group have the same row count; rows before the
-    // last are full unless a pair slot is empty
+    // last are full unless a pair slot is unused; a group of pairs without
+    // matches has no rows
     int nrows = (count + 15) >> 4;
     nrows = max(nrows, __shfl_xor(nrows, 16));
     nrows = max(nrows, __shfl_xor(nrows, 32));
     nrows = __builtin_amdgcn_readfirstlane(nrows);
-    const int nfull = (__ballot(!have) == 0ull) ? nrows - 1 : 0;
-    if constexpr (WMODE == W_IRLS) {
+    if (nrows > 0) {
+      const int nfull = (__ballot(!have) == 0ull) ? nrows - 1 : 0;
+      if constexpr (WMODE == W_IRLS) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) E[k] = have ? ess[n * 9 + k] : 0.0;
+        for (int k = 0; k < 9; ++k) E[k] = have ? ess[n * 9 + k] : 0.0;
+      }
+      stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch, kGRows>(uv, start, count, l16, nrows, nfull, E, fdelta, tau,
+                                                              weights, w_out, r_out, acc, nkept);
     }
-    stream_rows<DT, WMODE, BUILD, WRITE, 16, kBatch, kPerLane>(uv, start, count, l16, nrows, nfull, E, fdelta, tau, weights,
-                                                     w_out, r_out, acc, nkept);
     if constexpr (BUILD) {
       float v[3];
       row_reduce_scatter36(acc, lane, v);
@@ -357,34 +365,21 @@ __device__ inline void sum_kept(unsigned long long* __restrict__ kept_slots, int
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_kept(unsigned long long* __restrict__ kept_slots,
-                                                       int64_t* __restrict__ kept) {
-  sum_kept(kept_slots, kept);
-}
-
 // Gram of every pair that spans several work items: the sum of its chunk
-// partials (chunks of `chunk` matches) in float64, in chunk order (the other pairs with matches were
-// written by the pass itself, pairs without matches are zeroed here).
-// Block 0 also totals the kept counts of an IRLS pass (kept != NULL).
+// partials (chunks of `chunk` matches) in float64, in chunk order (the other
+// pairs, empty ones included, were written by the pass itself).  Block 0
+// also totals the kept counts of an IRLS pass (kept != NULL).
 __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restrict__ partials,
                                                           const int64_t* __restrict__ off,
                                                           const int32_t* __restrict__ multi,
                                                           const int64_t* __restrict__ multi_first, int64_t n_multi,
-                                                          const int32_t* __restrict__ empty, int64_t n_empty,
                                                           int64_t chunk, double* __restrict__ W64,
                                                           float* __restrict__ W32,
                                                           unsigned long long* __restrict__ kept_slots,
                                                           int64_t* __restrict__ kept) {
   if (kept && blockIdx.x == 0) sum_kept(kept_slots, kept);
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (n_multi + n_empty) * 36) return;
-  if (t >= n_multi * 36) {
-    t -= n_multi * 36;
-    const int64_t e = empty[t / 36] * (int64_t)36 + t % 36;
-    if (W64) W64[e] = 0.0;
-    if (W32) W32[e] = 0.0f;
-    return;
-  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_multi * 36) return;
   const int64_t i = t / 36;
   const int64_t n = multi[i];
   const int k = (int)(t % 36);
@@ -395,9 +390,28 @@ __global__ __launch_bounds__(kBlock) void k_gram_finalize(const float* __restric
   if (W32) W32[n * 36 + k] = (float)s;
 }
 
+// Check mode: flags a non-finite coordinate among the stored matches.
+template <int DT>
+__global__ __launch_bounds__(kBlock) void k_check_coords(const void* __restrict__ uv, int64_t M,
+                                                         unsigned* __restrict__ flag) {
+  using RawT = typename RawMatch<DT>::T;
+  bool bad = false;
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+    float4 f;
+    double x[4];
+    unpack<DT>(load_raw<DT>(reinterpret_cast<const RawT*>(uv) + m), f, x);
+    bad = bad || !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(x[3]));
+  }
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, FM_CHECK_COORDS);
+}
+
 // E_n for every pair at the given poses (float64), for the residual pass.
+// In check mode (flag != NULL) a pair whose |t_ij| is at most 1e-7 of
+// |t_i| + |t_j| (below the resolution of float32 parameters, so its direction
+// is rounding noise; exactly 0 included) or whose E_n is not finite (from
+// non-finite parameters) is flagged.
 __global__ void k_pair_essentials(const float* __restrict__ params, const int32_t* __restrict__ cams,
-                                  int64_t P, double* __restrict__ ess) {
+                                  int64_t P, double* __restrict__ ess, unsigned* __restrict__ flag) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= P) return;
   double a1[3], a2[3], ti[3], tj[3];
@@ -406,7 +420,17 @@ __global__ void k_pair_essentials(const float* __restrict__ params, const int32_
   gs_matrix(gs_forward(a1, a2), Ri);
   load_pose(params, cams[2 * n + 1], a1, a2, tj);
   gs_matrix(gs_forward(a1, a2), Rj);
-  pair_essential(Ri, ti, Rj, tj, Rij, th, E);
+  const double ns = pair_essential(Ri, ti, Rj, tj, Rij, th, E);
+  if (flag) {
+    const double tn = sqrt(ti[0] * ti[0] + ti[1] * ti[1] + ti[2] * ti[2]) +
+                      sqrt(tj[0] * tj[0] + tj[1] * tj[1] + tj[2] * tj[2]);
+    unsigned bits = ns <= 1e-7 * tn ? FM_CHECK_DEGENERATE : 0u;
+    bool fin = isfinite(ns);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) fin = fin && isfinite(E[a][b]);
+    if (!fin) bits |= FM_CHECK_PARAMS;
+    if (bits) atomicOr(flag, bits);
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -416,16 +440,15 @@ __global__ void k_pair_essentials(const float* __restrict__ params, const int32_
 // ------------------------------------------------------------------ host side
 
 template <int WMODE, bool BUILD, bool WRITE>
-static fm_status launch_partial(fm_scene* s, const float* weights, double delta, double tau, double* W64,
-                                float* W32, float* w_out, float* r_out, hipStream_t st) {
+static fm_status launch_pass(fm_scene* s, const float* weights, double delta, double tau, double* W64,
+                             float* W32, float* w_out, float* r_out, hipStream_t st) {
   const int64_t items = s->n_big + s->n_groups;
   if (items == 0) return FM_OK;
   const dim3 grid(grid_for(items, kGramWaves)), block(kGramWaves * kLanes);
   fm_timed timer(s->ctx, FM_K_GRAM, st, true);
 #define FM_GRAM_ARGS                                                                                          \
   s->uv, s->offsets, s->big_pair, s->big_chunk, s->big_slot, s->n_big, s->groups, s->n_groups, weights, s->ess,   \
-      delta, tau,                                                                                             \
-      s->partials, W64, W32, w_out, r_out, s->kept_slots
+      delta, tau, s->partials, W64, W32, w_out, r_out, s->kept_slots
   switch (s->dtype) {
     case FM_F32:
       hipExtLaunchKernelGGL((k_gram_pass<FM_F32, WMODE, BUILD, WRITE>), grid, block, 0, st, timer.a, timer.b, 0,
@@ -445,13 +468,15 @@ static fm_status launch_partial(fm_scene* s, const float* weights, double delta,
   return FM_OK;
 }
 
+// The multi-chunk sums and (with kept) the kept-match total; launched only
+// when there is something to do.
 static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* kept, hipStream_t st) {
-  if (s->n_multi + s->n_empty == 0 && !kept) return FM_OK;
+  if (s->n_multi == 0 && !kept) return FM_OK;
   fm_timed timer(s->ctx, FM_K_FINALIZE, st, true);
-  const int64_t nthreads = (s->n_multi + s->n_empty) * 36 > 0 ? (s->n_multi + s->n_empty) * 36 : 1;
+  const int64_t nthreads = s->n_multi * 36 > 0 ? s->n_multi * 36 : 1;
   hipExtLaunchKernelGGL(k_gram_finalize, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, st, timer.a, timer.b, 0,
-                        s->partials, s->offsets, s->multi, s->multi_first, s->n_multi, s->multi + s->n_multi,
-                        s->n_empty, s->chunk, W64, W32, s->kept_slots, kept);
+                        s->partials, s->offsets, s->multi, s->multi_first, s->n_multi, s->chunk, W64, W32,
+                        s->kept_slots, kept);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
@@ -459,13 +484,34 @@ static fm_status launch_finalize(fm_scene* s, double* W64, float* W32, int64_t* 
 static fm_status launch_essentials(fm_scene* s, const float* params, hipStream_t st) {
   fm_timed timer(s->ctx, FM_K_ESSENTIALS, st, true);
   hipExtLaunchKernelGGL(k_pair_essentials, dim3(grid_for(s->P > 0 ? s->P : 1, kBlock)), dim3(kBlock), 0, st, timer.a,
-                        timer.b, 0, params, (const int32_t*)s->pair_cams, s->P, s->ess);
+                        timer.b, 0, params, (const int32_t*)s->pair_cams, s->P, s->ess,
+                        s->ctx->check ? s->ctx->check_flag : nullptr);
   FM_CHECK_LAUNCH(s->ctx);
   return FM_OK;
 }
 
 fm_status fm_launch_essentials(fm_scene* s, const float* params, hipStream_t st) {
   return launch_essentials(s, params, st);
+}
+
+// Check mode: one extra pass over the stored coordinates.
+static fm_status launch_check_coords(fm_scene* s, hipStream_t st) {
+  if (!s->ctx->check || s->M == 0) return FM_OK;
+  const int64_t want = grid_for(s->M, kBlock);
+  const dim3 grid((unsigned)(want < 4096 ? want : 4096)), block(kBlock);
+  switch (s->dtype) {
+    case FM_F32:
+      hipLaunchKernelGGL(k_check_coords<FM_F32>, grid, block, 0, st, s->uv, s->M, s->ctx->check_flag);
+      break;
+    case FM_BF16:
+      hipLaunchKernelGGL(k_check_coords<FM_BF16>, grid, block, 0, st, s->uv, s->M, s->ctx->check_flag);
+      break;
+    default:
+      hipLaunchKernelGGL(k_check_coords<FM_F64>, grid, block, 0, st, s->uv, s->M, s->ctx->check_flag);
+      break;
+  }
+  FM_CHECK_LAUNCH(s->ctx);
+  return FM_OK;
 }
 
 static fm_status check_scene(fm_ctx* ctx, fm_scene* s, const char* fn) {
@@ -482,8 +528,10 @@ extern "C" fm_status fm_build_pair_grams(fm_ctx* ctx, fm_scene* s, const float* 
   if (rc != FM_OK) return rc;
   if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_build_pair_grams: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
-  rc = weights ? launch_partial<W_ARRAY, true, false>(s, weights, 0, 0, W64, W32, nullptr, nullptr, st)
-               : launch_partial<W_UNIT, true, false>(s, nullptr, 0, 0, W64, W32, nullptr, nullptr, st);
+  if ((rc = launch_check_coords(s, st)) != FM_OK) return rc;
+  fm_timed call(ctx, FM_K_GRAM_CALL, st);
+  rc = weights ? launch_pass<W_ARRAY, true, false>(s, weights, 0, 0, W64, W32, nullptr, nullptr, st)
+               : launch_pass<W_UNIT, true, false>(s, nullptr, 0, 0, W64, W32, nullptr, nullptr, st);
   if (rc != FM_OK) return rc;
   return launch_finalize(s, W64, W32, nullptr, st);
 }
@@ -503,13 +551,12 @@ extern "C" fm_status fm_reweight(fm_ctx* ctx, fm_scene* s, const float* params, 
   if ((rc = check_irls_args(ctx, "fm_reweight", params, delta, tau, kept)) != FM_OK) return rc;
   if (!w_out && s->M > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight: weights_out is NULL");
   hipStream_t st = (hipStream_t)stream;
+  if ((rc = launch_check_coords(s, st)) != FM_OK) return rc;
+  fm_timed call(ctx, FM_K_GRAM_CALL, st);
   if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
-  if ((rc = launch_partial<W_IRLS, false, true>(s, nullptr, delta, tau, nullptr, nullptr, w_out, r_out, st)) !=
-      FM_OK)
+  if ((rc = launch_pass<W_IRLS, false, true>(s, nullptr, delta, tau, nullptr, nullptr, w_out, r_out, st)) != FM_OK)
     return rc;
-  hipLaunchKernelGGL(k_count_kept, dim3(1), dim3(kBlock), 0, st, s->kept_slots, kept);
-  FM_CHECK_LAUNCH(ctx);
-  return FM_OK;
+  return launch_finalize(s, nullptr, nullptr, kept, st);
 }
 
 extern "C" fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* s, const float* params, float delta, float tau,
@@ -519,8 +566,10 @@ extern "C" fm_status fm_reweight_build(fm_ctx* ctx, fm_scene* s, const float* pa
   if ((rc = check_irls_args(ctx, "fm_reweight_build", params, delta, tau, kept)) != FM_OK) return rc;
   if (!W64 && !W32 && s->P > 0) return fm_fail(ctx, FM_EINVAL, "fm_reweight_build: both outputs are NULL");
   hipStream_t st = (hipStream_t)stream;
+  if ((rc = launch_check_coords(s, st)) != FM_OK) return rc;
+  fm_timed call(ctx, FM_K_GRAM_CALL, st);
   if ((rc = launch_essentials(s, params, st)) != FM_OK) return rc;
-  if ((rc = launch_partial<W_IRLS, true, false>(s, nullptr, delta, tau, W64, W32, nullptr, nullptr, st)) != FM_OK)
+  if ((rc = launch_pass<W_IRLS, true, false>(s, nullptr, delta, tau, W64, W32, nullptr, nullptr, st)) != FM_OK)
     return rc;
   return launch_finalize(s, W64, W32, kept, st);
 }

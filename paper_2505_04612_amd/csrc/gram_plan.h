@@ -4,15 +4,16 @@
 //
 // A pair with more than `small` matches is cut into chunks of lanes * rows
 // matches (one wavefront each: lane l takes matches l + lanes r of the
-// chunk); a pair with 1..small matches is bucketed by its number of
+// chunk); a pair with 0..small matches is bucketed by its number of
 // 16-match rows and packed four to a wavefront (16 lanes each; the last
-// group of a bucket is padded with -1).  Chunks are ordered by row count,
-// longest first, and so are the groups, so that the work items still waiting
-// for a free slot at the end of the pass are short ones.  A pair that spans
-// several chunks gets one partial slot per chunk (consecutive, in chunk
-// order); the finalize step adds them.  Which wavefront runs an item does not
-// change a pair's result (each pair's sums use a fixed lane/row assignment
-// and reduction order).
+// group of a bucket is padded with -1; a pair without matches is a group
+// slot of zero rows, which writes its zero Gram).  Chunks are ordered by row
+// count, longest first, and so are the groups, so that the work items still
+// waiting for a free slot at the end of the pass are short ones.  A pair
+// that spans several chunks gets one partial slot per chunk (consecutive, in
+// chunk order) and an arrival counter; the chunk that arrives last adds the
+// partials.  Which wavefront runs an item does not change a pair's result
+// (each pair's sums use a fixed lane/row assignment and reduction order).
 #pragma once
 
 #include <algorithm>
@@ -20,10 +21,11 @@
 #include <vector>
 
 struct GramPlan {
-  std::vector<int32_t> big_pair, big_chunk, big_slot;  // chunk work items (slot -1: the chunk is its whole pair)
-  std::vector<int32_t> groups;                          // [4 n_groups] pair ids, -1 = empty slot
-  std::vector<int32_t> multi;                           // pairs spanning several chunks, then the empty pairs
-  std::vector<int64_t> multi_first;                     // first partial slot of each multi-chunk pair
+  std::vector<int32_t> big_pair, big_chunk;  // chunk work items: pair, chunk index within the pair
+  std::vector<int32_t> big_slot;             // partial slot of the chunk (-1: the chunk is its whole pair)
+  std::vector<int32_t> groups;               // [4 n_groups] pair ids, -1 = unused slot
+  std::vector<int32_t> multi;                // pairs spanning several chunks
+  std::vector<int64_t> multi_first;          // first partial slot of each multi-chunk pair
   int64_t n_multi = 0, n_empty = 0, n_partials = 0;
 };
 
@@ -35,13 +37,11 @@ inline GramPlan make_gram_plan(const int64_t* off, int64_t P, int64_t lanes, int
   const int64_t max_group_rows = (small + 15) / 16;
   GramPlan g;
   std::vector<Chunk> chunks;
-  std::vector<int32_t> empty;
   std::vector<std::vector<int32_t>> bucket(max_group_rows + 1);
   for (int64_t n = 0; n < P; ++n) {
     const int64_t c = off[n + 1] - off[n];
-    if (c == 0) {
-      empty.push_back((int32_t)n);
-    } else if (c <= small) {
+    if (c <= small) {
+      if (c == 0) ++g.n_empty;
       bucket[(c + 15) / 16].push_back((int32_t)n);
     } else {
       const int64_t nch = (c + chunk - 1) / chunk;
@@ -63,12 +63,10 @@ inline GramPlan make_gram_plan(const int64_t* off, int64_t P, int64_t lanes, int
     g.big_chunk.push_back(ch.chunk);
     g.big_slot.push_back(ch.slot);
   }
-  for (int64_t r = max_group_rows; r >= 1; --r) {
+  for (int64_t r = max_group_rows; r >= 0; --r) {
     for (int32_t n : bucket[r]) g.groups.push_back(n);
     while (g.groups.size() % 4) g.groups.push_back(-1);
   }
   g.n_multi = (int64_t)g.multi.size();
-  g.n_empty = (int64_t)empty.size();
-  g.multi.insert(g.multi.end(), empty.begin(), empty.end());
   return g;
 }

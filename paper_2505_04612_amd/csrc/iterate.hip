@@ -217,10 +217,19 @@ extern "C" fm_status fm_epipolar_loss_grad(fm_ctx* ctx, fm_scene* s, const void*
   }
   FM_CHECK_LAUNCH(ctx);
   const unsigned gc = grid_for((int64_t)(s->N > 0 ? s->N : 1) * 64, kBlock);
+  {
   fm_timed timer(ctx, FM_K_CAMERA, st);
   hipLaunchKernelGGL(k_camera_grad, dim3(gc), dim3(kBlock), 0, st, params, s->cam_ptr, s->cam_items, s->contrib,
                      s->N, s->loss_part, (int64_t)gp, inv_Z, Z_dev, grad, loss);
+  }
   FM_CHECK_LAUNCH(ctx);
+  if (ctx->check) {
+    // degenerate pairs and non-finite parameters at the input poses, then
+    // the outputs themselves
+    if ((rc = fm_launch_essentials(s, params, st)) != FM_OK) return rc;
+    if ((rc = fm_check_finite(ctx, st, loss, 1, true, FM_CHECK_LOSS)) != FM_OK) return rc;
+    if ((rc = fm_check_finite(ctx, st, grad, (int64_t)s->N * 9, false, FM_CHECK_LOSS)) != FM_OK) return rc;
+  }
   return FM_OK;
 }
 
@@ -444,6 +453,21 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
   const int kq = lane < 9 ? lane : 8;
   const WT* W36 = reinterpret_cast<const WT*>(a.W36);
   const int64_t NR = (int64_t)a.N * 9;
+  // static data of the first 64 incidence entries of this wavefront's first
+  // camera (one per lane: the pair, the camera's side, both cameras), read
+  // once, so that each iteration's loads of that pass (poses, rotations,
+  // Gram) all depend on registers only and are in flight together
+  int n0 = -1, side0 = 0, ci0 = 0, cj0 = 0;
+  if (gwave < a.N) {
+    const int lo = a.cam_ptr[gwave], hi = a.cam_ptr[gwave + 1];
+    if (lo + lane < hi) {
+      const int item = a.cam_items[lo + lane];
+      n0 = item >> 1;
+      side0 = item & 1;
+      ci0 = a.cams[2 * n0];
+      cj0 = a.cams[2 * n0 + 1];
+    }
+  }
   // rotations of the initial parameters (buffer 0)
   for (int64_t c = gwave; c < a.N; c += nwaves) {
     const float p0 = a.params[c * 9 + kq];
@@ -471,11 +495,13 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
 #pragma unroll
       for (int j = 0; j < 12; ++j) acc[j] = 0.0;
       for (int q = lo + lane; q < hi; q += 64) {
-        const int item = a.cam_items[q];
-        const int64_t n = item >> 1;
-        const int side = item & 1;
+        const bool first = c == gwave && q == lo + lane;
+        const int item = first ? 0 : a.cam_items[q];
+        const int64_t n = first ? n0 : item >> 1;
+        const int side = first ? side0 : item & 1;
+        const int ci = first ? ci0 : a.cams[2 * n], cj = first ? cj0 : a.cams[2 * n + 1];
         float rec[24];
-        const double l = pair_loss_adjoint(pr, rr, a.cams[2 * n], a.cams[2 * n + 1], W36, n, 2.0 * iz, rec);
+        const double l = pair_loss_adjoint(pr, rr, ci, cj, W36, n, 2.0 * iz, rec);
         if (side == 0) lsum += l;   // each pair's loss once, from its first camera
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);
@@ -513,6 +539,17 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
     for (int64_t c = gwave; c < a.N; c += nwaves)
       if (lane < 9) a.params[c * 9 + lane] = a.params_alt[c * 9 + lane];
   }
+}
+
+// Check mode after a fused solve: the final parameters and the loss trace
+// finite, and no degenerate pair at the final poses.
+static fm_status solve_checks(fm_ctx* ctx, fm_scene* s, const float* params, const double* loss_trace, int32_t K,
+                              hipStream_t st) {
+  if (!ctx->check) return FM_OK;
+  fm_status rc = fm_check_finite(ctx, st, params, (int64_t)s->N * 9, false, FM_CHECK_PARAMS);
+  if (rc == FM_OK) rc = fm_check_finite(ctx, st, loss_trace, K, true, FM_CHECK_LOSS);
+  if (rc == FM_OK) rc = fm_launch_essentials(s, params, st);
+  return rc;
 }
 
 int fm_solve_coop_blocks(fm_ctx* ctx) {
@@ -571,12 +608,12 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   void* args[] = {&a};
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, s->bar);
   FM_CHECK_LAUNCH(ctx);
-  // automatic grid below kCamLoopMaxPairs: the camera-centric loop, one
-  // barrier per iteration; a forced workgroup count or a larger graph runs
-  // the pair loop
+  // automatic grid below kCamLoopMaxPairs, or cfg->blocks < 0: the
+  // camera-centric loop, one barrier per iteration; a forced workgroup count
+  // or a larger graph runs the pair loop
   int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
   if (want_cam > s->coop_blocks) want_cam = s->coop_blocks;
-  if (cfg->blocks <= 0 && s->P < kCamLoopMaxPairs && 2 * want_cam <= s->loss_part_cap) {
+  if ((cfg->blocks < 0 || (cfg->blocks == 0 && s->P < kCamLoopMaxPairs)) && 2 * want_cam <= s->loss_part_cap) {
     CamSolveArgs ca;
     ca.params = params; ca.params_alt = s->params_alt; ca.m = m; ca.v = v;
     ca.cams = s->pair_cams; ca.W36 = W36; ca.cam_ptr = s->cam_ptr; ca.cam_items = s->cam_items;
@@ -586,6 +623,7 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
     ca.b1 = a.b1; ca.b2 = a.b2; ca.eps = a.eps;
     ca.lr_step0 = a.lr_step0; ca.lr_total = a.lr_total; ca.adam_step0 = a.adam_step0;
     void* cargs[] = {&ca};
+    {
     fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
     hipError_t e = wdt == FM_F64
                        ? hipLaunchCooperativeKernel((const void*)k_solve_cam<double>, dim3((unsigned)want_cam),
@@ -593,15 +631,18 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
                        : hipLaunchCooperativeKernel((const void*)k_solve_cam<float>, dim3((unsigned)want_cam),
                                                     dim3(kSolveBlock), cargs, 0, (hipStream_t)stream);
     if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
-    return FM_OK;
+    }
+    return solve_checks(ctx, s, params, loss_trace, K, (hipStream_t)stream);
   }
+  {
   fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
   hipError_t e = wdt == FM_F64 ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want),
                                                            dim3(kSolveBlock), args, 0, (hipStream_t)stream)
                                : hipLaunchCooperativeKernel((const void*)k_solve<float>, dim3((unsigned)want),
                                                            dim3(kSolveBlock), args, 0, (hipStream_t)stream);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
-  return FM_OK;
+  }
+  return solve_checks(ctx, s, params, loss_trace, K, (hipStream_t)stream);
 }
 
 extern "C" fm_status fm_solve_barrier_failures(fm_ctx* ctx, fm_scene* s, int64_t* failures) {

@@ -2,14 +2,21 @@
 // (ReLU, ReLU, sigmoid) whose 64x64 layer runs on MFMA (float16 operands,
 // float32 accumulation), forward and backward.
 //
-// MFMA layout (v_mfma_f32_16x16x16_f16, one wavefront, lane l, r = l % 16,
-// q = l / 16): operand A (16x16, M x K) holds A[r][4q + j] in its 4 halves,
-// operand B (K x N) holds B[4q + j][r], and the 16x16 float32 result holds
-// D[4q + j][r].  A tile is 16 matches; lanes r = 0..15 of each quarter q
-// address one match (operand A) or one output unit (result).
+// MFMA layouts (one wavefront, lane l, r = l % 16, q = l / 16), both with
+// the 16x16 float32 result D[4q + j][r] in four registers:
+//   v_mfma_f32_16x16x32_f16 (gfx950): operand A (16 x 32, M x K) holds
+//     A[r][8q + j] in its 8 halves, operand B (32 x 16) holds B[8q + j][r];
+//     used where the contraction runs over the 64 hidden units (the
+//     forward's 64x64 layer, the backward's dh1 = dh2 W2): two per 16x16
+//     output tile;
+//   v_mfma_f32_16x16x16_f16: A[r][4q + j], B[4q + j][r]; used for the
+//     backward's dW2, whose contraction runs over a 16-match tile.
+// A tile is 16 matches; lanes r = 0..15 of each quarter q address one match
+// (operand A) or one output unit (result).
 #include "fm_internal.h"
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHid = 64;
@@ -21,6 +28,7 @@ struct MlpPtrs {
 };
 
 __device__ inline f4 mfma16(h4 a, h4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
+__device__ inline f4 mfma32(h8 a, h8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 
 struct MlpLds {
   float W1[kHid * 3], b1[kHid], b2[kHid], W3[kHid], mean[3], rstd[3], b3;
@@ -48,21 +56,21 @@ __device__ inline void load_x(const float* feats, int64_t m, const MlpLds& s, fl
 
 // Blocks of 4 wavefronts walk the 16-match tiles in block-uniform steps (so
 // block barriers are safe); tile = step * 4 * gridDim + 4 * block + wave.
-__global__ __launch_bounds__(256) void k_mlp_forward(int64_t M, const float* __restrict__ feats, MlpPtrs w,
+__global__ __launch_bounds__(256, 4) void k_mlp_forward(int64_t M, const float* __restrict__ feats, MlpPtrs w,
                                                      float out_scale, float* __restrict__ out,
                                                      _Float16* __restrict__ act) {
   __shared__ MlpLds s;
   load_lds(w, s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
-  // layer-2 operand B[k][n] = W2[n][k] for k-tile kk, n-tile nt
-  h4 B[4][4];
+  // layer-2 operand B[k][n] = W2[n][k] for k-tile kk (32 inputs), n-tile nt
+  h8 B[2][4];
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk)
+  for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) B[kk][nt][j] = (_Float16)w.W2[(16 * nt + r) * kHid + 16 * kk + 4 * q + j];
+      for (int j = 0; j < 8; ++j) B[kk][nt][j] = (_Float16)w.W2[(16 * nt + r) * kHid + 32 * kk + 8 * q + j];
   const int64_t ntiles = (M + 15) / 16;
   for (int64_t base = (int64_t)blockIdx.x * 4; base < ntiles; base += (int64_t)gridDim.x * 4) {
     const int64_t tile = base + wave;
@@ -71,26 +79,26 @@ __global__ __launch_bounds__(256) void k_mlp_forward(int64_t M, const float* __r
     const bool ok = m < M;
     float x[3];
     load_x(feats, ok ? m : M - 1, s, x);
-    h4 A[4];
+    h8 A[2];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = 16 * kk + 4 * q + j;
+      for (int j = 0; j < 8; ++j) {
+        const int k = 32 * kk + 8 * q + j;
         const float z = fmaf(s.W1[3 * k], x[0], fmaf(s.W1[3 * k + 1], x[1], fmaf(s.W1[3 * k + 2], x[2], s.b1[k])));
         A[kk][j] = (_Float16)fmaxf(z, 0.0f);
       }
     if (act && ok) {
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        *reinterpret_cast<h4*>(act + m * 128 + 16 * kk + 4 * q) = A[kk];
+      for (int kk = 0; kk < 2; ++kk)
+        *reinterpret_cast<h8*>(act + m * 128 + 32 * kk + 8 * q) = A[kk];
     }
     f4 C[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       C[nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) C[nt] = mfma16(A[kk], B[kk][nt], C[nt]);
+      for (int kk = 0; kk < 2; ++kk) C[nt] = mfma32(A[kk], B[kk][nt], C[nt]);
     }
     // C[nt][j] = z2 of match 16 tile + 4q + j, unit 16 nt + r
     float part[4];
@@ -130,14 +138,14 @@ __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __
   load_lds(w, s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
-  // operand B of dh1 = dh2 W2: B[k = o][n = i] = W2[o][i]
-  h4 B2[4][4];
+  // operand B of dh1 = dh2 W2: B[k = o][n = i] = W2[o][i], k-tiles of 32
+  h8 B2[2][4];
 #pragma unroll
-  for (int kt = 0; kt < 4; ++kt)
+  for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
     for (int it = 0; it < 4; ++it)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) B2[kt][it][j] = (_Float16)w.W2[(16 * kt + 4 * q + j) * kHid + 16 * it + r];
+      for (int j = 0; j < 8; ++j) B2[kt][it][j] = (_Float16)w.W2[(32 * kt + 8 * q + j) * kHid + 16 * it + r];
   f4 gW2[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -196,16 +204,16 @@ __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __
       for (int it = 0; it < 4; ++it) gW2[ot][it] = mfma16(A2[ot], B1[it], gW2[ot][it]);
     __syncthreads();
     // dh1 = (dh2 W2) * (h1 > 0): operand A[m][o] read back transposed
-    h4 A3[4];
+    h8 A3[2];
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt)
+    for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) A3[kt][j] = T[wave][r][16 * kt + 4 * q + j];
+      for (int j = 0; j < 8; ++j) A3[kt][j] = T[wave][r][32 * kt + 8 * q + j];
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       f4 C = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt) C = mfma16(A3[kt], B2[kt][it], C);
+      for (int kt = 0; kt < 2; ++kt) C = mfma32(A3[kt], B2[kt][it], C);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float dh1 = h1[j][it] > 0.0f ? C[j] : 0.0f;
@@ -403,7 +411,6 @@ extern "C" fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats,
   return FM_OK;
 }
 
-fm_status fm_launch_essentials(fm_scene* s, const float* params, hipStream_t st);
 
 extern "C" fm_status fm_match_features(fm_ctx* ctx, fm_scene* s, const float* params, float delta, float* feats,
                                        fm_stream stream) {
@@ -433,3 +440,4 @@ extern "C" fm_status fm_match_features(fm_ctx* ctx, fm_scene* s, const float* pa
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
 }
+

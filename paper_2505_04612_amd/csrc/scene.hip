@@ -112,7 +112,62 @@ extern "C" void fm_destroy(fm_ctx* ctx) {
   release_timings(ctx);
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   (void)hipFree(ctx->ws);
+  (void)hipFree(ctx->check_flag);
   delete ctx;
+}
+
+// ------------------------------------------------------------------ check mode
+
+extern "C" fm_status fm_set_check(fm_ctx* ctx, int enable) {
+  if (!ctx) return FM_EINVAL;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (enable && !ctx->check_flag) {
+    FM_HIP_TRY(ctx, hipMalloc(&ctx->check_flag, sizeof(unsigned)));
+    FM_HIP_TRY(ctx, hipMemset(ctx->check_flag, 0, sizeof(unsigned)));
+    FM_HIP_TRY(ctx, hipDeviceSynchronize());
+  }
+  ctx->check = enable != 0;
+  return FM_OK;
+}
+
+extern "C" fm_status fm_check(fm_ctx* ctx, fm_stream stream, uint32_t* flags) {
+  if (!ctx) return FM_EINVAL;
+  if (flags) *flags = 0;
+  if (!ctx->check_flag) return FM_OK;
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  FM_HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+  unsigned f = 0;
+  FM_HIP_TRY(ctx, hipMemcpy(&f, ctx->check_flag, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (!f) return FM_OK;
+  FM_HIP_TRY(ctx, hipMemset(ctx->check_flag, 0, sizeof(unsigned)));
+  FM_HIP_TRY(ctx, hipDeviceSynchronize());
+  if (flags) *flags = f;
+  return fm_fail(ctx, FM_EDEVICE_CHECK, "device check failed:%s%s%s%s",
+                 (f & FM_CHECK_COORDS) ? " non-finite match coordinates;" : "",
+                 (f & FM_CHECK_PARAMS) ? " non-finite pose parameters or essential matrices;" : "",
+                 (f & FM_CHECK_DEGENERATE) ? " pairs with zero relative translation;" : "",
+                 (f & FM_CHECK_LOSS) ? " non-finite loss or gradient;" : "");
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_check_finite(const T* __restrict__ p, int64_t n, unsigned bit,
+                                                         unsigned* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(p[k]);
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, bit);
+}
+
+fm_status fm_check_finite(fm_ctx* ctx, hipStream_t st, const void* p, int64_t n, bool f64, unsigned bit) {
+  if (!ctx->check || !p || n <= 0) return FM_OK;
+  const int64_t want = grid_for(n, kBlock);
+  const dim3 grid((unsigned)(want < 1024 ? want : 1024)), block(kBlock);
+  if (f64)
+    hipLaunchKernelGGL(k_check_finite<double>, grid, block, 0, st, (const double*)p, n, bit, ctx->check_flag);
+  else
+    hipLaunchKernelGGL(k_check_finite<float>, grid, block, 0, st, (const float*)p, n, bit, ctx->check_flag);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
 }
 
 extern "C" const char* fm_last_error(const fm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -267,8 +322,9 @@ static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
 }
 
 // Work decomposition of the Gram pass (make_gram_plan, host only): chunks of
-// 64 big_rows(dtype) matches for pairs with more than kSmall matches, groups
-// of four smaller pairs, both longest first; uploaded once per scene.
+// 64 big_rows(dtype) matches for pairs with more than small_max(dtype)
+// matches, groups of four smaller pairs (pairs without matches included),
+// both longest first; uploaded once per scene.
 static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   fm_ctx* ctx = s->ctx;
   const int64_t P = s->P;
@@ -277,7 +333,7 @@ static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fm_fail(ctx, FM_EHIP, "gram plan: %s", hipGetErrorString(e));
   s->chunk = (int64_t)kLanes * big_rows(s->dtype);
-  const GramPlan g = make_gram_plan(off.data(), P, kLanes, big_rows(s->dtype), kSmall);
+  const GramPlan g = make_gram_plan(off.data(), P, kLanes, big_rows(s->dtype), small_max(s->dtype));
   s->n_big = (int64_t)g.big_pair.size();
   s->n_groups = (int64_t)g.groups.size() / 4;
   s->n_partials = g.n_partials;
@@ -285,7 +341,8 @@ static fm_status build_gram_plan(fm_scene* s, hipStream_t st) {
   s->n_empty = g.n_empty;
   if ((e = upload(&s->big_pair, g.big_pair, st)) != hipSuccess ||
       (e = upload(&s->big_chunk, g.big_chunk, st)) != hipSuccess ||
-      (e = upload(&s->big_slot, g.big_slot, st)) != hipSuccess || (e = upload(&s->groups, g.groups, st)) != hipSuccess ||
+      (e = upload(&s->big_slot, g.big_slot, st)) != hipSuccess ||
+      (e = upload(&s->groups, g.groups, st)) != hipSuccess ||
       (e = upload(&s->multi, g.multi, st)) != hipSuccess || (e = upload(&s->multi_first, g.multi_first, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return fm_fail(ctx, e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP, "gram plan: %s", hipGetErrorString(e));
@@ -407,8 +464,8 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   SCENE_TRY(hipMalloc(&s->loss_part, sizeof(double) * s->loss_part_cap));
   SCENE_TRY(hipMalloc(&s->rot, sizeof(double) * 9 * 2 * (N > 0 ? N : 1)));
   SCENE_TRY(hipMalloc(&s->params_alt, sizeof(float) * 10 * (N > 0 ? N : 1)));
-  SCENE_TRY(hipMalloc(&s->bar, sizeof(unsigned) * 128));
-  SCENE_TRY(hipMemsetAsync(s->bar, 0, sizeof(unsigned) * 128, st));
+  SCENE_TRY(hipMalloc(&s->bar, sizeof(unsigned) * kBarWords));
+  SCENE_TRY(hipMemsetAsync(s->bar, 0, sizeof(unsigned) * kBarWords, st));
   SCENE_TRY(hipStreamSynchronize(st));
   *out = s;
   return FM_OK;

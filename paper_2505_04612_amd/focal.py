@@ -31,7 +31,8 @@ class FocalSchedule:
 def solve(scene: api.Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.Tensor, inv_Z: float,
           sched: FocalSchedule = FocalSchedule(), trace: bool = False, fused: bool = True):
     """Refine poses [N,9] and log focal scales [N] in place; returns the loss
-    trace (host list) if `trace`."""
+    trace (host list) if `trace`.  Raises FastMapError if the persistent
+    launch's grid barrier timed out."""
     ctx = scene.ctx
     N = scene.num_cams
     mp, vp = torch.zeros_like(params), torch.zeros_like(params)
@@ -41,6 +42,7 @@ def solve(scene: api.Scene, W36: torch.Tensor, params: torch.Tensor, phi: torch.
         api.epipolar_focal_solve(scene, W36, params, phi, mp, vp, mf, vf, sched.iters, sched.lr_rot, sched.lr_t,
                                  sched.lr_phi, sched.lr_final_frac, beta1=sched.beta1, beta2=sched.beta2,
                                  eps=sched.eps, inv_Z=inv_Z, loss_trace=tr)
+        scene.require_barriers_ok()
         return tr.cpu().tolist() if trace else None
     lr0 = np.tile(np.array([sched.lr_rot] * 6 + [sched.lr_t] * 3, np.float32), N)
     lr_p = torch.empty(9 * N, dtype=torch.float32, device=params.device)

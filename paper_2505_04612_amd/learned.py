@@ -1,26 +1,28 @@
-"""Learned robust weights for epipolar adjustment, with IRLS as fallback.
+"""Learned robust weights for epipolar adjustment, with IRLS as the judge.
 
 The paper robustifies the L2 epipolar objective by IRLS: weights 1/|r| at
 the current poses, recomputed after every optimisation loop (Sec. 3.3).
 Here a 3 -> 64 -> 64 -> 1 MLP proposes each match's weight directly from
-features (log residual, log pair size, parallax), so after a short warm-up
-one Gram build replaces the remaining IRLS rebuilds: the first
-`warm_rounds` loops of the plain schedule run as usual, the network weighs
-every match at the poses they reach, and the remaining Adam steps run on
-that one Gram.  The network is trained on the targets the method's own
-converged IRLS solves produce, omega_bar = delta / max(|r|, delta) (0 for
-filtered matches), from features at the same warm-up poses, with the
-library's MFMA forward/backward kernels and its Adam kernel.
+features (log residual, log pair size, parallax), so one Gram build stands
+in for a run of IRLS rebuilds: the first `warm_rounds` loops of the plain
+schedule run as usual, the network weighs every match at the poses they
+reach, and `iters` Adam steps run on that one Gram (at the schedule
+positions of the loops they replace).  The network is trained on the
+targets the method's own converged IRLS solves produce, omega_bar =
+delta / max(|r|, delta) (0 for filtered matches), from features at the same
+warm-up poses, with the library's MFMA forward/backward kernels and its
+Adam kernel.
 
-A tail of `tail_rounds` plain IRLS loops (final filter threshold, learning
-rate from the middle of the plain schedule's range down to its end) then
-takes the learned solution to the IRLS weighting.  Fallback: if the tail
-moves the relative rotation of more than a tenth of the pairs by over
-0.1 deg, or their translation direction by over 0.5 deg (the
-90th percentile of the per-pair changes, so a few pairs with an
-ill-conditioned baseline do not decide alone), the full plain IRLS schedule
-is run from the initial poses instead, so plain IRLS remains the reference
-for pose accuracy.
+Plain IRLS loops then continue from the learned solution at their own
+schedule positions (threshold and learning rate), and after each one
+fm_pose_change measures, on the device, how far it moved every pair's
+relative rotation and translation direction.  Once a loop moves at most
+`check_frac` of the pairs by more than 0.1 deg rotation or 0.5 deg
+translation direction, the solve is taken as converged and stops; otherwise
+the plain loops run to the end of the schedule (the fallback: it costs the
+rest of the plain schedule, never a restart).  `plain_converged_solve` is
+plain IRLS under the same stopping rule, the fair comparison for what the
+network buys.
 
     python -m paper_2505_04612_amd.learned --train 64 --test 16 --out results.json
 """
@@ -43,20 +45,18 @@ from . import api, solver, synth
 @dataclasses.dataclass
 class LearnedSchedule:
     warm_rounds: int = 2         # plain IRLS loops before the network weighs the matches
-    iters: int = 600             # Adam steps on the learned-weight Gram
-    tail_rounds: int = 3         # plain IRLS loops after them (their movement is the fallback check)
-    lr_rot: float = 3e-3
-    lr_t: float = 1e-2
-    lr_final_frac: float = 1e-3
+    iters: int = 600             # Adam steps on the learned-weight Gram (standing in for iters/round_len loops)
     delta: float = 1e-4
-    check_rot_deg: float = 0.1   # fallback thresholds on the per-pair changes
+    check_rot_deg: float = 0.1   # a loop that moves a pair by more than these has not converged
     check_t_deg: float = 0.5
-    check_quantile: float = 0.9
+    check_frac: float = 0.1      # converged: at most this fraction of the pairs moved beyond them
 
 
 def _pose_changes(pa: np.ndarray, pb: np.ndarray, pairs: np.ndarray):
     """Per-pair relative-rotation and translation-direction change (deg)
-    between two parameter sets; the sign of t is ignored."""
+    between two parameter sets; the sign of t is ignored.  Host-side
+    evaluation helper (accuracy reports against ground truth); the solve's
+    own convergence test runs on the device (fm_pose_change)."""
     def rot(p):
         a1, a2 = p[:, 0:3], p[:, 3:6]
         b1 = a1 / np.linalg.norm(a1, axis=1, keepdims=True)
@@ -78,14 +78,6 @@ def _pose_changes(pa: np.ndarray, pb: np.ndarray, pairs: np.ndarray):
     ub = tb / np.linalg.norm(tb, axis=1, keepdims=True)
     t_err = np.degrees(np.arctan2(np.linalg.norm(np.cross(ua, ub), axis=1), np.abs(np.sum(ua * ub, axis=1))))
     return r_err, t_err
-
-
-def _relative_pose_change(pa: np.ndarray, pb: np.ndarray, pairs: np.ndarray, q: float = 1.0):
-    """Quantile q (1 = max) of the per-pair relative-rotation and
-    translation-direction changes (deg): the host-side decision of the
-    fallback rule."""
-    r, t = _pose_changes(pa, pb, pairs)
-    return float(np.quantile(r, q)), float(np.quantile(t, q))
 
 
 def irls_targets(scene: api.Scene, params0: torch.Tensor, sched: solver.Schedule, warm_rounds: int = 2):
@@ -147,48 +139,71 @@ def train_mlp(ctx: api.Context, feats: torch.Tensor, target: torch.Tensor, cfg: 
     return w, hist
 
 
+def _plain_loops(scene: api.Scene, p: torch.Tensor, plain: solver.Schedule, first: int, ls: LearnedSchedule,
+                 stop_early: bool):
+    """Plain IRLS loops first, first+1, ... of the schedule (threshold and
+    learning rate at their own positions) from poses p, updated in place.
+    With stop_early, after each loop fm_pose_change compares the poses
+    before and after it and the loops stop once it moved at most
+    ls.check_frac of the pairs beyond the thresholds.  Returns (loops run,
+    converged)."""
+    R = plain.round_len
+    loops = -(-plain.iters // R)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    limit = ls.check_frac * scene.num_pairs
+    run = 0
+    for k in range(first, loops):
+        prev = p.clone() if stop_early else None
+        W, Z = solver._grams(scene, p, plain, solver.tau_at(plain, k))
+        m.zero_()
+        v.zero_()
+        K = min(R, plain.iters - k * R)
+        api.epipolar_solve(scene, W, p, m, v, K, plain.lr_rot, plain.lr_t, plain.lr_final_frac, k * R, plain.iters,
+                           0, plain.beta1, plain.beta2, plain.eps, Z=Z)
+        run += 1
+        if stop_early:
+            counts, _, _ = api.pose_change(scene, prev, p, ls.check_rot_deg, ls.check_t_deg)
+            n_rot, n_t = (int(x) for x in counts.tolist())
+            if n_rot <= limit and n_t <= limit:
+                scene.require_barriers_ok()
+                return run, True
+    scene.require_barriers_ok()
+    return run, False
+
+
+def plain_converged_solve(scene: api.Scene, params0: torch.Tensor, plain: solver.Schedule,
+                          ls: LearnedSchedule = LearnedSchedule()):
+    """Plain IRLS (every loop reweighted, from the initial poses) under the
+    learned form's stopping rule; returns (params, info)."""
+    p = params0.detach().clone().contiguous()
+    loops, conv = _plain_loops(scene, p, plain, 0, ls, True)
+    return p, {"loops": loops, "converged": conv}
+
+
 def learned_solve(scene: api.Scene, params0: torch.Tensor, w: api.MlpWeights, ls: LearnedSchedule,
-                  fallback: solver.Schedule):
-    """Solve with MLP-proposed weights after a short plain warm-up; returns
+                  plain: solver.Schedule):
+    """Solve with MLP-proposed weights after a short plain warm-up, then plain
+    IRLS loops to convergence (or to the end of the schedule); returns
     (params, info)."""
     ctx = scene.ctx
-    warm = ls.warm_rounds * fallback.round_len
+    R = plain.round_len
+    warm = ls.warm_rounds * R
     p = params0.detach().clone().contiguous()
     if ls.warm_rounds > 0:
-        p, _, _ = solver.solve(scene, params0, fallback, trace=False, rounds=ls.warm_rounds)
+        p, _, _ = solver.solve(scene, params0, plain, trace=False, rounds=ls.warm_rounds)
     feats = api.match_features(scene, p, ls.delta)
     omega, _ = api.mlp_forward(ctx, w, feats, out_scale=1.0 / ls.delta)
     W64, _ = api.build_pair_grams(scene, omega, f64=True, f32=False)
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
-    api.epipolar_solve(scene, W64, p, m, v, ls.iters, ls.lr_rot, ls.lr_t, ls.lr_final_frac, warm, warm + ls.iters,
-                       inv_Z=1.0 / max(scene.num_matches, 1))
-    # a tail of plain IRLS loops from the learned solution, at the final
-    # filter threshold and with the learning rate falling from the geometric
-    # middle of the plain schedule's range to its end; how far the tail moves
-    # the learned solution decides the fallback
+    api.epipolar_solve(scene, W64, p, m, v, ls.iters, plain.lr_rot, plain.lr_t, plain.lr_final_frac, warm,
+                       plain.iters, inv_Z=1.0 / max(scene.num_matches, 1))
     p_learned = p.clone()
-    tau = solver.tau_at(fallback, max(fallback.iters // fallback.round_len - 1, 0))
-    half = math.sqrt(fallback.lr_final_frac)
-    T = max(ls.tail_rounds, 1)
-    tail = dataclasses.replace(fallback, iters=T * fallback.round_len, tau0=tau, lr_rot=fallback.lr_rot * half,
-                               lr_t=fallback.lr_t * half, lr_final_frac=half)
-    p_chk = p.clone()
-    for r in range(T):
-        Wt, Zt = solver._grams(scene, p_chk, tail, solver.tau_at(tail, r))
-        m.zero_()
-        v.zero_()
-        api.epipolar_solve(scene, Wt, p_chk, m, v, tail.round_len, tail.lr_rot, tail.lr_t, tail.lr_final_frac,
-                           r * tail.round_len, tail.iters, 0, tail.beta1, tail.beta2, tail.eps, Z=Zt)
-    d_rot, d_t = _relative_pose_change(p_learned.cpu().numpy(), p_chk.cpu().numpy(), scene.pairs.cpu().numpy(),
-                                       ls.check_quantile)
-    info = {"check_rot_deg": d_rot, "check_t_deg": d_t, "fallback": False, "params_learned": p_learned}
-    if d_rot > ls.check_rot_deg or d_t > ls.check_t_deg:
-        # the learned weights missed the IRLS optimum: plain IRLS from the
-        # initial poses decides the result
-        info["fallback"] = True
-        p_chk, _, _ = solver.solve(scene, params0, fallback, trace=False)
-    return p_chk, info
+    first = ls.warm_rounds + -(-ls.iters // R)
+    loops, conv = _plain_loops(scene, p, plain, first, ls, True)
+    return p, {"params_learned": p_learned, "tail_loops": loops, "converged": conv,
+               "fallback": not conv, "loops_total": ls.warm_rounds + loops}
 
 
 def _gen(seed: int, n_cams: int, n_points: int):
@@ -217,7 +232,6 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--learned-iters", type=int, default=600)
     ap.add_argument("--warm-rounds", type=int, default=2)
-    ap.add_argument("--tail-rounds", type=int, default=3)
     ap.add_argument("--out", default="learned_results.json")
     args = ap.parse_args(argv)
     t0 = time.time()
@@ -255,7 +269,7 @@ def main(argv=None) -> int:
                         progress=lambda k, l: print(f"[learned] step {k} loss {l:.4g}", flush=True)
                         if k % 500 == 0 else None)
     print(f"[learned] trained: loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g} ({time.time() - t0:.0f}s)", flush=True)
-    ls = LearnedSchedule(iters=args.learned_iters, warm_rounds=args.warm_rounds, tail_rounds=args.tail_rounds)
+    ls = LearnedSchedule(iters=args.learned_iters, warm_rounds=args.warm_rounds)
     rows = []
     for sc in scenes[args.train:]:
         # plain method: FP32 coordinates, IRLS every loop; learned form: BF16
@@ -264,7 +278,8 @@ def main(argv=None) -> int:
         s16 = api.Scene.from_numpy(ctx, len(sc["R_gt"]), sc["pairs"], sc["offsets"], sc["uv"], torch.bfloat16)
         p0 = torch.from_numpy(np.concatenate([sc["R_init"][:, :, 0], sc["R_init"][:, :, 1], sc["t_init"]],
                                              axis=1).astype(np.float32)).to(dev)
-        solver.solve(s, p0, sched, trace=False)            # warm-up of both paths
+        solver.solve(s, p0, sched, trace=False)            # warm-up of the paths
+        plain_converged_solve(s, p0, sched, ls)
         learned_solve(s16, p0, w, ls, sched)
         torch.cuda.synchronize()
         a = time.perf_counter()
@@ -272,19 +287,27 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         t_irls = time.perf_counter() - a
         a = time.perf_counter()
+        p_pc, info_pc = plain_converged_solve(s, p0, sched, ls)
+        torch.cuda.synchronize()
+        t_pc = time.perf_counter() - a
+        a = time.perf_counter()
         p_l, info = learned_solve(s16, p0, w, ls, sched)
         torch.cuda.synchronize()
         t_l = time.perf_counter() - a
         s16.close()
         e_irls = _pose_err(p_irls.cpu().numpy(), sc["R_gt"], sc["t_gt"], sc["pairs"])
+        e_pc = _pose_err(p_pc.cpu().numpy(), sc["R_gt"], sc["t_gt"], sc["pairs"])
         e_l = _pose_err(p_l.cpu().numpy(), sc["R_gt"], sc["t_gt"], sc["pairs"])
         e_lo = _pose_err(info.pop("params_learned").cpu().numpy(), sc["R_gt"], sc["t_gt"], sc["pairs"])
-        d = _relative_pose_change(p_l.cpu().numpy(), p_irls.cpu().numpy(), sc["pairs"])
-        rows.append({"seed": sc["seed"], "irls_s": t_irls, "learned_s": t_l, "irls_err_deg": e_irls,
-                     "learned_err_deg": e_l, "learned_before_check_err_deg": e_lo, "learned_vs_irls_max_deg": d,
-                     **info})
-        print(f"[learned] seed {sc['seed']}: IRLS {t_irls * 1e3:.1f} ms err {e_irls}, learned "
-              f"{t_l * 1e3:.1f} ms err {e_l} fallback {info['fallback']}", flush=True)
+        r_d, t_d = _pose_changes(p_l.cpu().numpy(), p_irls.cpu().numpy(), sc["pairs"])
+        rows.append({"seed": sc["seed"], "irls_s": t_irls, "plain_converged_s": t_pc, "learned_s": t_l,
+                     "irls_err_deg": e_irls, "plain_converged_err_deg": e_pc, "learned_err_deg": e_l,
+                     "learned_before_tail_err_deg": e_lo, "plain_converged": info_pc,
+                     "learned_vs_irls_max_deg": (float(r_d.max()), float(t_d.max())), **info})
+        print(f"[learned] seed {sc['seed']}: IRLS {t_irls * 1e3:.1f} ms rot med {e_irls['rot_med']:.3f}; plain "
+              f"with the stopping rule {t_pc * 1e3:.1f} ms ({info_pc['loops']} loops) rot med "
+              f"{e_pc['rot_med']:.3f}; learned {t_l * 1e3:.1f} ms ({info['loops_total']} loops, converged "
+              f"{info['converged']}) rot med {e_l['rot_med']:.3f}", flush=True)
         s.close()
     res = {"train_scenes": args.train, "test_scenes": args.test, "samples": int(feats.shape[0]),
            "train_loss": hist, "test": rows, "wall_s": time.time() - t0,

@@ -37,7 +37,8 @@ def average(scene: api.Scene, Rrel: torch.Tensor, sched: RotationSchedule = Rota
     """World-to-camera rotation parameters [N,6] (a1, a2) from the measured
     relative rotations Rrel [P,9] (row-major).  Returns (params, info) with
     the initial parameters, the Lanczos eigenvalues and steps, and, if
-    `trace`, the loss trace of the solve."""
+    `trace`, the loss trace of the solve.  Raises FastMapError if a
+    persistent launch's grid barrier timed out."""
     N = scene.num_cams
     start = torch.from_numpy(np.random.default_rng(sched.seed).normal(size=(2, 3 * N))).to(scene.ctx.device)
     p0, lz = api.rotation_init(scene, Rrel, start, sched.lanczos_steps)
@@ -46,6 +47,7 @@ def average(scene: api.Scene, Rrel: torch.Tensor, sched: RotationSchedule = Rota
     tr = torch.empty(sched.iters, dtype=torch.float64, device=p.device) if trace else None
     api.rotation_solve(scene, Rrel, p, m, v, sched.iters, sched.lr, sched.lr_final_frac, beta1=sched.beta1,
                        beta2=sched.beta2, eps=sched.eps, loss_trace=tr)
+    scene.require_barriers_ok()
     info = {"init": p0, "lanczos": lz}
     if trace:
         info["trace"] = tr

@@ -32,7 +32,9 @@ class Schedule:
     tau0: float = 0.1             # first filter threshold on |r|
     tau_min: float = 0.01         # threshold floor
     first_round_unit_weights: bool = False
-    gram_dtype: torch.dtype = torch.float64  # Gram precision the iterations read
+    gram_dtype: torch.dtype = torch.float32  # Gram precision the iterations read (the float32 copy of the
+                                             # float64 per-pair sums: half the bytes of each iteration)
+    blocks: int = 0               # fused loop grid: 0 automatic, > 0 workgroups of the pair loop, < 0 the camera loop
 
 
 def tau_at(s: Schedule, k: int) -> float:
@@ -49,11 +51,15 @@ def _grams(scene, params, s: Schedule, tau: float | None):
     return (W64 if f64 else W32), kept
 
 
-def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = True, rounds: int | None = None):
+def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = True, rounds: int | None = None,
+          check_barriers: bool = True):
     """Run the schedule from params0 [N,9] float32.  Returns (params, loss
     trace [iters] float64 or None, Z [1] int64 or None for unit weights).
     `rounds` stops after that many optimisation loops (the schedule's learning
-    rates and thresholds are those of the full run)."""
+    rates and thresholds are those of the full run).  With `check_barriers`
+    the call ends by synchronising the device and raises FastMapError if a
+    grid barrier of the fused loops timed out (their results would then be
+    invalid); without it the caller reads scene.barrier_failures() itself."""
     dev = scene.ctx.device
     params = params0.detach().to(dev, torch.float32).clone().contiguous()
     m = torch.zeros_like(params)
@@ -74,9 +80,11 @@ def solve(scene: api.Scene, params0: torch.Tensor, s: Schedule, trace: bool = Tr
         v.zero_()
         api.epipolar_solve(scene, W, params, m, v, K, s.lr_rot, s.lr_t, s.lr_final_frac, done, s.iters, 0,
                            s.beta1, s.beta2, s.eps, inv_Z=None if Z is not None else inv_Z, Z=Z,
-                           loss_trace=losses[done:done + K] if trace else None)
+                           loss_trace=losses[done:done + K] if trace else None, blocks=s.blocks)
         done += K
         if s.irls and done < stop:
             W, Z = _grams(scene, params, s, tau_at(s, k_rw))
             k_rw += 1
+    if check_barriers:
+        scene.require_barriers_ok()
     return params, losses, Z

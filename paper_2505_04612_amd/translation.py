@@ -38,7 +38,8 @@ def average(scene: api.Scene, dirs: torch.Tensor, init: torch.Tensor,
     """Camera centres [N,3] from targets `dirs` [P,3] and initial centres
     `init` [runs,N,3] (one random initialisation per run).  Returns
     (centres, info) with the runs' final centres, the merge choice and, if
-    `trace`, the loss traces of the runs and of the final loop."""
+    `trace`, the loss traces of the runs and of the final loop.  Raises
+    FastMapError if a persistent launch's grid barrier timed out."""
     R = int(init.shape[0])
     runs = init.clone()
     m = torch.zeros_like(runs)
@@ -53,6 +54,7 @@ def average(scene: api.Scene, dirs: torch.Tensor, init: torch.Tensor,
     tr1 = torch.empty((1, sched.final_iters), dtype=torch.float64, device=runs.device) if trace else None
     api.translation_solve(scene, dirs, final, m1, v1, sched.final_iters, sched.lr, sched.lr_final_frac,
                           beta1=sched.beta1, beta2=sched.beta2, eps=sched.eps, loss_trace=tr1)
+    scene.require_barriers_ok()
     info = {"runs": runs, "merged": merged, "choice": choice, "cam_loss": cam}
     if trace:
         info["trace_runs"] = tr

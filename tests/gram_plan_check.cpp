@@ -19,8 +19,11 @@ static int check(const std::vector<int64_t>& off, int64_t lanes, int64_t rows, i
   std::vector<int> seen(P, 0);
   std::vector<int64_t> covered(P, 0);
   std::map<int32_t, int64_t> first;  // multi pair -> first slot
-  for (size_t i = 0; i < g.multi.size() && (int64_t)i < g.n_multi; ++i) first[g.multi[i]] = g.multi_first[i];
-  if ((int64_t)g.multi_first.size() != g.n_multi) return fail("multi_first size", (long)g.multi_first.size(), g.n_multi);
+  for (size_t i = 0; i < g.multi.size(); ++i) first[g.multi[i]] = g.multi_first[i];
+  if ((int64_t)g.multi_first.size() != g.n_multi || (int64_t)g.multi.size() != g.n_multi)
+    return fail("multi sizes", (long)g.multi_first.size(), g.n_multi);
+  if (g.big_slot.size() != g.big_pair.size() || g.big_chunk.size() != g.big_pair.size())
+    return fail("chunk table sizes", (long)g.big_slot.size(), (long)g.big_pair.size());
   std::vector<int> slot_used(g.n_partials, 0);
   int32_t prev_rows = 1 << 30;
   for (size_t i = 0; i < g.big_pair.size(); ++i) {
@@ -60,7 +63,7 @@ static int check(const std::vector<int64_t>& off, int64_t lanes, int64_t rows, i
       if (pad) return fail("live pair after an empty slot", (long)q, n);
       if (n >= P) return fail("group pair out of range", n);
       const int64_t c = off[n + 1] - off[n];
-      if (c < 1 || c > small) return fail("group pair size", n, c);
+      if (c < 0 || c > small) return fail("group pair size", n, c);
       const int32_t rr = (int32_t)((c + 15) / 16);
       if (r >= 0 && rr != r) return fail("group rows differ", (long)q, rr);
       r = rr;
@@ -71,15 +74,12 @@ static int check(const std::vector<int64_t>& off, int64_t lanes, int64_t rows, i
     if (r > prev_rows) return fail("groups not longest first", (long)q, r);
     prev_rows = r;
   }
-  for (int64_t i = g.n_multi; i < (int64_t)g.multi.size(); ++i) {
-    const int32_t n = g.multi[i];
-    if (n < 0 || n >= P || off[n + 1] != off[n]) return fail("empty list", n);
-    ++seen[n];
-  }
-  if ((int64_t)g.multi.size() != g.n_multi + g.n_empty) return fail("multi + empty size");
+  int64_t empty = 0;
+  for (int64_t n = 0; n < P; ++n) empty += off[n + 1] == off[n];
+  if (empty != g.n_empty) return fail("empty count", (long)empty, (long)g.n_empty);
   for (int64_t n = 0; n < P; ++n) {
     const int64_t c = off[n + 1] - off[n];
-    const int expect = c == 0 ? 1 : (c <= small ? 1 : (int)((c + chunk - 1) / chunk));
+    const int expect = c <= small ? 1 : (int)((c + chunk - 1) / chunk);
     if (seen[n] != expect) return fail("pair covered a wrong number of times", n, seen[n]);
     if (covered[n] != c) return fail("pair matches not covered exactly", n, covered[n]);
   }
@@ -99,6 +99,8 @@ int main() {
     if (std::scanf("%ld", &c) != 1 || c < 0) return fail("input size", n);
     off[n + 1] = off[n] + c;
   }
-  // the two chunk shapes the library uses: 16 rows (FP32/FP64), 32 (BF16)
-  return check(off, 64, 16, 256) || check(off, 64, 32, 256);
+  // the two shapes the library uses: chunks of 16 rows and groups of pairs
+  // up to 256 matches (FP32/FP64), chunks of 64 rows and groups of pairs up
+  // to 1024 matches (BF16)
+  return check(off, 64, 16, 256) || check(off, 64, 64, 1024);
 }
