@@ -490,6 +490,22 @@ fm_status fm_pose_change(fm_ctx* ctx, fm_scene* scene, const float* params_a, co
                          float rot_deg, float t_deg, float* rot_out, float* t_out, int64_t* counts,
                          fm_stream stream);
 
+/* fm_mlp_backward without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc): the same gradients, with the per-wavefront
+ * gradient slots in a static device array of the library (512 slots of 4,481
+ * floats, 9.2 MB, held by each GPU the library runs on until the process
+ * ends) instead of a context workspace that grows on demand.  The launch is
+ * capped at 128 workgroups of four wavefronts, so any M is accepted; up to
+ * 8,192 matches it is fm_mlp_backward's launch and the results are
+ * bit-identical, above it the float32 slot sums run in another order.
+ * Every call on a GPU shares that GPU's array and fully rewrites the slots
+ * it reads: calls that overlap on one GPU (two streams, two host threads)
+ * race.  The first call on a device looks the array's device address up
+ * (hipGetSymbolAddress); no call allocates. */
+fm_status fm_mlp_backward_noalloc(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
+                                  const void* act, const float* dout, fm_mlp_grad* g, fm_stream stream);
+
 /* ------------------------------------------------------------------ launch timing */
 
 /* Optional device-time measurement of the library's own launches (for

@@ -26,7 +26,7 @@ EXPORTS = [
     "fm_build_pair_grams", "fm_reweight", "fm_reweight_build",
     "fm_epipolar_loss_grad", "fm_adam_step", "fm_epipolar_solve", "fm_solve_barrier_failures",
     "fm_profile_enable", "fm_profile_read",
-    "fm_match_features", "fm_mlp_forward", "fm_mlp_backward",
+    "fm_match_features", "fm_mlp_forward", "fm_mlp_backward", "fm_mlp_backward_noalloc",
     "fm_translation_directions", "fm_translation_loss_grad", "fm_translation_solve", "fm_translation_merge",
     "fm_rotation_loss_grad", "fm_rotation_solve", "fm_rotation_init", "fm_translation_search",
     "fm_epipolar_focal_loss_grad", "fm_epipolar_focal_solve", "fm_poses_from_centres", "fm_pose_change",
@@ -86,6 +86,7 @@ _SIGNATURES = {
     "fm_match_features": (_S, [_P, _P, _P, _F, _P, _P]),
     "fm_mlp_forward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _F, _P, _P, _P]),
     "fm_mlp_backward": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(MlpGrad), _P]),
+    "fm_mlp_backward_noalloc": (_S, [_P, _I64, _P, ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(MlpGrad), _P]),
     "fm_profile_read": (_S, [_P, _S, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "fm_translation_directions": (_S, [_P, _P, _P, _P, _P, _P]),
     "fm_translation_loss_grad": (_S, [_P, _P, _P, _I32, _P, _P, _P, _P]),

@@ -13,6 +13,8 @@
 //     backward's dW2, whose contraction runs over a 16-match tile.
 // A tile is 16 matches; lanes r = 0..15 of each quarter q address one match
 // (operand A) or one output unit (result).
+#include <mutex>
+
 #include "fm_internal.h"
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
@@ -441,3 +443,68 @@ extern "C" fm_status fm_match_features(fm_ctx* ctx, fm_scene* s, const float* pa
   return FM_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free backward
+
+// Gradient slots of fm_mlp_backward_noalloc: a file-scope device array (each
+// GPU the library runs on holds its own copy until the process ends) sized
+// for kNoAllocBlocks workgroups of four wavefronts, 512 slots of kG_N floats
+// (9.2 MB).  Host code never passes `scratch` itself to a kernel (its host
+// name is a stand-in, not a device address): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kNoAllocBlocks = 128;
+constexpr int64_t kNoAllocSlots = (int64_t)kNoAllocBlocks * 4;
+static __device__ __align__(256) float scratch[kNoAllocSlots * kG_N];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_dev[kMaxDevices];
+
+// The device address of `scratch` on the context's device (which the caller
+// has made current), looked up on the first call on that device.
+static fm_status scratch_ptr(fm_ctx* ctx, float** out) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return fm_fail(ctx, FM_EINVAL, "fm_mlp_backward_noalloc: device %d beyond %d", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fm_fail(ctx, FM_EHIP, "fm_mlp_backward_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_dev[ctx->device] = (float*)p;
+  }
+  *out = g_scratch_dev[ctx->device];
+  return FM_OK;
+}
+
+extern "C" fm_status fm_mlp_backward_noalloc(fm_ctx* ctx, int64_t M, const float* feats, const fm_mlp* w,
+                                             const void* act, const float* dout, fm_mlp_grad* g, fm_stream stream) {
+  if (!ctx) return FM_EINVAL;
+  if (M < 0) return fm_fail(ctx, FM_ESHAPE, "fm_mlp_backward_noalloc: M < 0");
+  MlpPtrs p;
+  fm_status rc = mlp_ptrs(ctx, w, p);
+  if (rc != FM_OK) return rc;
+  if (!g || !g->W1 || !g->b1 || !g->W2 || !g->b2 || !g->W3 || !g->b3)
+    return fm_fail(ctx, FM_EINVAL, "fm_mlp_backward_noalloc: gradient pointer is NULL");
+  if (M > 0 && (!feats || !act || !dout)) return fm_fail(ctx, FM_EINVAL, "fm_mlp_backward_noalloc: NULL input");
+  FM_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  float* part = nullptr;
+  if ((rc = scratch_ptr(ctx, &part)) != FM_OK) return rc;
+  // the launch of fm_mlp_backward, capped at the workgroups the scratch holds
+  // slots for (identical launch, so identical results, up to 8,192 matches)
+  unsigned blocks = mlp_blocks(ctx, M);
+  if (blocks > (unsigned)kNoAllocBlocks) blocks = kNoAllocBlocks;
+  const int64_t slots = (int64_t)blocks * 4;
+  if (slots > kNoAllocSlots)
+    return fm_fail(ctx, FM_ESHAPE, "fm_mlp_backward_noalloc: %lld gradient slots exceed the %lld the scratch holds",
+                   (long long)slots, (long long)kNoAllocSlots);
+  if (M > 0) {
+    hipLaunchKernelGGL(k_mlp_backward, dim3(blocks), dim3(256), 0, (hipStream_t)stream, M, feats, p,
+                       (const _Float16*)act, dout, part);
+    FM_CHECK_LAUNCH(ctx);
+  }
+  MlpGradPtrs gp{g->W1, g->b1, g->W2, g->b2, g->W3, g->b3};
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(kG_N, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, part,
+                     M > 0 ? slots : (int64_t)0, gp);
+  FM_CHECK_LAUNCH(ctx);
+  return FM_OK;
+}
