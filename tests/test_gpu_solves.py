@@ -102,10 +102,12 @@ def test_solve_matches_stored_oracle_solve(name, blocks, gram):
     if name == "medium":
         assert rot.max() <= 0.1 and tra.max() <= 0.5, rep
     # the final kept count moves with the poses (matches whose residual sits
-    # at the last threshold): within 1e-5 of the matches, or within twice what
-    # float32 parameter storage alone moves the oracle's own count
+    # at the last threshold): within 1e-5 of the matches, or within four times
+    # what float32 parameter storage alone moves the oracle's own count (one
+    # integer sample of that spread, hence a wider factor than the
+    # percentiles over pairs get)
     sens = golden.get("float32_storage_sensitivity", {})
-    tol = max(3, int(1e-5 * sc.num_matches), 2 * abs(sens.get("kept", golden["kept"]) - golden["kept"]))
+    tol = max(3, int(1e-5 * sc.num_matches), 4 * abs(sens.get("kept", golden["kept"]) - golden["kept"]))
     assert abs(int(Z.item()) - golden["kept"]) <= tol, (int(Z.item()), golden["kept"], tol)
 
 
