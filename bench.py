@@ -597,7 +597,8 @@ def bench_rotation(ctx, s, sc, steps: int = 300, iters: int = 500, cpu_budget: f
 
 
 def traffic_entry(path: str):
-    """HBM bytes per launch of the Gram pass from a committed rocprofv3
+    """HBM bytes per fm_reweight_build call (its three kernels: FETCH_SIZE
+    and WRITE_SIZE scaled by a plain copy's) from a committed rocprofv3
     counter summary, if it was taken on the current Gram kernel source."""
     try:
         with open(path) as f:
@@ -606,7 +607,7 @@ def traffic_entry(path: str):
         return None
     if t.get("gram_hip_sha256") != _file_sha(GRAM_SRC):
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_call")
 
 
 def load_golden(name: str, sc, coords_digest) -> dict:
@@ -695,6 +696,7 @@ def solve_leg(ctx, sc, uv_dev, golden, steps: int, warmup: int, label: str) -> d
     iters = sched.iters * steps
     return {
         "scene": s, "p0": p0, "theta0": theta0, "sched": sched, "wall": wall, "passed": passed,
+        "gram_elem": torch.empty((), dtype=sched.gram_dtype).element_size(),
         "bracket_s": call_ms / 1e3 / max(n_call, 1),
         "call_s": (ess_ms + pass_ms + fin_ms) / 1e3 / max(n_call, 1), "pass_s": pass_ms / 1e3 / max(n_pass, 1),
         "ess_s": ess_ms / 1e3 / max(n_ess, 1), "fin_s": fin_ms / 1e3 / max(n_fin, 1), "n_call": n_call,
@@ -813,8 +815,9 @@ def main() -> int:
     M, P, N = sc.num_matches, sc.num_pairs, sc.num_cams
     call_s = leg["call_s"]
     # algorithmic bytes of one fm_reweight_build call: the BF16 coordinates,
-    # the pair offsets, the poses, the FP64 Grams written
-    alg_bytes = 8.0 * M + (8.0 + 288.0) * P + 36.0 * N
+    # the pair offsets, the poses, the Grams written (36 values per pair in
+    # the schedule's Gram precision)
+    alg_bytes = 8.0 * M + (8.0 + 36.0 * leg["gram_elem"]) * P + 36.0 * N
     alg_ops = VALU_PER_MATCH_BF16 * M
     copy_gbps = measure_copy_gbps(ctx.device)
     hbm = alg_bytes / call_s / 1e9
@@ -883,7 +886,7 @@ def bench_medium(ctx, args) -> dict:
     golden = load_golden("medium", sc, dig)
     leg = solve_leg(ctx, sc, uv_host.to(ctx.device).contiguous(), golden, args.steps, args.warmup, "medium")
     M, P = sc.num_matches, sc.num_pairs
-    alg_bytes = 16.0 * M + (8.0 + 288.0) * P + 36.0 * sc.num_cams
+    alg_bytes = 16.0 * M + (8.0 + 36.0 * leg["gram_elem"]) * P + 36.0 * sc.num_cams
     out = {
         "matches_per_s": M / leg["call_s"] if leg["passed"] else 0.0,
         "gram_call_us": leg["call_s"] * 1e6,
