@@ -112,7 +112,7 @@ struct fm_scene {
   double* rot = nullptr;          // [2, N, 9] rotations of the current poses (fused solve; two buffers)
   float* params_alt = nullptr;    // [N, 10] second parameter buffer of the camera loops ([N, 9] poses, then [N] focal scales)
   int64_t loss_part_cap = 0;
-  unsigned* bar = nullptr;        // [kBarWords] grid barrier of the persistent loops (layout at grid_barrier)
+  unsigned* bar = nullptr;        // [kBarWords] grid barriers of the persistent loops (layout at kBarWords)
   int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
   // translation averaging workspace, grown on demand by the translation calls
   int32_t ta_runs_cap = 0;        // runs the workspace holds
@@ -195,12 +195,52 @@ __device__ inline void gs_matrix(const Gs& g, double R[3][3]) {
   }
 }
 
+// Reads of arrays that other workgroups write while a persistent launch
+// runs, between two grid_sync calls (SH = true): buffer loads with the sc0
+// cache policy, which bypass the CU's L1 (grid_sync does not invalidate the
+// L1s) and are served by the XCD's L2, which grid_sync writes back and
+// invalidates once per XCD.  Byte offsets are 32-bit: arrays below 2 GiB.
+// SH = false: plain loads.
+constexpr int kBufWord3 = 0x00020000;   // buffer resource word 3 for raw loads on gfx9
+constexpr int kSc0 = 1;                 // cache-policy bits of the buffer-load builtins: sc0
+
+template <bool SH, typename T>
+struct Arr;
+
+template <typename T>
+struct Arr<false, T> {
+  const T* p;
+  __device__ explicit Arr(const T* q) : p(q) {}
+  __device__ T operator[](int64_t i) const { return p[i]; }
+  __device__ float4 f4(int64_t i) const { return reinterpret_cast<const float4*>(p + i)[0]; }
+};
+
+template <typename T>
+struct Arr<true, T> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ explicit Arr(const T* q)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q), 0, 0x7fffffff, kBufWord3)) {}
+  __device__ T operator[](int64_t i) const {
+    const int off = (int)(i * (int64_t)sizeof(T));
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kSc0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kSc0));
+  }
+  // 16 bytes from element i on (16-byte aligned)
+  __device__ float4 f4(int64_t i) const {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * (int64_t)sizeof(T)), 0, kSc0));
+  }
+};
+
+template <bool SH = false>
 __device__ inline void load_pose(const float* params, int c, double a1[3], double a2[3], double t[3]) {
-  const float* p = params + (int64_t)c * 9;
+  const Arr<SH, float> p(params);
+  const int64_t b = (int64_t)c * 9;
   for (int k = 0; k < 3; ++k) {
-    a1[k] = (double)p[k];
-    a2[k] = (double)p[3 + k];
-    t[k] = (double)p[6 + k];
+    a1[k] = (double)p[b + k];
+    a2[k] = (double)p[b + 3 + k];
+    t[k] = (double)p[b + 6 + k];
   }
 }
 
@@ -275,19 +315,32 @@ __device__ __host__ constexpr int mono_q(int a, int c) {
 }
 
 // Incidence list of one camera as one 16-lane row reads it: the list bounds
-// and this lane's first four entries (q = lo + l16 + 16 j; -1 past the end).
-// Static during a solve, so the fused loop reads it once.
-struct RowList {
-  int lo, hi, it[4];
+// and this lane's first NE entries (q = lo + l16 + 16 j; -1 past the end).
+// Static during a solve, so the fused loops read it once.
+template <int NE>
+struct RowListN {
+  int lo, hi, it[NE];
 };
+using RowList = RowListN<4>;
 
-__device__ inline RowList row_list(const int32_t* __restrict__ cam_ptr, const int32_t* __restrict__ cam_items, int c,
-                                   int l16) {
-  RowList L;
+template <int NE = 4>
+__device__ inline RowListN<NE> row_list(const int32_t* __restrict__ cam_ptr, const int32_t* __restrict__ cam_items,
+                                        int c, int l16) {
+  RowListN<NE> L;
   L.lo = cam_ptr[c];
   L.hi = cam_ptr[c + 1];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) L.it[j] = L.lo + l16 + 16 * j < L.hi ? cam_items[L.lo + l16 + 16 * j] : -1;
+  for (int j = 0; j < NE; ++j) L.it[j] = L.lo + l16 + 16 * j < L.hi ? cam_items[L.lo + l16 + 16 * j] : -1;
+  return L;
+}
+
+// A row list with no entries (rows past the last camera).
+template <int NE = 4>
+__device__ inline RowListN<NE> empty_row_list() {
+  RowListN<NE> L;
+  L.lo = L.hi = 0;
+#pragma unroll
+  for (int j = 0; j < NE; ++j) L.it[j] = -1;
   return L;
 }
 
@@ -319,9 +372,12 @@ __device__ inline void rs_stage_d(const double (&in)[S], double (&out)[(S + 1) /
   }
 }
 
+// Adds one side (12 floats) of a pair record to acc (SH: see Arr).
+template <bool SH = false>
 __device__ inline void add_record(const float* __restrict__ contrib, int item, double acc[12]) {
-  const float4* src = reinterpret_cast<const float4*>(contrib + (int64_t)(item >> 1) * 24 + (item & 1) * 12);
-  const float4 r0 = src[0], r1 = src[1], r2 = src[2];
+  const Arr<SH, float> c(contrib);
+  const int64_t b = (int64_t)(item >> 1) * 24 + (item & 1) * 12;
+  const float4 r0 = c.f4(b), r1 = c.f4(b + 4), r2 = c.f4(b + 8);
   acc[0] += r0.x; acc[1] += r0.y; acc[2] += r0.z; acc[3] += r0.w;
   acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
   acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
@@ -398,14 +454,15 @@ __device__ inline void row_sum12(double acc[12], int lane) {
 }
 
 // Summed records of one camera in every lane of its row.
+template <bool SH = false>
 __device__ inline void row_camera_sums(const RowList& L, const int32_t* __restrict__ cam_items,
                                        const float* __restrict__ contrib, int lane, double acc[12]) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
-    if (L.it[j] >= 0) add_record(contrib, L.it[j], acc);
-  for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record(contrib, cam_items[q], acc);
+    if (L.it[j] >= 0) add_record<SH>(contrib, L.it[j], acc);
+  for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record<SH>(contrib, cam_items[q], acc);
   row_sum12(acc, lane);
 }
 
@@ -455,22 +512,62 @@ __device__ inline float adam_update(float p, float g, float& m, float& v, double
 // street graph (185k pairs, uneven degrees) 44.3 vs 41.0.
 constexpr int64_t kCamLoopMaxPairs = 131072;
 
+// Workgroup count from which the fused epipolar loops synchronise with the
+// per-XCD grid_sync instead of the flat grid_barrier.  Per iteration, flat
+// vs per-XCD: large street graph, pair loop at 192 workgroups 37.0 vs
+// 29.2 us; camera loop at 256 workgroups 38.2 vs 35.9 us; medium helix
+// scene, camera loop at 25 workgroups 9.75 vs 11.15 us, pair loop at 16 and
+// 64 workgroups 14.9 vs 17.2 and 15.5 vs 17.3 us (the second level of
+// notification costs more than the fences it saves on small grids).
+constexpr int64_t kXcdSyncMinBlocks = 128;
+
 constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
-// Words of `bar`: arrival count, generation, failure flag of the running
-// launch, failure total since the last query, one 128-byte line each.
-constexpr int kBarWords = 128;
+// XCD slots of the grid_sync barrier (the XCC_ID hardware field is 4 bits).
+constexpr int kMaxXcd = 16;
+// Words of `bar`, one 128-byte line each: arrival count, generation, failure
+// flag of the running launch, failure total since the last query; then per
+// XCD the arrival count and generation of grid_sync and the number of the
+// launch's workgroups on that XCD.
+constexpr int kBarXcdCount = 128;
+constexpr int kBarXcdGen = kBarXcdCount + 32 * kMaxXcd;
+constexpr int kBarXcdReg = kBarXcdGen + 32 * kMaxXcd;
+constexpr int kBarWords = kBarXcdReg + 32 * kMaxXcd;
 
-// Grid barrier of the persistent solves (epipolar and translation loops).
-// Thread 0 of each workgroup makes the workgroup's writes visible
-// (agent-scope release), counts itself in, and waits for the generation word
-// to move; the last to arrive acquires the others' writes, re-arms the
-// counter and moves the generation.  All atomics are relaxed and
-// agent-scoped; the fences carry the ordering.  The wait is bounded: if it
-// expires (the workgroups were not all resident), the launch's failure flag
-// and the scene's failure total are raised, every later barrier of the
-// launch returns at once and the host reads the total with
-// fm_solve_barrier_failures.
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
+constexpr int kWaitVmcnt0 = 0x0F70;
 
+// Bounded wait of thread 0 for the word w to move from g.  If the wait
+// expires (the workgroups were not all resident) or another workgroup has
+// raised the launch's failure flag, it raises the flag and the scene's
+// failure total; every later barrier of the launch then returns at once and
+// the host reads the total with fm_solve_barrier_failures.
+__device__ inline void bar_wait(unsigned* __restrict__ bar, unsigned* w, unsigned g) {
+  unsigned* fail = bar + 64;
+  bool moved = false;
+  for (unsigned outer = 0; outer < kBarSpinOuter && !moved; ++outer) {
+#pragma unroll 1
+    for (int i = 0; i < 256; ++i) {
+      if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) {
+        moved = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!moved && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+  }
+  if (!moved) {
+    __hip_atomic_fetch_add(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(bar + 96, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Grid barrier of the persistent loops that share data through plain loads
+// and stores.  Thread 0 of each workgroup makes the workgroup's writes
+// visible (agent-scope release: writes back the dirty lines of its XCD's L2),
+// counts itself in and waits for the generation word to move; the last to
+// arrive re-arms the counter and moves the generation; each then acquires
+// (invalidates its XCD's L2 and its CU's L1).  All atomics are relaxed and
+// agent-scoped; the fences carry the ordering.
 __device__ inline void grid_barrier(unsigned* __restrict__ bar) {
   unsigned* count = bar;
   unsigned* gen = bar + 32;
@@ -485,24 +582,80 @@ __device__ inline void grid_barrier(unsigned* __restrict__ bar) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_store(gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      bool moved = false;
-      for (unsigned outer = 0; outer < kBarSpinOuter && !moved; ++outer) {
-#pragma unroll 1
-        for (int i = 0; i < 256; ++i) {
-          if (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) {
-            moved = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        if (!moved && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-      }
-      if (!moved) {
-        __hip_atomic_fetch_add(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(bar + 96, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      bar_wait(bar, gen, g);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// XCD of the running workgroup (hardware register XCC_ID, bits 3:0) and,
+// after xcd_register, the number of the launch's workgroups on it and the
+// number of XCDs that hold any.
+struct XcdSync {
+  unsigned x, nx, nact;
+};
+
+__device__ inline unsigned xcc_id() {
+  // s_getreg_b32 hwreg(HW_REG_XCC_ID = 20, offset 0, size 4)
+  return (unsigned)__builtin_amdgcn_s_getreg(20 | (3 << 11)) & (kMaxXcd - 1);
+}
+
+// Called once by every thread at the start of a launch that uses grid_sync
+// (the registration counters were cleared by fm_bar_reset); ends with a
+// grid_barrier.
+__device__ inline XcdSync xcd_register(unsigned* __restrict__ bar) {
+  XcdSync xs;
+  xs.x = xcc_id();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(bar + kBarXcdReg + 32 * xs.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  grid_barrier(bar);
+  xs.nx = 0;
+  xs.nact = 0;
+  for (int k = 0; k < kMaxXcd; ++k) {
+    const unsigned n = __hip_atomic_load(bar + kBarXcdReg + 32 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((unsigned)k == xs.x) xs.nx = n;
+    xs.nact += n > 0u ? 1u : 0u;
+  }
+  return xs;
+}
+
+// Grid barrier for loops whose data shared between workgroups is written
+// with plain stores and read through Arr<true, T> (sc0 loads: L1 bypassed,
+// served by the XCD's L2).  Cache maintenance runs once per XCD instead of
+// once per workgroup: each thread waits for its own stores to reach the L2;
+// the workgroups of an XCD count in on the XCD's counter; the last of them
+// writes the XCD's L2 back (agent-scope release), meets the other XCDs' last
+// arrivals on the top-level counter, invalidates the XCD's L2 (agent-scope
+// acquire; complete before it moves on) and moves the XCD's generation word,
+// which the XCD's other workgroups wait for.
+__device__ inline void grid_sync(unsigned* __restrict__ bar, const XcdSync& xs) {
+  unsigned* fail = bar + 64;
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  __syncthreads();
+  if (threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    unsigned* xc = bar + kBarXcdCount + 32 * xs.x;
+    unsigned* xg = bar + kBarXcdGen + 32 * xs.x;
+    const unsigned g = __hip_atomic_load(xg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == xs.nx - 1) {
+      __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      unsigned* count = bar;
+      unsigned* gen = bar + 32;
+      const unsigned gt = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == xs.nact - 1) {
+        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        __hip_atomic_store(gen, gt + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        bar_wait(bar, gen, gt);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __hip_atomic_store(xg, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      bar_wait(bar, xg, g);
+    }
   }
   __syncthreads();
 }

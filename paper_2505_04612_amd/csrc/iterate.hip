@@ -26,25 +26,32 @@ __device__ inline double load_w(const WT* p, int k) {
 // Loss term and adjoint record of pair n.  rec = [dL/dR_i (3x3 row-major),
 // dL/dt_i, dL/dR_j, dL/dt_j] as float32.
 // `rot` (optional) holds each camera's rotation from Gram-Schmidt of the
-// current parameters, so pairs need not repeat it.
-template <typename WT>
+// current parameters, so pairs need not repeat it.  SH: parameters and
+// rotations are read through Arr<true, T> (the persistent loops, where other
+// workgroups wrote them since the last grid_sync); the Gram is constant.
+template <typename WT, bool SH = false>
 __device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot, int ci,
                                            int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
                                            float* __restrict__ rec) {
   double a1[3], a2[3], ti[3], tj[3];
   double Ri[3][3], Rj[3][3], Rij[3][3], th[3], E[3][3];
-  load_pose(params, ci, a1, a2, ti);
-  load_pose(params, cj, a1, a2, tj);
   if (rot) {
+    const Arr<SH, float> P(params);
+    const Arr<SH, double> R(rot);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ti[k] = (double)P[(int64_t)ci * 9 + 6 + k];
+      tj[k] = (double)P[(int64_t)cj * 9 + 6 + k];
+    }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      Ri[k / 3][k % 3] = rot[(int64_t)ci * 9 + k];
-      Rj[k / 3][k % 3] = rot[(int64_t)cj * 9 + k];
+      Ri[k / 3][k % 3] = R[(int64_t)ci * 9 + k];
+      Rj[k / 3][k % 3] = R[(int64_t)cj * 9 + k];
     }
   } else {
-    load_pose(params, ci, a1, a2, ti);
+    load_pose<SH>(params, ci, a1, a2, ti);
     gs_matrix(gs_forward(a1, a2), Ri);
-    load_pose(params, cj, a1, a2, tj);
+    load_pose<SH>(params, cj, a1, a2, tj);
     gs_matrix(gs_forward(a1, a2), Rj);
   }
   const double ns = pair_essential(Ri, ti, Rj, tj, Rij, th, E);
@@ -91,16 +98,18 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
 
 // Pair phase over pairs [first, P) with stride `stride`; writes the records
 // and returns this thread's loss sum (float64, in pair order).  The cameras
-// of the first pair come in registers (ci0, cj0), read once per solve.
-template <typename WT>
+// of the first two pairs come in registers (ci0, cj0 and ci1, cj1), read
+// once per solve.  SH: the poses are read through Arr<true, T>.
+template <typename WT, bool SH = false>
 __device__ inline double pair_phase(const float* params, const double* rot, const int32_t* cams, const WT* W36,
                                     int64_t P, double two_inv_Z, float* contrib, int64_t first, int64_t stride,
-                                    int ci0, int cj0) {
+                                    int ci0, int cj0, int ci1 = 0, int cj1 = 0) {
   double sum = 0.0;
   for (int64_t n = first; n < P; n += stride) {
     float rec[24];
-    const int ci = n == first ? ci0 : cams[2 * n], cj = n == first ? cj0 : cams[2 * n + 1];
-    sum += pair_loss_adjoint(params, rot, ci, cj, W36, n, two_inv_Z, rec);
+    const bool held0 = n == first, held1 = n == first + stride;
+    const int ci = held0 ? ci0 : (held1 ? ci1 : cams[2 * n]), cj = held0 ? cj0 : (held1 ? cj1 : cams[2 * n + 1]);
+    sum += pair_loss_adjoint<WT, SH>(params, rot, ci, cj, W36, n, two_inv_Z, rec);
     float4* dst = reinterpret_cast<float4*>(contrib + n * 24);
 #pragma unroll
     for (int k = 0; k < 6; ++k) dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
@@ -274,6 +283,11 @@ __global__ void k_bar_reset(unsigned* __restrict__ bar) {
     bar[0] = 0u;
     bar[64] = 0u;
   }
+  // grid_sync's per-XCD arrival counts and workgroup registrations
+  if (threadIdx.x < kMaxXcd) {
+    bar[kBarXcdCount + 32 * threadIdx.x] = 0u;
+    bar[kBarXcdReg + 32 * threadIdx.x] = 0u;
+  }
 }
 
 hipError_t fm_bar_reset(unsigned* bar, hipStream_t st) {
@@ -304,7 +318,52 @@ struct SolveArgs {
   int64_t lr_step0, lr_total, adam_step0;
 };
 
-template <typename WT>
+// Incidence entries per lane that the pair loop's camera rows hold in
+// registers: 6 x 16 covers cameras of up to 96 pairs with one round of
+// record loads (entries past them are read in further rounds).
+constexpr int kRowItems = 6;
+
+// Summed records of one camera in every lane of its row: the records of the
+// held entries are all loaded before any is added (so their loads are in
+// flight together), then added in entry order, then the rest of the list.
+template <bool SH, int NE>
+__device__ inline void row_camera_sums_held(const RowListN<NE>& L, const int32_t* __restrict__ cam_items,
+                                            const float* __restrict__ contrib, int lane, double acc[12]) {
+  const Arr<SH, float> c(contrib);
+  float4 r[NE][3];
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    r[j][0] = r[j][1] = r[j][2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (L.it[j] >= 0) {
+      const int64_t b = (int64_t)(L.it[j] >> 1) * 24 + (L.it[j] & 1) * 12;
+      r[j][0] = c.f4(b);
+      r[j][1] = c.f4(b + 4);
+      r[j][2] = c.f4(b + 8);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    acc[0] += r[j][0].x; acc[1] += r[j][0].y; acc[2] += r[j][0].z; acc[3] += r[j][0].w;
+    acc[4] += r[j][1].x; acc[5] += r[j][1].y; acc[6] += r[j][1].z; acc[7] += r[j][1].w;
+    acc[8] += r[j][2].x; acc[9] += r[j][2].y; acc[10] += r[j][2].z; acc[11] += r[j][2].w;
+  }
+  for (int q = L.lo + 16 * NE + (lane & 15); q < L.hi; q += 16) add_record<SH>(contrib, cam_items[q], acc);
+  row_sum12(acc, lane);
+}
+
+// Grid barrier of the fused loops: per-XCD (grid_sync, with the shared
+// arrays read through Arr<true, T>) or flat (grid_barrier, plain reads).
+template <bool XS>
+__device__ inline void loop_sync(unsigned* __restrict__ bar, const XcdSync& xs) {
+  if constexpr (XS)
+    grid_sync(bar, xs);
+  else
+    grid_barrier(bar);
+}
+
+template <typename WT, bool XS>
 __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   __shared__ double lds[kSolveBlock / 64];
   const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
@@ -316,22 +375,27 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   // static data of this thread's first pair and this wavefront's first
   // camera, read once instead of once per iteration
   const int ci0 = gtid < a.P ? a.cams[2 * gtid] : 0, cj0 = gtid < a.P ? a.cams[2 * gtid + 1] : 0;
+  const int64_t g1 = gtid + gsize;
+  const int ci1 = g1 < a.P ? a.cams[2 * g1] : 0, cj1 = g1 < a.P ? a.cams[2 * g1 + 1] : 0;
   // cameras 4 gwave + row, then strided by 4 nwaves
   const int row = lane >> 4, l16 = lane & 15, base = lane & ~15;
   const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
-  RowList L0 = {0, 0, {-1, -1, -1, -1}};
-  if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
+  RowListN<kRowItems> L0 = empty_row_list<kRowItems>();
+  if (c_first < a.N) L0 = row_list<kRowItems>(a.cam_ptr, a.cam_items, (int)c_first, l16);
+  XcdSync xs = {0u, 0u, 0u};
+  if constexpr (XS) xs = xcd_register(a.bar);
   for (int k = 0; k < a.K; ++k) {
     // iteration 0 runs Gram-Schmidt per pair; later iterations read the
     // rotations the camera phase stored with the updated parameters
-    const double v = pair_phase(a.params, k > 0 ? a.rot : nullptr, a.cams, W36, a.P, 2.0 * iz, a.contrib, gtid,
-                                gsize, ci0, cj0);
+    const double v = pair_phase<WT, XS>(a.params, k > 0 ? a.rot : nullptr, a.cams, W36, a.P, 2.0 * iz, a.contrib,
+                                          gtid, gsize, ci0, cj0, ci1, cj1);
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
-    grid_barrier(a.bar);
+    loop_sync<XS>(a.bar, xs);
     if (a.loss_trace && gtid == 0) {
       double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += a.loss_part[b];
+      const Arr<XS, double> lp(a.loss_part);
+      for (int b = 0; b < (int)gridDim.x; ++b) s += lp[b];
       a.loss_trace[k] = s * iz;
     }
     const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
@@ -345,15 +409,17 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
       // parameters and moments first (they do not depend on the records),
       // so their loads overlap the record loads
       float p0 = 0.0f, mq = 0.0f, vq = 0.0f;
+      // (m, v: only this lane reads and writes them during the launch)
       if (live && l16 < 9) {
-        p0 = a.params[c * 9 + l16];
+        p0 = Arr<XS, float>(a.params)[c * 9 + l16];
         mq = a.m[c * 9 + l16];
         vq = a.v[c * 9 + l16];
       }
       double acc[12];
-      const RowList L = c0 == 4 * gwave ? L0 : (live ? row_list(a.cam_ptr, a.cam_items, (int)c, l16)
-                                                     : RowList{0, 0, {-1, -1, -1, -1}});
-      row_camera_sums(L, a.cam_items, a.contrib, lane, acc);
+      const RowListN<kRowItems> L =
+          c0 == 4 * gwave ? L0
+                          : (live ? row_list<kRowItems>(a.cam_ptr, a.cam_items, (int)c, l16) : empty_row_list<kRowItems>());
+      row_camera_sums_held<XS, kRowItems>(L, a.cam_items, a.contrib, lane, acc);
       double a1[3], a2[3], g[9];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -389,7 +455,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
         a.rot[c * 9 + l16] = rv;
       }
     }
-    grid_barrier(a.bar);
+    loop_sync<XS>(a.bar, xs);
   }
 }
 
@@ -442,7 +508,7 @@ __device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float 
   }
 }
 
-template <typename WT>
+template <typename WT, bool XS>
 __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
   __shared__ double lds[kSolveBlock / 64];
   const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
@@ -473,7 +539,11 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
     const float p0 = a.params[c * 9 + kq];
     cam_store_rot(a.rot, c, p0, lane);
   }
-  grid_barrier(a.bar);
+  XcdSync xs = {0u, 0u, 0u};
+  if constexpr (XS)
+    xs = xcd_register(a.bar);
+  else
+    grid_barrier(a.bar);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
     const float* pr = rb ? a.params_alt : a.params;
@@ -488,8 +558,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
     // run with every lane present
     for (int64_t c = gwave; c < a.N; c += nwaves) {
       const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
-      // the camera's own parameters and moments (lanes 9..63 read entry 8)
-      const float p0 = pr[c * 9 + kq];
+      // the camera's own parameters and moments (lanes 9..63 read entry 8;
+      // m and v are read and written by this wavefront alone)
+      const float p0 = Arr<XS, float>(pr)[c * 9 + kq];
       float mq = a.m[c * 9 + kq], vq = a.v[c * 9 + kq];
       double acc[12];
 #pragma unroll
@@ -501,7 +572,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
         const int side = first ? side0 : item & 1;
         const int ci = first ? ci0 : a.cams[2 * n], cj = first ? cj0 : a.cams[2 * n + 1];
         float rec[24];
-        const double l = pair_loss_adjoint(pr, rr, ci, cj, W36, n, 2.0 * iz, rec);
+        const double l = pair_loss_adjoint<WT, XS>(pr, rr, ci, cj, W36, n, 2.0 * iz, rec);
         if (side == 0) lsum += l;   // each pair's loss once, from its first camera
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);
@@ -527,17 +598,18 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
       const double t = block_sum(lsum, lds);
       if (threadIdx.x == 0) a.loss_part[rb * gridDim.x + blockIdx.x] = t;
     }
-    grid_barrier(a.bar);
+    loop_sync<XS>(a.bar, xs);
     if (a.loss_trace && gtid == 0) {
       double sum = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) sum += a.loss_part[rb * gridDim.x + b];
+      const Arr<XS, double> lp(a.loss_part);
+      for (int b = 0; b < (int)gridDim.x; ++b) sum += lp[rb * gridDim.x + b];
       a.loss_trace[k] = sum * iz;
     }
   }
   // after an odd number of iterations the latest parameters are in buffer 1
   if (a.K & 1) {
     for (int64_t c = gwave; c < a.N; c += nwaves)
-      if (lane < 9) a.params[c * 9 + lane] = a.params_alt[c * 9 + lane];
+      if (lane < 9) a.params[c * 9 + lane] = Arr<XS, float>(a.params_alt)[c * 9 + lane];
   }
 }
 
@@ -552,18 +624,36 @@ static fm_status solve_checks(fm_ctx* ctx, fm_scene* s, const float* params, con
   return rc;
 }
 
+// Co-resident workgroups of the fused loops: the smallest occupancy over
+// every instantiation, times the CU count.
+template <typename K>
+static bool occ_min(K kernel, int& per_cu) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kSolveBlock, 0) != hipSuccess) return false;
+  if (n < per_cu) per_cu = n;
+  return true;
+}
+
 int fm_solve_coop_blocks(fm_ctx* ctx) {
-  int per_cu64 = 0, per_cu32 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_solve<double>, kSolveBlock, 0) != hipSuccess)
+  int per_cu = 1 << 20;
+  if (!occ_min(k_solve<double, false>, per_cu) || !occ_min(k_solve<float, false>, per_cu) ||
+      !occ_min(k_solve<double, true>, per_cu) || !occ_min(k_solve<float, true>, per_cu) ||
+      !occ_min(k_solve_cam<double, false>, per_cu) || !occ_min(k_solve_cam<float, false>, per_cu) ||
+      !occ_min(k_solve_cam<double, true>, per_cu) || !occ_min(k_solve_cam<float, true>, per_cu))
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, k_solve<float>, kSolveBlock, 0) != hipSuccess) return 0;
-  int per_cu = per_cu64 < per_cu32 ? per_cu64 : per_cu32;
-  int pc64 = 0, pc32 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc64, k_solve_cam<double>, kSolveBlock, 0) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc32, k_solve_cam<float>, kSolveBlock, 0) != hipSuccess) return 0;
-  if (pc64 < per_cu) per_cu = pc64;
-  if (pc32 < per_cu) per_cu = pc32;
   return per_cu * ctx->num_cu;
+}
+
+// Instantiation of a fused loop (camera or pair loop) for the Gram dtype
+// and the barrier kind (per-XCD from kXcdSyncMinBlocks workgroups on).
+static const void* loop_kernel(bool cam, fm_dtype wdt, int64_t blocks) {
+  const bool xs = blocks >= kXcdSyncMinBlocks;
+  if (cam) {
+    if (wdt == FM_F64) return xs ? (const void*)k_solve_cam<double, true> : (const void*)k_solve_cam<double, false>;
+    return xs ? (const void*)k_solve_cam<float, true> : (const void*)k_solve_cam<float, false>;
+  }
+  if (wdt == FM_F64) return xs ? (const void*)k_solve<double, true> : (const void*)k_solve<double, false>;
+  return xs ? (const void*)k_solve<float, true> : (const void*)k_solve<float, false>;
 }
 
 extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36, fm_dtype wdt, float* params,
@@ -625,21 +715,16 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
     void* cargs[] = {&ca};
     {
     fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
-    hipError_t e = wdt == FM_F64
-                       ? hipLaunchCooperativeKernel((const void*)k_solve_cam<double>, dim3((unsigned)want_cam),
-                                                    dim3(kSolveBlock), cargs, 0, (hipStream_t)stream)
-                       : hipLaunchCooperativeKernel((const void*)k_solve_cam<float>, dim3((unsigned)want_cam),
-                                                    dim3(kSolveBlock), cargs, 0, (hipStream_t)stream);
+    hipError_t e = hipLaunchCooperativeKernel(loop_kernel(true, wdt, want_cam), dim3((unsigned)want_cam),
+                                              dim3(kSolveBlock), cargs, 0, (hipStream_t)stream);
     if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
     }
     return solve_checks(ctx, s, params, loss_trace, K, (hipStream_t)stream);
   }
   {
   fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
-  hipError_t e = wdt == FM_F64 ? hipLaunchCooperativeKernel((const void*)k_solve<double>, dim3((unsigned)want),
-                                                           dim3(kSolveBlock), args, 0, (hipStream_t)stream)
-                               : hipLaunchCooperativeKernel((const void*)k_solve<float>, dim3((unsigned)want),
-                                                           dim3(kSolveBlock), args, 0, (hipStream_t)stream);
+  hipError_t e = hipLaunchCooperativeKernel(loop_kernel(false, wdt, want), dim3((unsigned)want), dim3(kSolveBlock),
+                                            args, 0, (hipStream_t)stream);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
   }
   return solve_checks(ctx, s, params, loss_trace, K, (hipStream_t)stream);

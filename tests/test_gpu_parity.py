@@ -300,13 +300,16 @@ def test_fused_solve_grid_invariance(fm, ctx, name):
     """The fused loop's camera sums run in a fixed order, so the parameters
     after K iterations are bit-identical for any number of workgroups (1 to
     beyond the automatic choice): every grid barrier must publish every
-    workgroup's records and poses before the next phase reads them."""
+    workgroup's records and poses before the next phase reads them.  Grids
+    of 128 workgroups and more synchronise per XCD (one L2 write-back and
+    invalidation per XCD, shared arrays read past the L1), smaller ones with
+    the flat barrier, so the comparison also pins one against the other."""
     sc = scene(name)
     s = _scene_on_gpu(fm, ctx, sc, torch.float64 if name == "tiny" else torch.float32)
     W64, _ = fm.build_pair_grams(s)
     th = torch.from_numpy(_theta(sc)).to(ctx.device)
     results = []
-    for blocks in (1, 2, 5, 16, 37):
+    for blocks in (1, 2, 5, 16, 37, 128, 200, 256):
         p = th.clone()
         m = torch.zeros_like(p)
         v = torch.zeros_like(p)
