@@ -162,24 +162,24 @@ static inline unsigned grid_for(int64_t n, int block) {
 // ------------------------------------------------------------------ device helpers
 
 // Gram-Schmidt of the 6D rotation parameters (a1, a2) into the columns
-// b1, b2, b3 of R, in float64.  Also returns |a1|, |u2| and b1.a2 for the
-// adjoint.
+// b1, b2, b3 of R, in float64.  Also returns |a1|, |u2|, their reciprocals
+// and b1.a2 for the adjoint.
 struct Gs {
   double b1[3], b2[3], b3[3];
-  double n1, n2, d12;
+  double n1, n2, r1, r2, d12;
 };
 
 __device__ inline Gs gs_forward(const double a1[3], const double a2[3]) {
   Gs g;
   g.n1 = sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]);
-  double r1 = 1.0 / g.n1;
-  for (int k = 0; k < 3; ++k) g.b1[k] = a1[k] * r1;
+  g.r1 = 1.0 / g.n1;
+  for (int k = 0; k < 3; ++k) g.b1[k] = a1[k] * g.r1;
   g.d12 = g.b1[0] * a2[0] + g.b1[1] * a2[1] + g.b1[2] * a2[2];
   double u2[3];
   for (int k = 0; k < 3; ++k) u2[k] = a2[k] - g.d12 * g.b1[k];
   g.n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
-  double r2 = 1.0 / g.n2;
-  for (int k = 0; k < 3; ++k) g.b2[k] = u2[k] * r2;
+  g.r2 = 1.0 / g.n2;
+  for (int k = 0; k < 3; ++k) g.b2[k] = u2[k] * g.r2;
   g.b3[0] = g.b1[1] * g.b2[2] - g.b1[2] * g.b2[1];
   g.b3[1] = g.b1[2] * g.b2[0] - g.b1[0] * g.b2[2];
   g.b3[2] = g.b1[0] * g.b2[1] - g.b1[1] * g.b2[0];
@@ -422,7 +422,7 @@ __device__ inline void gs_adjoint(const double acc[12], const double a1[3], cons
   const double b2g2 = f.b2[0] * g2[0] + f.b2[1] * g2[1] + f.b2[2] * g2[2];
   double gu[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) gu[k] = (g2[k] - b2g2 * f.b2[k]) / f.n2;
+  for (int k = 0; k < 3; ++k) gu[k] = (g2[k] - b2g2 * f.b2[k]) * f.r2;
   const double b1gu = f.b1[0] * gu[0] + f.b1[1] * gu[1] + f.b1[2] * gu[2];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -433,7 +433,7 @@ __device__ inline void gs_adjoint(const double acc[12], const double a1[3], cons
   const double b1g1 = f.b1[0] * g1[0] + f.b1[1] * g1[1] + f.b1[2] * g1[2];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    grad[k] = (g1[k] - b1g1 * f.b1[k]) / f.n1;
+    grad[k] = (g1[k] - b1g1 * f.b1[k]) * f.r1;
     grad[6 + k] = acc[9 + k];
   }
 }
@@ -489,14 +489,17 @@ __device__ inline double block_sum(double v, double* lds) {
 }
 
 // One Adam update (Kingma & Ba, bias-corrected) of a float32 value; the
-// arithmetic is float64, the stored moments float32.
+// arithmetic is float64, the stored moments float32.  The bias corrections
+// are applied as products with their reciprocals (uniform over a step, so
+// the persistent loops compute them once per iteration).
 __device__ inline float adam_update(float p, float g, float& m, float& v, double lr, double b1, double b2,
                                     double eps, double bc1, double bc2) {
   const double md = b1 * (double)m + (1.0 - b1) * (double)g;
   const double vd = b2 * (double)v + (1.0 - b2) * (double)g * (double)g;
   m = (float)md;
   v = (float)vd;
-  return (float)((double)p - lr * (md / bc1) / (sqrt(vd / bc2) + eps));
+  const double ib1 = 1.0 / bc1, ib2 = 1.0 / bc2;
+  return (float)((double)p - lr * (md * ib1) / (sqrt(vd * ib2) + eps));
 }
 
 // Pair count below which the epipolar persistent loop runs camera by camera
