@@ -488,6 +488,31 @@ __device__ inline double block_sum(double v, double* lds) {
   return t;
 }
 
+// Step schedule of a persistent Adam loop: the learning-rate fraction
+// exp(log_frac (lr_step0 + k) / lr_total) and the powers b1^s, b2^s of the
+// bias corrections (s = adam_step0 + k + 1) for k = 0, 1, ..., evaluated
+// with exp/pow at the launch's first step and then advanced by one product
+// each per step (over a launch's steps the running products stay within
+// ~1e-13 relative of the direct formulas; the direct ones cost two float64
+// pow and an exp per lane per iteration).
+struct StepSched {
+  double frac, p1, p2;
+  double dfrac, b1, b2;
+  __device__ StepSched(double log_frac, int64_t lr_step0, int64_t lr_total, int64_t adam_step0, double b1_,
+                       double b2_)
+      : frac(exp(log_frac * (double)lr_step0 / (double)lr_total)),
+        p1(pow(b1_, (double)(adam_step0 + 1))),
+        p2(pow(b2_, (double)(adam_step0 + 1))),
+        dfrac(exp(log_frac / (double)lr_total)),
+        b1(b1_),
+        b2(b2_) {}
+  __device__ void next() {
+    frac *= dfrac;
+    p1 *= b1;
+    p2 *= b2;
+  }
+};
+
 // One Adam update (Kingma & Ba, bias-corrected) of a float32 value; the
 // arithmetic is float64, the stored moments float32.  The bias corrections
 // are applied as products with their reciprocals (uniform over a step, so

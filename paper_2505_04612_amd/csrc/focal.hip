@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
   const int64_t NR = (int64_t)a.N * 9;
   for (int64_t c = gwave; c < a.N; c += nwaves) fo_store_rot(a.rot, c, a.params[c * 9 + kq], lane);
   grid_barrier(a.bar);
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
     const float* pr = rb ? a.params_alt : a.params;
@@ -221,9 +222,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
     float* fw = rb ? a.phi : a.phi_alt;
     const double* rr = a.rot + rb * NR;
     double* rw = a.rot + (rb ^ 1) * NR;
-    const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double frac = sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     double lsum = 0.0;
     // the loop bound is uniform over the wavefront, so the wavefront sums
     // run with every lane present

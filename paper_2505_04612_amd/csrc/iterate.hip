@@ -384,6 +384,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   if (c_first < a.N) L0 = row_list<kRowItems>(a.cam_ptr, a.cam_items, (int)c_first, l16);
   XcdSync xs = {0u, 0u, 0u};
   if constexpr (XS) xs = xcd_register(a.bar);
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     // iteration 0 runs Gram-Schmidt per pair; later iterations read the
     // rotations the camera phase stored with the updated parameters
@@ -398,9 +399,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
       for (int b = 0; b < (int)gridDim.x; ++b) s += lp[b];
       a.loss_trace[k] = s * iz;
     }
-    const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double frac = sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     // the loop bound is uniform over the wavefront (rows past N idle), so
     // the row exchanges below always run with every lane present
     for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
@@ -544,15 +545,16 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
     xs = xcd_register(a.bar);
   else
     grid_barrier(a.bar);
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
     const float* pr = rb ? a.params_alt : a.params;
     float* pw = rb ? a.params : a.params_alt;
     const double* rr = a.rot + rb * NR;
     double* rw = a.rot + (rb ^ 1) * NR;
-    const double frac = exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double frac = sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     double lsum = 0.0;
     // the loop bound is uniform over the wavefront, so the wavefront sums
     // run with every lane present

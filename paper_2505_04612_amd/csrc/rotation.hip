@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
   RowList L0 = {0, 0, {-1, -1, -1, -1}};
   if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
   grid_barrier(a.bar);
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     double v = 0.0;
     for (int64_t n = gtid; n < a.P; n += gsize) {
@@ -215,9 +216,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
       for (int b = 0; b < (int)gridDim.x; ++b) s += a.part[b];
       a.trace[k] = s * a.invP;
     }
-    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double lr = a.lr * sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     // the loop bound is uniform over the wavefront (rows past N idle), so
     // the row exchanges always run with every lane present
     for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
@@ -292,15 +293,16 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
   // rotations of the initial parameters (buffer 0)
   for (int64_t c = gwave; c < a.N; c += nwaves) ra_store_rot(a.rot, c, a.params[6 * c + kq], 0, lane, true);
   grid_barrier(a.bar);
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
     const float* pr = rb ? a.alt : a.params;
     float* pw = rb ? a.params : a.alt;
     const double* rr = a.rot + rb * NR;
     double* rw = a.rot + (rb ^ 1) * NR;
-    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double lr = a.lr * sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     double lsum = 0.0;
     // the loop bound is uniform over the wavefront, so the wavefront sums
     // run with every lane present

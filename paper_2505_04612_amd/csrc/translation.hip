@@ -299,6 +299,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
   const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
   RowList L0 = {0, 0, {-1, -1, -1, -1}};
   if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     if (gtid < a.P) ta_pair_runs(a.centres, a.N, a.runs, a.P, gtid, ci0, cj0, d0, a.invP, a.rec);
     for (int64_t n = gtid + gsize; n < a.P; n += gsize) {
@@ -315,9 +316,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
         a.trace[(int64_t)r * a.K + k] = s * a.invP;
       }
     }
-    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double lr = a.lr * sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     // rows past N skip the camera work as a whole
     for (int64_t c0 = 4 * gwave; c0 < a.N; c0 += c_stride) {
       const int64_t c = c0 + row;
@@ -442,13 +443,14 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
   const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
   const int64_t RS = (int64_t)a.runs * a.part_stride;
   double* wl = a.trace ? wloss[wv] : nullptr;
+  StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
     const float* pr = rb ? a.alt : a.centres;
     float* pw = rb ? a.centres : a.alt;
-    const double lr = a.lr * exp(a.log_frac * (double)(a.lr_step0 + k) / (double)a.lr_total);
-    const double step = (double)(a.adam_step0 + k + 1);
-    const double bc1 = 1.0 - pow(a.b1, step), bc2 = 1.0 - pow(a.b2, step);
+    const double lr = a.lr * sch.frac;
+    const double bc1 = 1.0 - sch.p1, bc2 = 1.0 - sch.p2;
+    sch.next();
     if (wl) wl[lane] = 0.0;   // kTaMaxRuns == 64: one entry per lane
     // the loop bound is uniform over the wavefront, so the wavefront sums
     // run with every lane present
