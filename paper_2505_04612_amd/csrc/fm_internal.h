@@ -103,6 +103,7 @@ struct fm_scene {
   unsigned long long* kept_slots = nullptr;  // [kKeptSlots * 16] kept-match counters, one per 128-B line
   int32_t* cam_ptr = nullptr;     // [N+1] incidence list offsets
   int32_t* cam_items = nullptr;   // [2P] 2*pair + side (0: camera is i_n, 1: j_n), pair order
+  int32_t* pair_slot = nullptr;   // [2P] position of item 2*pair + side in cam_items
   // workspace
   float* partials = nullptr;      // [n_big, 36]
   double* ess = nullptr;          // [P, 9] essential matrices (reweight)

@@ -117,6 +117,35 @@ __device__ inline double pair_phase(const float* params, const double* rot, cons
   return sum;
 }
 
+// Camera-major record layout of the pair loop: the 12 floats of item q of
+// the incidence lists (a pair's side for one camera) at contrib + 12 q, so a
+// camera's records are one contiguous run.  Pair phase as above, each side
+// written to its slot (qi0, qj0 and qi1, qj1: slots of the first two pairs,
+// held in registers).
+template <typename WT, bool SH>
+__device__ inline double pair_phase_slots(const float* params, const double* rot, const int32_t* cams,
+                                          const int32_t* pair_slot, const WT* W36, int64_t P, double two_inv_Z,
+                                          float* contrib, int64_t first, int64_t stride, int ci0, int cj0, int ci1,
+                                          int cj1, int qi0, int qj0, int qi1, int qj1) {
+  double sum = 0.0;
+  for (int64_t n = first; n < P; n += stride) {
+    float rec[24];
+    const bool held0 = n == first, held1 = n == first + stride;
+    const int ci = held0 ? ci0 : (held1 ? ci1 : cams[2 * n]), cj = held0 ? cj0 : (held1 ? cj1 : cams[2 * n + 1]);
+    const int qi = held0 ? qi0 : (held1 ? qi1 : pair_slot[2 * n]);
+    const int qj = held0 ? qj0 : (held1 ? qj1 : pair_slot[2 * n + 1]);
+    sum += pair_loss_adjoint<WT, SH>(params, rot, ci, cj, W36, n, two_inv_Z, rec);
+    float4* di = reinterpret_cast<float4*>(contrib + (int64_t)qi * 12);
+    float4* dj = reinterpret_cast<float4*>(contrib + (int64_t)qj * 12);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      di[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
+      dj[k] = make_float4(rec[12 + 4 * k], rec[12 + 4 * k + 1], rec[12 + 4 * k + 2], rec[12 + 4 * k + 3]);
+    }
+  }
+  return sum;
+}
+
 // Incidence list of one camera as one wavefront reads it: the list bounds
 // and the first two entries of this lane (q = lo + lane and lo + 64 + lane;
 // -1 past the end).  Static during a solve, so the fused loop reads it once.
@@ -316,29 +345,32 @@ struct SolveArgs {
   double lr_rot, lr_t, log_frac;
   double b1, b2, eps;
   int64_t lr_step0, lr_total, adam_step0;
+  const int32_t* pair_slot;
 };
 
-// Incidence entries per lane that the pair loop's camera rows hold in
-// registers: 6 x 16 covers cameras of up to 96 pairs with one round of
-// record loads (entries past them are read in further rounds).
+// Record slots per lane that the pair loop's camera rows load in one round:
+// 6 x 16 covers cameras of up to 96 pairs (slots past them are read in
+// further rounds).
 constexpr int kRowItems = 6;
 
-// Summed records of one camera in every lane of its row: the records of the
-// held entries are all loaded before any is added (so their loads are in
-// flight together), then added in entry order, then the rest of the list.
+// Summed records of one camera in every lane of its row, from the
+// camera-major layout (slots lo..hi-1): lane l16 takes slots lo + l16 + 16 j;
+// the first NE of them are all loaded before any is added (so their loads are
+// in flight together), then added in slot order, then the rest.
 template <bool SH, int NE>
-__device__ inline void row_camera_sums_held(const RowListN<NE>& L, const int32_t* __restrict__ cam_items,
-                                            const float* __restrict__ contrib, int lane, double acc[12]) {
+__device__ inline void row_camera_sums_slots(int lo, int hi, const float* __restrict__ contrib, int lane,
+                                             double acc[12]) {
   const Arr<SH, float> c(contrib);
+  const int l16 = lane & 15;
   float4 r[NE][3];
 #pragma unroll
   for (int j = 0; j < NE; ++j) {
     r[j][0] = r[j][1] = r[j][2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (L.it[j] >= 0) {
-      const int64_t b = (int64_t)(L.it[j] >> 1) * 24 + (L.it[j] & 1) * 12;
-      r[j][0] = c.f4(b);
-      r[j][1] = c.f4(b + 4);
-      r[j][2] = c.f4(b + 8);
+    const int q = lo + l16 + 16 * j;
+    if (q < hi) {
+      r[j][0] = c.f4((int64_t)q * 12);
+      r[j][1] = c.f4((int64_t)q * 12 + 4);
+      r[j][2] = c.f4((int64_t)q * 12 + 8);
     }
   }
 #pragma unroll
@@ -349,7 +381,12 @@ __device__ inline void row_camera_sums_held(const RowListN<NE>& L, const int32_t
     acc[4] += r[j][1].x; acc[5] += r[j][1].y; acc[6] += r[j][1].z; acc[7] += r[j][1].w;
     acc[8] += r[j][2].x; acc[9] += r[j][2].y; acc[10] += r[j][2].z; acc[11] += r[j][2].w;
   }
-  for (int q = L.lo + 16 * NE + (lane & 15); q < L.hi; q += 16) add_record<SH>(contrib, cam_items[q], acc);
+  for (int q = lo + 16 * NE + l16; q < hi; q += 16) {
+    const float4 a0 = c.f4((int64_t)q * 12), a1 = c.f4((int64_t)q * 12 + 4), a2 = c.f4((int64_t)q * 12 + 8);
+    acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
+    acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
+    acc[8] += a2.x; acc[9] += a2.y; acc[10] += a2.z; acc[11] += a2.w;
+  }
   row_sum12(acc, lane);
 }
 
@@ -372,24 +409,27 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
   const WT* W36 = reinterpret_cast<const WT*>(a.W36);
-  // static data of this thread's first pair and this wavefront's first
-  // camera, read once instead of once per iteration
+  // static data of this thread's first two pairs (cameras and record slots)
+  // and this row's first camera (its slot range), read once instead of once
+  // per iteration
   const int ci0 = gtid < a.P ? a.cams[2 * gtid] : 0, cj0 = gtid < a.P ? a.cams[2 * gtid + 1] : 0;
+  const int qi0 = gtid < a.P ? a.pair_slot[2 * gtid] : 0, qj0 = gtid < a.P ? a.pair_slot[2 * gtid + 1] : 0;
   const int64_t g1 = gtid + gsize;
   const int ci1 = g1 < a.P ? a.cams[2 * g1] : 0, cj1 = g1 < a.P ? a.cams[2 * g1 + 1] : 0;
+  const int qi1 = g1 < a.P ? a.pair_slot[2 * g1] : 0, qj1 = g1 < a.P ? a.pair_slot[2 * g1 + 1] : 0;
   // cameras 4 gwave + row, then strided by 4 nwaves
   const int row = lane >> 4, l16 = lane & 15, base = lane & ~15;
   const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
-  RowListN<kRowItems> L0 = empty_row_list<kRowItems>();
-  if (c_first < a.N) L0 = row_list<kRowItems>(a.cam_ptr, a.cam_items, (int)c_first, l16);
+  const int lo0 = c_first < a.N ? a.cam_ptr[c_first] : 0, hi0 = c_first < a.N ? a.cam_ptr[c_first + 1] : 0;
   XcdSync xs = {0u, 0u, 0u};
   if constexpr (XS) xs = xcd_register(a.bar);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     // iteration 0 runs Gram-Schmidt per pair; later iterations read the
     // rotations the camera phase stored with the updated parameters
-    const double v = pair_phase<WT, XS>(a.params, k > 0 ? a.rot : nullptr, a.cams, W36, a.P, 2.0 * iz, a.contrib,
-                                          gtid, gsize, ci0, cj0, ci1, cj1);
+    const double v = pair_phase_slots<WT, XS>(a.params, k > 0 ? a.rot : nullptr, a.cams, a.pair_slot, W36, a.P,
+                                                2.0 * iz, a.contrib, gtid, gsize, ci0, cj0, ci1, cj1, qi0, qj0, qi1,
+                                                qj1);
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
     loop_sync<XS>(a.bar, xs);
@@ -417,10 +457,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
         vq = a.v[c * 9 + l16];
       }
       double acc[12];
-      const RowListN<kRowItems> L =
-          c0 == 4 * gwave ? L0
-                          : (live ? row_list<kRowItems>(a.cam_ptr, a.cam_items, (int)c, l16) : empty_row_list<kRowItems>());
-      row_camera_sums_held<XS, kRowItems>(L, a.cam_items, a.contrib, lane, acc);
+      const bool first = c0 == 4 * gwave;
+      const int lo = first ? lo0 : (live ? a.cam_ptr[c] : 0), hi = first ? hi0 : (live ? a.cam_ptr[c + 1] : 0);
+      row_camera_sums_slots<XS, kRowItems>(lo, hi, a.contrib, lane, acc);
       double a1[3], a2[3], g[9];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -697,6 +736,7 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   a.lr_rot = cfg->lr_rot; a.lr_t = cfg->lr_t; a.log_frac = log((double)cfg->lr_final_frac);
   a.b1 = cfg->beta1; a.b2 = cfg->beta2; a.eps = cfg->eps;
   a.lr_step0 = cfg->lr_step0; a.lr_total = cfg->lr_total_steps; a.adam_step0 = cfg->adam_step0;
+  a.pair_slot = s->pair_slot;
   void* args[] = {&a};
   hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, s->bar);
   FM_CHECK_LAUNCH(ctx);

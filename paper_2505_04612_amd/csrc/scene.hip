@@ -271,6 +271,12 @@ __global__ void k_cam_sort(const int32_t* cam_ptr, const int32_t* cam_of_slot, c
   sorted[lo + rank] = v;
 }
 
+// Inverse of the incidence lists: the position of every item in cam_items.
+__global__ void k_pair_slots(const int32_t* cam_items, int64_t total, int32_t* pair_slot) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < total) pair_slot[cam_items[q]] = (int32_t)q;
+}
+
 __global__ void k_slot_camera(const int32_t* cam_ptr, int32_t N, int32_t* cam_of_slot) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < N)
@@ -292,6 +298,7 @@ static void scene_free(fm_scene* s) {
   (void)hipFree(s->kept_slots);
   (void)hipFree(s->cam_ptr);
   (void)hipFree(s->cam_items);
+  (void)hipFree(s->pair_slot);
   (void)hipFree(s->partials);
   (void)hipFree(s->ess);
   (void)hipFree(s->contrib);
@@ -424,6 +431,7 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   // camera incidence lists
   SCENE_TRY(hipMalloc(&s->cam_ptr, sizeof(int32_t) * (N + 1)));
   SCENE_TRY(hipMalloc(&s->cam_items, sizeof(int32_t) * (2 * P + 1)));
+  SCENE_TRY(hipMalloc(&s->pair_slot, sizeof(int32_t) * (2 * P + 1)));
   SCENE_TRY(hipMalloc(&tmp_i32, sizeof(int32_t) * (N + 1 + 4 * P + 2)));
   int32_t* cursor = tmp_i32;                 // [N+1]
   int32_t* unsorted = tmp_i32 + N + 1;       // [2P+1]
@@ -442,6 +450,9 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
     SCENE_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_cam_sort, dim3(grid_for(2 * P, kBlock)), dim3(kBlock), 0, st, s->cam_ptr, slot_cam,
                        unsorted, 2 * P, s->cam_items);
+    SCENE_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_pair_slots, dim3(grid_for(2 * P, kBlock)), dim3(kBlock), 0, st, s->cam_items, 2 * P,
+                       s->pair_slot);
     SCENE_TRY(hipGetLastError());
   }
   SCENE_TRY(hipStreamSynchronize(st));
