@@ -32,6 +32,12 @@ constexpr int kBlock = 256;
 // Threads per workgroup of the persistent solve (eight wavefronts: fewer,
 // larger workgroups make its grid barriers cheaper).
 constexpr int kSolveBlock = 512;
+// Threads per workgroup of the epipolar camera loop: four wavefronts, so
+// that the loop's wavefronts (one per camera, two per SIMD at its register
+// use) spread over twice as many CUs as with eight.  Medium helix scene, µs
+// per iteration: 512 threads 8.2, 256 7.1, 128 7.6 (more workgroups make
+// each grid barrier dearer).
+constexpr int kCamBlock = 256;
 // Integer counters the IRLS pass spreads its kept-match counts over (one
 // 128-byte line each, so concurrent atomics rarely meet on one address).
 constexpr int kKeptSlots = 256;
@@ -114,7 +120,8 @@ struct fm_scene {
   float* params_alt = nullptr;    // [N, 10] second parameter buffer of the camera loops ([N, 9] poses, then [N] focal scales)
   int64_t loss_part_cap = 0;
   unsigned* bar = nullptr;        // [kBarWords] grid barriers of the persistent loops (layout at kBarWords)
-  int coop_blocks = 0;            // max co-resident blocks of the fused solve kernel
+  int coop_blocks = 0;            // max co-resident workgroups of the fused pair loop (kSolveBlock threads)
+  int coop_blocks_cam = 0;        // max co-resident workgroups of the fused camera loop (kCamBlock threads)
   // translation averaging workspace, grown on demand by the translation calls
   int32_t ta_runs_cap = 0;        // runs the workspace holds
   int64_t ta_part_cap = 0;        // loss partials per run

@@ -549,8 +549,8 @@ __device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float 
 }
 
 template <typename WT, bool XS>
-__global__ __launch_bounds__(kSolveBlock) void k_solve_cam(CamSolveArgs a) {
-  __shared__ double lds[kSolveBlock / 64];
+__global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
+  __shared__ double lds[kCamBlock / 64];
   const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -668,21 +668,24 @@ static fm_status solve_checks(fm_ctx* ctx, fm_scene* s, const float* params, con
 // Co-resident workgroups of the fused loops: the smallest occupancy over
 // every instantiation, times the CU count.
 template <typename K>
-static bool occ_min(K kernel, int& per_cu) {
+static bool occ_min(K kernel, int block, int& per_cu) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kSolveBlock, 0) != hipSuccess) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) != hipSuccess) return false;
   if (n < per_cu) per_cu = n;
   return true;
 }
 
-int fm_solve_coop_blocks(fm_ctx* ctx) {
+int fm_solve_coop_blocks(fm_ctx* ctx, bool cam) {
   int per_cu = 1 << 20;
-  if (!occ_min(k_solve<double, false>, per_cu) || !occ_min(k_solve<float, false>, per_cu) ||
-      !occ_min(k_solve<double, true>, per_cu) || !occ_min(k_solve<float, true>, per_cu) ||
-      !occ_min(k_solve_cam<double, false>, per_cu) || !occ_min(k_solve_cam<float, false>, per_cu) ||
-      !occ_min(k_solve_cam<double, true>, per_cu) || !occ_min(k_solve_cam<float, true>, per_cu))
-    return 0;
-  return per_cu * ctx->num_cu;
+  const bool ok = cam ? occ_min(k_solve_cam<double, false>, kCamBlock, per_cu) &&
+                            occ_min(k_solve_cam<float, false>, kCamBlock, per_cu) &&
+                            occ_min(k_solve_cam<double, true>, kCamBlock, per_cu) &&
+                            occ_min(k_solve_cam<float, true>, kCamBlock, per_cu)
+                      : occ_min(k_solve<double, false>, kSolveBlock, per_cu) &&
+                            occ_min(k_solve<float, false>, kSolveBlock, per_cu) &&
+                            occ_min(k_solve<double, true>, kSolveBlock, per_cu) &&
+                            occ_min(k_solve<float, true>, kSolveBlock, per_cu);
+  return ok ? per_cu * ctx->num_cu : 0;
 }
 
 // Instantiation of a fused loop (camera or pair loop) for the Gram dtype
@@ -743,8 +746,8 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
   // automatic grid below kCamLoopMaxPairs, or cfg->blocks < 0: the
   // camera-centric loop, one barrier per iteration; a forced workgroup count
   // or a larger graph runs the pair loop
-  int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
-  if (want_cam > s->coop_blocks) want_cam = s->coop_blocks;
+  int64_t want_cam = grid_for((int64_t)s->N * 64, kCamBlock);
+  if (want_cam > s->coop_blocks_cam) want_cam = s->coop_blocks_cam;
   if ((cfg->blocks < 0 || (cfg->blocks == 0 && s->P < kCamLoopMaxPairs)) && 2 * want_cam <= s->loss_part_cap) {
     CamSolveArgs ca;
     ca.params = params; ca.params_alt = s->params_alt; ca.m = m; ca.v = v;
@@ -758,7 +761,7 @@ extern "C" fm_status fm_epipolar_solve(fm_ctx* ctx, fm_scene* s, const void* W36
     {
     fm_timed timer(ctx, FM_K_SOLVE, (hipStream_t)stream);
     hipError_t e = hipLaunchCooperativeKernel(loop_kernel(true, wdt, want_cam), dim3((unsigned)want_cam),
-                                              dim3(kSolveBlock), cargs, 0, (hipStream_t)stream);
+                                              dim3(kCamBlock), cargs, 0, (hipStream_t)stream);
     if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
     }
     return solve_checks(ctx, s, params, loss_trace, K, (hipStream_t)stream);

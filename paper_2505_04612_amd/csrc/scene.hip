@@ -319,7 +319,7 @@ extern "C" void fm_scene_destroy(fm_scene* s) { scene_free(s); }
 
 extern "C" int64_t fm_scene_work_items(const fm_scene* s) { return s ? s->n_big + s->n_groups : -1; }
 
-int fm_solve_coop_blocks(fm_ctx* ctx);  // iterate.hip
+int fm_solve_coop_blocks(fm_ctx* ctx, bool cam);  // iterate.hip
 
 template <typename T>
 static hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
@@ -461,13 +461,15 @@ extern "C" fm_status fm_scene_create(fm_ctx* ctx, int64_t P, int64_t M, int32_t 
   (void)hipFree(flag);
   flag = nullptr;
   // workspace
-  s->coop_blocks = fm_solve_coop_blocks(ctx);
-  if (s->coop_blocks <= 0) {
+  s->coop_blocks = fm_solve_coop_blocks(ctx, false);
+  s->coop_blocks_cam = fm_solve_coop_blocks(ctx, true);
+  if (s->coop_blocks <= 0 || s->coop_blocks_cam <= 0) {
     scene_free(s);
     return fm_fail(ctx, FM_ECOOP, "cannot size the cooperative solve kernel");
   }
   s->loss_part_cap = (int64_t)grid_for(P, kBlock);   // also covers k_pair_phase's blocks
-  if (s->loss_part_cap < 2 * (int64_t)s->coop_blocks) s->loss_part_cap = 2 * (int64_t)s->coop_blocks;   // the camera loop double-buffers its partials
+  if (s->loss_part_cap < (int64_t)s->coop_blocks) s->loss_part_cap = s->coop_blocks;
+  if (s->loss_part_cap < 2 * (int64_t)s->coop_blocks_cam) s->loss_part_cap = 2 * (int64_t)s->coop_blocks_cam;   // the camera loop double-buffers its partials
   SCENE_TRY(hipMalloc(&s->partials, sizeof(float) * 36 * (s->n_partials > 0 ? s->n_partials : 1)));
   SCENE_TRY(hipMalloc(&s->ess, sizeof(double) * 9 * (P > 0 ? P : 1)));
   SCENE_TRY(hipMalloc(&s->contrib, sizeof(float) * 24 * (P > 0 ? P : 1)));
