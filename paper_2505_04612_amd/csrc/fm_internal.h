@@ -410,8 +410,7 @@ __device__ inline void wave_sum12(double acc[12], int lane) {
 
 // dL/dtheta [9] of one camera from its summed dL/dR (columns g1, g2, g3 in
 // acc[3r + col]) and dL/dt (acc[9..11]): the Gram-Schmidt adjoint in float64.
-__device__ inline void gs_adjoint(const double acc[12], const double a1[3], const double a2[3], double grad[9]) {
-  const Gs f = gs_forward(a1, a2);
+__device__ inline void gs_adjoint(const double acc[12], const Gs& f, const double a2[3], double grad[9]) {
   double g1[3], g2[3], g3[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -444,6 +443,11 @@ __device__ inline void gs_adjoint(const double acc[12], const double a1[3], cons
     grad[k] = (g1[k] - b1g1 * f.b1[k]) * f.r1;
     grad[6 + k] = acc[9 + k];
   }
+}
+
+// The same from the parameters (the forward pass computed here).
+__device__ inline void gs_adjoint(const double acc[12], const double a1[3], const double a2[3], double grad[9]) {
+  gs_adjoint(acc, gs_forward(a1, a2), a2, grad);
 }
 
 // Row-wide total of the 12 per-lane sums over one 16-lane row, returned in

@@ -459,17 +459,20 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
       double acc[12];
       const bool first = c0 == 4 * gwave;
       const int lo = first ? lo0 : (live ? a.cam_ptr[c] : 0), hi = first ? hi0 : (live ? a.cam_ptr[c + 1] : 0);
-      row_camera_sums_slots<XS, kRowItems>(lo, hi, a.contrib, lane, acc);
+      // Gram-Schmidt of the camera's own parameters ahead of the record
+      // gather (it overlaps the record loads); a row without a camera has
+      // zero parameters: keep its Gram-Schmidt away from 0/0 (its results
+      // are not stored)
       double a1[3], a2[3], g[9];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         a1[j] = (double)__shfl(p0, base + j);
         a2[j] = (double)__shfl(p0, base + 3 + j);
       }
-      // a row without a camera has zero sums and zero parameters: keep its
-      // Gram-Schmidt away from 0/0 (its results are not stored)
       if (!live) a1[0] = a2[1] = 1.0;
-      gs_adjoint(acc, a1, a2, g);
+      const Gs f = gs_forward(a1, a2);
+      row_camera_sums_slots<XS, kRowItems>(lo, hi, a.contrib, lane, acc);
+      gs_adjoint(acc, f, a2, g);
       // lanes 0..8 of the row update one parameter each
       float pq = 0.0f;
       if (live && l16 < 9) {
@@ -603,6 +606,15 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
       // m and v are read and written by this wavefront alone)
       const float p0 = Arr<XS, float>(pr)[c * 9 + kq];
       float mq = a.m[c * 9 + kq], vq = a.v[c * 9 + kq];
+      // Gram-Schmidt of the camera's own parameters, needed by the adjoint
+      // below, ahead of the pair evaluations (it overlaps their loads)
+      double a1[3], a2[3], g[9];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        a1[j] = (double)__shfl(p0, j);
+        a2[j] = (double)__shfl(p0, 3 + j);
+      }
+      const Gs f = gs_forward(a1, a2);
       double acc[12];
 #pragma unroll
       for (int j = 0; j < 12; ++j) acc[j] = 0.0;
@@ -619,13 +631,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
         for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);
       }
       wave_sum12(acc, lane);
-      double a1[3], a2[3], g[9];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        a1[j] = (double)__shfl(p0, j);
-        a2[j] = (double)__shfl(p0, 3 + j);
-      }
-      gs_adjoint(acc, a1, a2, g);
+      gs_adjoint(acc, f, a2, g);
       const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
       const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
       if (lane < 9) {
