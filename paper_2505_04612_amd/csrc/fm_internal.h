@@ -221,6 +221,7 @@ struct Arr<false, T> {
   __device__ explicit Arr(const T* q) : p(q) {}
   __device__ T operator[](int64_t i) const { return p[i]; }
   __device__ float4 f4(int64_t i) const { return reinterpret_cast<const float4*>(p + i)[0]; }
+  __device__ float2 f2(int64_t i) const { return reinterpret_cast<const float2*>(p + i)[0]; }
 };
 
 template <typename T>
@@ -238,6 +239,10 @@ struct Arr<true, T> {
   // 16 bytes from element i on (16-byte aligned)
   __device__ float4 f4(int64_t i) const {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * (int64_t)sizeof(T)), 0, kSc0));
+  }
+  // 8 bytes from element i on (8-byte aligned)
+  __device__ float2 f2(int64_t i) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * (int64_t)sizeof(T)), 0, kSc0));
   }
 };
 
@@ -313,6 +318,53 @@ __device__ inline void essential_adjoint(const double G[3][3], const double th[3
   for (int a = 0; a < 3; ++a) {
     rec[21 + a] = (float)gs[a];
     rec[9 + a] = (float)(-(Rij[0][a] * gs[0] + Rij[1][a] * gs[1] + Rij[2][a] * gs[2]));
+  }
+}
+
+// The adjoint of E = [th]_x R_ij in the form the fused loops' camera updates
+// use.  The loss depends on R_i, R_j only through R_ij = R_j R_i^T, so the
+// body-frame rotation gradients of the two cameras are opposite: om =
+// vee(skew(R_j^T dL/dR_j)) for camera j and -om for camera i, with
+// R_j^T dL/dR_j = R_j^T dRij R_i (dRij = dL/dR_ij).  Only that tangent part of
+// dL/dR reaches the 6D parameters (every change of the parameters moves R
+// along SO(3)), so a camera's update can rebuild dL/dR from the sum of its
+// pairs' om (omega_grad).  Also dL/dt_i and dL/dt_j.  ns = |s| > 0.
+__device__ inline void essential_adjoint_omega(const double G[3][3], const double th[3], double ns,
+                                               const double Rij[3][3], const double Ri[3][3], const double Rj[3][3],
+                                               const double ti[3], double om[3], double dti[3], double dtj[3]) {
+  const double T[3][3] = {{0.0, -th[2], th[1]}, {th[2], 0.0, -th[0]}, {-th[1], th[0], 0.0}};
+  double A[3][3], dRij[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      A[a][b] = G[a][0] * Rij[b][0] + G[a][1] * Rij[b][1] + G[a][2] * Rij[b][2];
+      dRij[a][b] = T[0][a] * G[0][b] + T[1][a] * G[1][b] + T[2][a] * G[2][b];
+    }
+  const double gth[3] = {A[2][1] - A[1][2], A[0][2] - A[2][0], A[1][0] - A[0][1]};
+  const double dp = th[0] * gth[0] + th[1] * gth[1] + th[2] * gth[2];
+  const double rns = 1.0 / ns;
+  double gs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gs[k] = (gth[k] - dp * th[k]) * rns;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) dRij[a][b] -= gs[a] * ti[b];
+  // N = dRij R_i; the off-diagonal entries of M = R_j^T N
+  double N[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) N[a][b] = dRij[a][0] * Ri[0][b] + dRij[a][1] * Ri[1][b] + dRij[a][2] * Ri[2][b];
+  auto M = [&](int a, int b) { return Rj[0][a] * N[0][b] + Rj[1][a] * N[1][b] + Rj[2][a] * N[2][b]; };
+  om[0] = 0.5 * (M(2, 1) - M(1, 2));
+  om[1] = 0.5 * (M(0, 2) - M(2, 0));
+  om[2] = 0.5 * (M(1, 0) - M(0, 1));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dtj[a] = gs[a];
+    dti[a] = -(Rij[0][a] * gs[0] + Rij[1][a] * gs[1] + Rij[2][a] * gs[2]);
   }
 }
 
@@ -476,6 +528,51 @@ __device__ inline void row_camera_sums(const RowList& L, const int32_t* __restri
     if (L.it[j] >= 0) add_record<SH>(contrib, L.it[j], acc);
   for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record<SH>(contrib, cam_items[q], acc);
   row_sum12(acc, lane);
+}
+
+// Row-wide total of 6 per-lane sums over one 16-lane row, in every lane of
+// the row: reduce-scatter over lane bits 3..1 (6 -> 3 -> 2 -> 1), the partner
+// over bit 0 added, then a gather inside the row (entry s ends in lane
+// 8 (s / 3) + 2 (s % 3) of the row).  Fixed order: deterministic.
+__device__ inline double row_partial6(const double (&acc)[6], int lane) {
+  double b3[3], b2[2], b1[1];
+  rs_stage_d<6, 3>(acc, b3, lane);
+  rs_stage_d<3, 2>(b3, b2, lane);
+  rs_stage_d<2, 1>(b2, b1, lane);
+  return b1[0] + dpp_mov_d<0xB1>(b1[0]);   // quad_perm xor 1
+}
+
+__device__ inline void row_sum6(double (&acc)[6], int lane) {
+  const double v = row_partial6(acc, lane);
+  const int base = lane & ~15;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) acc[k] = __shfl(v, base + 8 * (k / 3) + 2 * (k % 3));
+}
+
+// Wave-wide total of 6 per-lane sums, in every lane: the row reduction, the
+// four rows added, the gather.
+__device__ inline void wave_sum6(double (&acc)[6], int lane) {
+  double v = row_partial6(acc, lane);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) acc[k] = __shfl(v, 8 * (k / 3) + 2 * (k % 3));
+}
+
+// A camera's summed body-frame rotation gradient om (sums of its pairs'
+// essential_adjoint_omega terms) as dL/dR = R [om]_x, with R's columns
+// b1, b2, b3 from its Gram-Schmidt, in the acc[12] layout gs_adjoint reads
+// (dL/dR row-major, then dL/dt from dt).
+__device__ inline void omega_grad(const Gs& f, const double om[3], const double dt[3], double acc[12]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double R0 = f.b1[r], R1 = f.b2[r], R2 = f.b3[r];
+    acc[3 * r + 0] = R1 * om[2] - R2 * om[1];
+    acc[3 * r + 1] = R2 * om[0] - R0 * om[2];
+    acc[3 * r + 2] = R0 * om[1] - R1 * om[0];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) acc[9 + k] = dt[k];
 }
 
 // The element q of a per-lane array held identically by all lanes.

@@ -23,65 +23,78 @@ __device__ inline double load_w(const WT* p, int k) {
   return (double)p[k];
 }
 
-// Loss term and adjoint record of pair n.  rec = [dL/dR_i (3x3 row-major),
-// dL/dt_i, dL/dR_j, dL/dt_j] as float32.
-// `rot` (optional) holds each camera's rotation from Gram-Schmidt of the
-// current parameters, so pairs need not repeat it.  SH: parameters and
-// rotations are read through Arr<true, T> (the persistent loops, where other
-// workgroups wrote them since the last grid_sync); the Gram is constant.
-template <typename WT, bool SH = false>
-__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot, int ci,
-                                           int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
-                                           float* __restrict__ rec) {
-  double a1[3], a2[3], ti[3], tj[3];
-  double Ri[3][3], Rj[3][3], Rij[3][3], th[3], E[3][3];
+// Loss term of pair n and what its adjoint needs: E_n at the current poses
+// (`rot`, optional, holds each camera's rotation from Gram-Schmidt of the
+// current parameters, so pairs need not repeat it) and g = W_n e_n, in
+// float64.  SH: parameters and rotations are read through Arr<true, T> (the
+// persistent loops, where other workgroups wrote them since the last
+// grid_sync); the Gram is constant.
+struct PairEval {
+  double Ri[3][3], Rj[3][3], Rij[3][3], th[3], ti[3], g[3][3];
+  double ns, loss;
+};
+
+template <typename WT, bool SH>
+__device__ inline PairEval pair_eval(const float* __restrict__ params, const double* __restrict__ rot, int ci, int cj,
+                                     const WT* __restrict__ W36, int64_t n) {
+  PairEval e;
+  double a1[3], a2[3], tj[3], E[3][3];
   if (rot) {
     const Arr<SH, float> P(params);
     const Arr<SH, double> R(rot);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      ti[k] = (double)P[(int64_t)ci * 9 + 6 + k];
+      e.ti[k] = (double)P[(int64_t)ci * 9 + 6 + k];
       tj[k] = (double)P[(int64_t)cj * 9 + 6 + k];
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      Ri[k / 3][k % 3] = R[(int64_t)ci * 9 + k];
-      Rj[k / 3][k % 3] = R[(int64_t)cj * 9 + k];
+      e.Ri[k / 3][k % 3] = R[(int64_t)ci * 9 + k];
+      e.Rj[k / 3][k % 3] = R[(int64_t)cj * 9 + k];
     }
   } else {
-    load_pose<SH>(params, ci, a1, a2, ti);
-    gs_matrix(gs_forward(a1, a2), Ri);
+    load_pose<SH>(params, ci, a1, a2, e.ti);
+    gs_matrix(gs_forward(a1, a2), e.Ri);
     load_pose<SH>(params, cj, a1, a2, tj);
-    gs_matrix(gs_forward(a1, a2), Rj);
+    gs_matrix(gs_forward(a1, a2), e.Rj);
   }
-  const double ns = pair_essential(Ri, ti, Rj, tj, Rij, th, E);
+  e.ns = pair_essential(e.Ri, e.ti, e.Rj, tj, e.Rij, e.th, E);
   // g = W e with W_{(ab),(cd)} = W36[6 q(a,c) + q(b,d)]: walk the index
   // pairs (a, c) and read only the 6-entry row q(a,c) of the compact Gram
   // for each, so few Gram values are live at once
   const WT* Wn = W36 + n * 36;
-  double g[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) g[a][b] = 0.0;
+    for (int b = 0; b < 3; ++b) e.g[a][b] = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double row[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) row[k] = load_w(Wn, 6 * mono_q(a, c) + k);
+      for (int k = 0; k < 6; ++k) row[k] = (double)Wn[6 * mono_q(a, c) + k];
 #pragma unroll
       for (int b = 0; b < 3; ++b)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) g[a][b] = fma(row[mono_q(b, d)], E[c][d], g[a][b]);
+        for (int d = 0; d < 3; ++d) e.g[a][b] = fma(row[mono_q(b, d)], E[c][d], e.g[a][b]);
     }
-  double loss = 0.0;
+  e.loss = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) loss = fma(E[a][b], g[a][b], loss);
-  if (!(ns > 0.0)) {
+    for (int b = 0; b < 3; ++b) e.loss = fma(E[a][b], e.g[a][b], e.loss);
+  return e;
+}
+
+// Loss term and adjoint record of pair n.  rec = [dL/dR_i (3x3 row-major),
+// dL/dt_i, dL/dR_j, dL/dt_j] as float32.
+template <typename WT, bool SH = false>
+__device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot, int ci,
+                                           int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
+                                           float* __restrict__ rec) {
+  const PairEval e = pair_eval<WT, SH>(params, rot, ci, cj, W36, n);
+  if (!(e.ns > 0.0)) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) rec[k] = 0.0f;
     return 0.0;
@@ -91,9 +104,31 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) G[a][b] = two_inv_Z * g[a][b];
-  essential_adjoint(G, th, ns, Rij, Ri, Rj, ti, rec);
-  return loss;
+    for (int b = 0; b < 3; ++b) G[a][b] = two_inv_Z * e.g[a][b];
+  essential_adjoint(G, e.th, e.ns, e.Rij, e.Ri, e.Rj, e.ti, rec);
+  return e.loss;
+}
+
+// Loss term of pair n and its adjoint in the fused loops' compact form
+// (essential_adjoint_omega): om, dL/dt_i, dL/dt_j (all 0 for a degenerate
+// pair).
+template <typename WT, bool SH>
+__device__ inline double pair_loss_omega(const float* __restrict__ params, const double* __restrict__ rot, int ci,
+                                         int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
+                                         double om[3], double dti[3], double dtj[3]) {
+  const PairEval e = pair_eval<WT, SH>(params, rot, ci, cj, W36, n);
+  if (!(e.ns > 0.0)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) om[k] = dti[k] = dtj[k] = 0.0;
+    return 0.0;
+  }
+  double G[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[a][b] = two_inv_Z * e.g[a][b];
+  essential_adjoint_omega(G, e.th, e.ns, e.Rij, e.Ri, e.Rj, e.ti, om, dti, dtj);
+  return e.loss;
 }
 
 // Pair phase over pairs [first, P) with stride `stride`; writes the records
@@ -117,11 +152,12 @@ __device__ inline double pair_phase(const float* params, const double* rot, cons
   return sum;
 }
 
-// Camera-major record layout of the pair loop: the 12 floats of item q of
-// the incidence lists (a pair's side for one camera) at contrib + 12 q, so a
-// camera's records are one contiguous run.  Pair phase as above, each side
-// written to its slot (qi0, qj0 and qi1, qj1: slots of the first two pairs,
-// held in registers).
+// Camera-major record layout of the pair loop: the 6 floats of item q of the
+// incidence lists (a pair's side for one camera: its body-frame rotation
+// gradient, -om for camera i and om for camera j, then dL/dt of that camera)
+// at contrib + 6 q, so a camera's records are one contiguous run.  Pair phase
+// as above, each side written to its slot (qi0, qj0 and qi1, qj1: slots of
+// the first two pairs, held in registers).
 template <typename WT, bool SH>
 __device__ inline double pair_phase_slots(const float* params, const double* rot, const int32_t* cams,
                                           const int32_t* pair_slot, const WT* W36, int64_t P, double two_inv_Z,
@@ -129,19 +165,20 @@ __device__ inline double pair_phase_slots(const float* params, const double* rot
                                           int cj1, int qi0, int qj0, int qi1, int qj1) {
   double sum = 0.0;
   for (int64_t n = first; n < P; n += stride) {
-    float rec[24];
     const bool held0 = n == first, held1 = n == first + stride;
     const int ci = held0 ? ci0 : (held1 ? ci1 : cams[2 * n]), cj = held0 ? cj0 : (held1 ? cj1 : cams[2 * n + 1]);
     const int qi = held0 ? qi0 : (held1 ? qi1 : pair_slot[2 * n]);
     const int qj = held0 ? qj0 : (held1 ? qj1 : pair_slot[2 * n + 1]);
-    sum += pair_loss_adjoint<WT, SH>(params, rot, ci, cj, W36, n, two_inv_Z, rec);
-    float4* di = reinterpret_cast<float4*>(contrib + (int64_t)qi * 12);
-    float4* dj = reinterpret_cast<float4*>(contrib + (int64_t)qj * 12);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      di[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
-      dj[k] = make_float4(rec[12 + 4 * k], rec[12 + 4 * k + 1], rec[12 + 4 * k + 2], rec[12 + 4 * k + 3]);
-    }
+    double om[3], dti[3], dtj[3];
+    sum += pair_loss_omega<WT, SH>(params, rot, ci, cj, W36, n, two_inv_Z, om, dti, dtj);
+    float2* di = reinterpret_cast<float2*>(contrib + (int64_t)qi * 6);
+    float2* dj = reinterpret_cast<float2*>(contrib + (int64_t)qj * 6);
+    di[0] = make_float2((float)-om[0], (float)-om[1]);
+    di[1] = make_float2((float)-om[2], (float)dti[0]);
+    di[2] = make_float2((float)dti[1], (float)dti[2]);
+    dj[0] = make_float2((float)om[0], (float)om[1]);
+    dj[1] = make_float2((float)om[2], (float)dtj[0]);
+    dj[2] = make_float2((float)dtj[1], (float)dtj[2]);
   }
   return sum;
 }
@@ -354,40 +391,39 @@ struct SolveArgs {
 constexpr int kRowItems = 6;
 
 // Summed records of one camera in every lane of its row, from the
-// camera-major layout (slots lo..hi-1): lane l16 takes slots lo + l16 + 16 j;
-// the first NE of them are all loaded before any is added (so their loads are
-// in flight together), then added in slot order, then the rest.
+// camera-major layout (slots lo..hi-1, 6 floats each): lane l16 takes slots
+// lo + l16 + 16 j; the first NE of them are all loaded before any is added
+// (so their loads are in flight together), then added in slot order, then
+// the rest.  acc = (om, dL/dt) of the camera.
 template <bool SH, int NE>
 __device__ inline void row_camera_sums_slots(int lo, int hi, const float* __restrict__ contrib, int lane,
-                                             double acc[12]) {
+                                             double (&acc)[6]) {
   const Arr<SH, float> c(contrib);
   const int l16 = lane & 15;
-  float4 r[NE][3];
+  float2 r[NE][3];
 #pragma unroll
   for (int j = 0; j < NE; ++j) {
-    r[j][0] = r[j][1] = r[j][2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    r[j][0] = r[j][1] = r[j][2] = make_float2(0.0f, 0.0f);
     const int q = lo + l16 + 16 * j;
     if (q < hi) {
-      r[j][0] = c.f4((int64_t)q * 12);
-      r[j][1] = c.f4((int64_t)q * 12 + 4);
-      r[j][2] = c.f4((int64_t)q * 12 + 8);
+      r[j][0] = c.f2((int64_t)q * 6);
+      r[j][1] = c.f2((int64_t)q * 6 + 2);
+      r[j][2] = c.f2((int64_t)q * 6 + 4);
     }
   }
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 6; ++k) acc[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < NE; ++j) {
-    acc[0] += r[j][0].x; acc[1] += r[j][0].y; acc[2] += r[j][0].z; acc[3] += r[j][0].w;
-    acc[4] += r[j][1].x; acc[5] += r[j][1].y; acc[6] += r[j][1].z; acc[7] += r[j][1].w;
-    acc[8] += r[j][2].x; acc[9] += r[j][2].y; acc[10] += r[j][2].z; acc[11] += r[j][2].w;
+    acc[0] += r[j][0].x; acc[1] += r[j][0].y; acc[2] += r[j][1].x;
+    acc[3] += r[j][1].y; acc[4] += r[j][2].x; acc[5] += r[j][2].y;
   }
   for (int q = lo + 16 * NE + l16; q < hi; q += 16) {
-    const float4 a0 = c.f4((int64_t)q * 12), a1 = c.f4((int64_t)q * 12 + 4), a2 = c.f4((int64_t)q * 12 + 8);
-    acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
-    acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
-    acc[8] += a2.x; acc[9] += a2.y; acc[10] += a2.z; acc[11] += a2.w;
+    const float2 a0 = c.f2((int64_t)q * 6), a1 = c.f2((int64_t)q * 6 + 2), a2 = c.f2((int64_t)q * 6 + 4);
+    acc[0] += a0.x; acc[1] += a0.y; acc[2] += a1.x;
+    acc[3] += a1.y; acc[4] += a2.x; acc[5] += a2.y;
   }
-  row_sum12(acc, lane);
+  row_sum6(acc, lane);
 }
 
 // Grid barrier of the fused loops: per-XCD (grid_sync, with the shared
@@ -456,7 +492,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
         mq = a.m[c * 9 + l16];
         vq = a.v[c * 9 + l16];
       }
-      double acc[12];
+      double acc6[6], acc[12];
       const bool first = c0 == 4 * gwave;
       const int lo = first ? lo0 : (live ? a.cam_ptr[c] : 0), hi = first ? hi0 : (live ? a.cam_ptr[c + 1] : 0);
       // Gram-Schmidt of the camera's own parameters ahead of the record
@@ -471,7 +507,8 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
       }
       if (!live) a1[0] = a2[1] = 1.0;
       const Gs f = gs_forward(a1, a2);
-      row_camera_sums_slots<XS, kRowItems>(lo, hi, a.contrib, lane, acc);
+      row_camera_sums_slots<XS, kRowItems>(lo, hi, a.contrib, lane, acc6);
+      omega_grad(f, acc6, acc6 + 3, acc);
       gs_adjoint(acc, f, a2, g);
       // lanes 0..8 of the row update one parameter each
       float pq = 0.0f;
@@ -615,22 +652,28 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
         a2[j] = (double)__shfl(p0, 3 + j);
       }
       const Gs f = gs_forward(a1, a2);
-      double acc[12];
+      // this camera's side of each of its pairs: body-frame rotation
+      // gradient (om for camera j, -om for camera i) and dL/dt
+      double acc6[6], acc[12];
 #pragma unroll
-      for (int j = 0; j < 12; ++j) acc[j] = 0.0;
+      for (int j = 0; j < 6; ++j) acc6[j] = 0.0;
       for (int q = lo + lane; q < hi; q += 64) {
         const bool first = c == gwave && q == lo + lane;
         const int item = first ? 0 : a.cam_items[q];
         const int64_t n = first ? n0 : item >> 1;
         const int side = first ? side0 : item & 1;
         const int ci = first ? ci0 : a.cams[2 * n], cj = first ? cj0 : a.cams[2 * n + 1];
-        float rec[24];
-        const double l = pair_loss_adjoint<WT, XS>(pr, rr, ci, cj, W36, n, 2.0 * iz, rec);
+        double om[3], dti[3], dtj[3];
+        const double l = pair_loss_omega<WT, XS>(pr, rr, ci, cj, W36, n, 2.0 * iz, om, dti, dtj);
         if (side == 0) lsum += l;   // each pair's loss once, from its first camera
 #pragma unroll
-        for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);
+        for (int j = 0; j < 3; ++j) {
+          acc6[j] += (double)(float)(side ? om[j] : -om[j]);
+          acc6[3 + j] += (double)(float)(side ? dtj[j] : dti[j]);
+        }
       }
-      wave_sum12(acc, lane);
+      wave_sum6(acc6, lane);
+      omega_grad(f, acc6, acc6 + 3, acc);
       gs_adjoint(acc, f, a2, g);
       const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
       const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
