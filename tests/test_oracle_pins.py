@@ -242,6 +242,47 @@ def test_gradient_zero_along_gauge(tiny):
     assert abs(np.sum(g * d_shift)) <= 1e-10 * scale
 
 
+def test_pair_rotation_gradients_are_opposite_in_body_frames(tiny):
+    """A pair's loss depends on R_i, R_j only through R_ij = R_j R_i^T, so a
+    common body-frame turn R -> R exp([d]_x) of both cameras leaves it
+    unchanged: the rate along d of camera i's parameters is minus that of
+    camera j's, pair by pair (what lets the fused loops exchange one
+    rotation term per pair).  Rates from the oracle's analytic gradient."""
+    th = ea.params_from_poses(tiny.R_init, tiny.t_init)
+    W = ea.pair_grams(tiny.uv, tiny.offsets)
+    R, _ = ea.poses_from_params(th)
+    rng = np.random.default_rng(5)
+    for n in range(0, tiny.num_pairs, 17):
+        pair = tiny.pairs[n:n + 1]
+        _, g = ea.loss_grad(th, pair, W[n:n + 1], 1e-3)
+        for _ in range(3):
+            d = ea.skew(rng.normal(size=3))
+            rate = []
+            for c in pair[0]:
+                dR = R[c] @ d           # d/d(eps) of R exp(eps [d]_x); a1, a2 are R's first two columns
+                rate.append(np.dot(g[c, 0:3], dR[:, 0]) + np.dot(g[c, 3:6], dR[:, 1]))
+            scale = np.linalg.norm(g[pair[0], 0:6]) * np.linalg.norm(d)
+            assert abs(rate[0] + rate[1]) <= 1e-10 * scale, (n, rate)
+            assert abs(rate[0]) > 1e-6 * scale or scale == 0.0
+
+
+def test_gradient_zero_where_rotation_does_not_move(tiny):
+    """Scaling a1 or a2 and adding a multiple of a1 to a2 leave R = GS(a1, a2)
+    unchanged, so the gradient has no component along them: only the tangent
+    part of dL/dR reaches the 6D parameters."""
+    rng = np.random.default_rng(6)
+    th = ea.params_from_poses(tiny.R_init, tiny.t_init)
+    th[:, 0:3] *= rng.uniform(0.5, 2.0, (tiny.num_cams, 1))
+    th[:, 3:6] = th[:, 3:6] * rng.uniform(0.5, 2.0, (tiny.num_cams, 1)) + 0.3 * th[:, 0:3]
+    W = ea.pair_grams(tiny.uv, tiny.offsets)
+    _, g = ea.loss_grad(th, tiny.pairs, W, 1e-3)
+    a1, a2 = th[:, 0:3], th[:, 3:6]
+    scale = np.linalg.norm(g[:, 0:6], axis=1) * np.maximum(np.linalg.norm(a1, axis=1), np.linalg.norm(a2, axis=1))
+    for d1, d2 in ((a1, 0 * a2), (0 * a1, a1), (0 * a1, a2)):
+        rate = np.sum(g[:, 0:3] * d1, axis=1) + np.sum(g[:, 3:6] * d2, axis=1)
+        assert np.all(np.abs(rate) <= 1e-10 * scale + 1e-300)
+
+
 # ----------------------------------------------------------- IRLS
 
 def test_irls_weighted_l2_equals_l1_at_reweight_point(tiny):
