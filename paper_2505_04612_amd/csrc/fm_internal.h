@@ -324,14 +324,16 @@ __device__ inline void essential_adjoint(const double G[3][3], const double th[3
 // The adjoint of E = [th]_x R_ij in the form the fused loops' camera updates
 // use.  The loss depends on R_i, R_j only through R_ij = R_j R_i^T, so the
 // body-frame rotation gradients of the two cameras are opposite: om =
-// vee(skew(R_j^T dL/dR_j)) for camera j and -om for camera i, with
-// R_j^T dL/dR_j = R_j^T dRij R_i (dRij = dL/dR_ij).  Only that tangent part of
+// vee(skew(R_j^T dL/dR_j)) for camera j and -om for camera i.  With
+// R_j^T dL/dR_j = R_j^T dRij R_i (dRij = dL/dR_ij) and R_j = R_ij R_i,
+// om = R_i^T vee(skew(R_ij^T dRij)) (vee(skew(Q^T A Q)) = Q^T vee(skew(A))
+// for a rotation Q), so R_j is not needed here.  Only that tangent part of
 // dL/dR reaches the 6D parameters (every change of the parameters moves R
-// along SO(3)), so a camera's update can rebuild dL/dR from the sum of its
+// along SO(3)), so a camera's update rebuilds dL/dR from the sum of its
 // pairs' om (omega_grad).  Also dL/dt_i and dL/dt_j.  ns = |s| > 0.
 __device__ inline void essential_adjoint_omega(const double G[3][3], const double th[3], double ns,
-                                               const double Rij[3][3], const double Ri[3][3], const double Rj[3][3],
-                                               const double ti[3], double om[3], double dti[3], double dtj[3]) {
+                                               const double Rij[3][3], const double Ri[3][3], const double ti[3],
+                                               double om[3], double dti[3], double dtj[3]) {
   const double T[3][3] = {{0.0, -th[2], th[1]}, {th[2], 0.0, -th[0]}, {-th[1], th[0], 0.0}};
   double A[3][3], dRij[3][3];
 #pragma unroll
@@ -351,18 +353,12 @@ __device__ inline void essential_adjoint_omega(const double G[3][3], const doubl
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) dRij[a][b] -= gs[a] * ti[b];
-  // N = dRij R_i; the off-diagonal entries of M = R_j^T N
-  double N[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) N[a][b] = dRij[a][0] * Ri[0][b] + dRij[a][1] * Ri[1][b] + dRij[a][2] * Ri[2][b];
-  auto M = [&](int a, int b) { return Rj[0][a] * N[0][b] + Rj[1][a] * N[1][b] + Rj[2][a] * N[2][b]; };
-  om[0] = 0.5 * (M(2, 1) - M(1, 2));
-  om[1] = 0.5 * (M(0, 2) - M(2, 0));
-  om[2] = 0.5 * (M(1, 0) - M(0, 1));
+  // w = vee(skew(R_ij^T dRij)) from the off-diagonal entries of R_ij^T dRij
+  auto K = [&](int a, int b) { return Rij[0][a] * dRij[0][b] + Rij[1][a] * dRij[1][b] + Rij[2][a] * dRij[2][b]; };
+  const double w[3] = {0.5 * (K(2, 1) - K(1, 2)), 0.5 * (K(0, 2) - K(2, 0)), 0.5 * (K(1, 0) - K(0, 1))};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    om[a] = Ri[0][a] * w[0] + Ri[1][a] * w[1] + Ri[2][a] * w[2];
     dtj[a] = gs[a];
     dti[a] = -(Rij[0][a] * gs[0] + Rij[1][a] * gs[1] + Rij[2][a] * gs[2]);
   }

@@ -127,7 +127,7 @@ __device__ inline double pair_loss_omega(const float* __restrict__ params, const
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) G[a][b] = two_inv_Z * e.g[a][b];
-  essential_adjoint_omega(G, e.th, e.ns, e.Rij, e.Ri, e.Rj, e.ti, om, dti, dtj);
+  essential_adjoint_omega(G, e.th, e.ns, e.Rij, e.Ri, e.ti, om, dti, dtj);
   return e.loss;
 }
 
