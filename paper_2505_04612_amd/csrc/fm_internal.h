@@ -657,76 +657,102 @@ constexpr int64_t kXcdSyncMinBlocks = 128;
 constexpr unsigned kBarSpinOuter = 1u << 14;   // x 256 polls
 // XCD slots of the grid_sync barrier (the XCC_ID hardware field is 4 bits).
 constexpr int kMaxXcd = 16;
-// Words of `bar`, one 128-byte line each: arrival count, generation, failure
-// flag of the running launch, failure total since the last query; then per
-// XCD the arrival count and generation of grid_sync and the number of the
-// launch's workgroups on that XCD.
+// Words of `bar`, one 128-byte line each: arrival count and generation of
+// grid_barrier (words 0 and 32), failure flag of the running launch (64),
+// failure total since the last query (96); then per XCD the arrival count
+// and generation of grid_sync and the number of the launch's workgroups on
+// that XCD; then grid_sync's count of XCDs arrived.  Every count and generation starts the
+// launch at 0 (fm_bar_reset) and only grows, so a workgroup knows the value
+// at which each barrier opens without reading anything first.
 constexpr int kBarXcdCount = 128;
 constexpr int kBarXcdGen = kBarXcdCount + 32 * kMaxXcd;
 constexpr int kBarXcdReg = kBarXcdGen + 32 * kMaxXcd;
-constexpr int kBarWords = kBarXcdReg + 32 * kMaxXcd;
+constexpr int kBarTop = kBarXcdReg + 32 * kMaxXcd;
+constexpr int kBarWords = kBarTop + 32;
 
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
 constexpr int kWaitVmcnt0 = 0x0F70;
 
-// Bounded wait of thread 0 for the word w to move from g.  If the wait
+__device__ inline unsigned bar_load(unsigned* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of thread 0 until the count w reaches `target` (compared
+// modulo 2^32: a waiter is never more than one barrier behind).  If the wait
 // expires (the workgroups were not all resident) or another workgroup has
 // raised the launch's failure flag, it raises the flag and the scene's
 // failure total; every later barrier of the launch then returns at once and
 // the host reads the total with fm_solve_barrier_failures.
-__device__ inline void bar_wait(unsigned* __restrict__ bar, unsigned* w, unsigned g) {
+__device__ inline void bar_reach(unsigned* __restrict__ bar, unsigned* w, unsigned target) {
   unsigned* fail = bar + 64;
-  bool moved = false;
-  for (unsigned outer = 0; outer < kBarSpinOuter && !moved; ++outer) {
+  bool reached = false;
+  for (unsigned outer = 0; outer < kBarSpinOuter && !reached; ++outer) {
 #pragma unroll 1
     for (int i = 0; i < 256; ++i) {
-      if (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != g) {
-        moved = true;
+      if ((int)(bar_load(w) - target) >= 0) {
+        reached = true;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    if (!moved && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+    if (!reached && bar_load(fail) != 0u) break;
   }
-  if (!moved) {
+  if (!reached) {
     __hip_atomic_fetch_add(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(bar + 96, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
+// One workgroup's state of the flat grid barrier (the same in every thread):
+// the arrival count and the generation at which the launch's next barrier
+// opens.
+struct GridBar {
+  unsigned* bar;
+  unsigned next, gnext;
+};
+
+__device__ inline GridBar grid_bar(unsigned* bar) { return GridBar{bar, gridDim.x, 1u}; }
+
 // Grid barrier of the persistent loops that share data through plain loads
 // and stores.  Thread 0 of each workgroup makes the workgroup's writes
-// visible (agent-scope release: writes back the dirty lines of its XCD's L2),
-// counts itself in and waits for the generation word to move; the last to
-// arrive re-arms the counter and moves the generation; each then acquires
-// (invalidates its XCD's L2 and its CU's L1).  All atomics are relaxed and
-// agent-scoped; the fences carry the ordering.
-__device__ inline void grid_barrier(unsigned* __restrict__ bar) {
-  unsigned* count = bar;
-  unsigned* gen = bar + 32;
-  unsigned* fail = bar + 64;
+// visible (agent-scope release: writes back the dirty lines of its XCD's L2)
+// and counts itself in; the workgroup whose increment brings the count to
+// the barrier's opening value stores the new generation, which the others
+// wait for (polling a word that no arrival increments); each then acquires
+// (invalidates its XCD's L2 and its CU's L1).  Counts and generations are
+// never reset within a launch, so a workgroup knows both opening values
+// without reading anything first, and opening the barrier takes one store.
+// That store needs no fence of its own: every workgroup's writes reached
+// memory before its increment, and the store is issued only after the last
+// increment has returned.  All atomics are relaxed and agent-scoped.  The
+// failure flag is read before the workgroup gathers, so that its latency
+// overlaps the wait for the other wavefronts.
+__device__ inline void grid_barrier(GridBar& gb) {
+  unsigned* count = gb.bar;
+  unsigned* gen = gb.bar + 32;
+  unsigned f = 0u;
+  if (threadIdx.x == 0) f = bar_load(gb.bar + 64);
   __syncthreads();
-  if (threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0 && f == 0u) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(gen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      bar_wait(bar, gen, g);
-    }
+    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gb.next)
+      __hip_atomic_store(gen, gb.gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      bar_reach(gb.bar, gen, gb.gnext);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  gb.next += gridDim.x;
+  gb.gnext += 1u;
   __syncthreads();
 }
 
-// XCD of the running workgroup (hardware register XCC_ID, bits 3:0) and,
-// after xcd_register, the number of the launch's workgroups on it and the
-// number of XCDs that hold any.
+// XCD of the running workgroup (hardware register XCC_ID, bits 3:0), and
+// after xcd_register the number of the launch's workgroups on it, the number
+// of XCDs that hold any, and the opening values of the next grid_sync: the
+// XCD's arrival count, the count of XCDs arrived, and the XCD's generation.
 struct XcdSync {
   unsigned x, nx, nact;
+  unsigned lnext, tnext, gnext;
 };
 
 __device__ inline unsigned xcc_id() {
@@ -735,21 +761,23 @@ __device__ inline unsigned xcc_id() {
 }
 
 // Called once by every thread at the start of a launch that uses grid_sync
-// (the registration counters were cleared by fm_bar_reset); ends with a
-// grid_barrier.
-__device__ inline XcdSync xcd_register(unsigned* __restrict__ bar) {
+// (the counters were cleared by fm_bar_reset); ends with a grid_barrier on gb.
+__device__ inline XcdSync xcd_register(GridBar& gb) {
   XcdSync xs;
   xs.x = xcc_id();
   if (threadIdx.x == 0)
-    __hip_atomic_fetch_add(bar + kBarXcdReg + 32 * xs.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  grid_barrier(bar);
+    __hip_atomic_fetch_add(gb.bar + kBarXcdReg + 32 * xs.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  grid_barrier(gb);
   xs.nx = 0;
   xs.nact = 0;
   for (int k = 0; k < kMaxXcd; ++k) {
-    const unsigned n = __hip_atomic_load(bar + kBarXcdReg + 32 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned n = bar_load(gb.bar + kBarXcdReg + 32 * k);
     if ((unsigned)k == xs.x) xs.nx = n;
     xs.nact += n > 0u ? 1u : 0u;
   }
+  xs.lnext = xs.nx;
+  xs.tnext = xs.nact;
+  xs.gnext = 1u;
   return xs;
 }
 
@@ -758,41 +786,38 @@ __device__ inline XcdSync xcd_register(unsigned* __restrict__ bar) {
 // served by the XCD's L2).  Cache maintenance runs once per XCD instead of
 // once per workgroup: each thread waits for its own stores to reach the L2;
 // the workgroups of an XCD count in on the XCD's counter; the last of them
-// writes the XCD's L2 back (agent-scope release), meets the other XCDs' last
-// arrivals on the top-level counter, invalidates the XCD's L2 (agent-scope
-// acquire; complete before it moves on) and moves the XCD's generation word,
-// which the XCD's other workgroups wait for.
-__device__ inline void grid_sync(unsigned* __restrict__ bar, const XcdSync& xs) {
-  unsigned* fail = bar + 64;
+// writes the XCD's L2 back (agent-scope release), counts the XCD in on the
+// top-level counter and waits for every XCD to have arrived, invalidates the
+// XCD's L2 (agent-scope acquire; complete before it moves on) and moves the
+// XCD's generation word, which the XCD's other workgroups wait for.  As in
+// grid_barrier, counts and generations only grow within a launch.
+__device__ inline void grid_sync(unsigned* __restrict__ bar, XcdSync& xs) {
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  unsigned f = 0u;
+  if (threadIdx.x == 0) f = bar_load(bar + 64);
   __syncthreads();
-  if (threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+  if (threadIdx.x == 0 && f == 0u) {
     unsigned* xc = bar + kBarXcdCount + 32 * xs.x;
     unsigned* xg = bar + kBarXcdGen + 32 * xs.x;
-    const unsigned g = __hip_atomic_load(xg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (__hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == xs.nx - 1) {
-      __hip_atomic_store(xc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_fetch_add(xc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == xs.lnext) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      unsigned* count = bar;
-      unsigned* gen = bar + 32;
-      const unsigned gt = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == xs.nact - 1) {
-        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        __hip_atomic_store(gen, gt + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        bar_wait(bar, gen, gt);
-      }
+      unsigned* top = bar + kBarTop;
+      if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u != xs.tnext)
+        bar_reach(bar, top, xs.tnext);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-      __hip_atomic_store(xg, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(xg, xs.gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      bar_wait(bar, xg, g);
+      bar_reach(bar, xg, xs.gnext);
     }
   }
+  xs.lnext += xs.nx;
+  xs.tnext += xs.nact;
+  xs.gnext += 1u;
   __syncthreads();
 }
 
-// Clears the arrival count and the launch's failure flag of a grid barrier
-// before a persistent launch (iterate.hip).
+// Clears the counts, generations and registrations of the grid barriers and
+// the launch's failure flag before a persistent launch (iterate.hip); every
+// launch that uses grid_barrier or grid_sync needs it.
 hipError_t fm_bar_reset(unsigned* bar, hipStream_t st);

@@ -202,6 +202,7 @@ __device__ inline void fo_store_rot(double* __restrict__ rot, int64_t c, float p
 
 template <typename WT>
 __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
+  GridBar gb = grid_bar(a.bar);
   __shared__ double lds[kSolveBlock / 64];
   const double iz = a.Z_dev ? 1.0 / (double)(*a.Z_dev > 0 ? *a.Z_dev : 1) : a.inv_Z;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
   const WT* W36 = reinterpret_cast<const WT*>(a.W36);
   const int64_t NR = (int64_t)a.N * 9;
   for (int64_t c = gwave; c < a.N; c += nwaves) fo_store_rot(a.rot, c, a.params[c * 9 + kq], lane);
-  grid_barrier(a.bar);
+  grid_barrier(gb);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
       const double t = block_sum(lsum, lds);
       if (threadIdx.x == 0) a.part[rb * gridDim.x + blockIdx.x] = t;
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
     if (a.trace && gtid == 0) {
       double t = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) t += a.part[rb * gridDim.x + b];

@@ -342,16 +342,21 @@ extern "C" fm_status fm_adam_step(fm_ctx* ctx, int64_t n, float* p, const float*
 
 // ------------------------------------------------------------------ fused persistent solve
 
-// Re-arms the barrier before a launch: arrival count and the launch's
-// failure flag (a launch that ended on a failed barrier leaves them set).
+// Re-arms the barriers before a launch: counts, generations and XCD
+// registrations start at 0, and the launch's failure flag is cleared (a
+// launch that ended on a failed barrier leaves it set).
 __global__ void k_bar_reset(unsigned* __restrict__ bar) {
   if (threadIdx.x == 0) {
     bar[0] = 0u;
+    bar[32] = 0u;
     bar[64] = 0u;
+    bar[kBarTop] = 0u;
   }
-  // grid_sync's per-XCD arrival counts and workgroup registrations
+  // grid_sync's per-XCD arrival counts, generations and workgroup
+  // registrations
   if (threadIdx.x < kMaxXcd) {
     bar[kBarXcdCount + 32 * threadIdx.x] = 0u;
+    bar[kBarXcdGen + 32 * threadIdx.x] = 0u;
     bar[kBarXcdReg + 32 * threadIdx.x] = 0u;
   }
 }
@@ -429,11 +434,11 @@ __device__ inline void row_camera_sums_slots(int lo, int hi, const float* __rest
 // Grid barrier of the fused loops: per-XCD (grid_sync, with the shared
 // arrays read through Arr<true, T>) or flat (grid_barrier, plain reads).
 template <bool XS>
-__device__ inline void loop_sync(unsigned* __restrict__ bar, const XcdSync& xs) {
+__device__ inline void loop_sync(GridBar& gb, XcdSync& xs) {
   if constexpr (XS)
-    grid_sync(bar, xs);
+    grid_sync(gb.bar, xs);
   else
-    grid_barrier(bar);
+    grid_barrier(gb);
 }
 
 template <typename WT, bool XS>
@@ -457,8 +462,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   const int row = lane >> 4, l16 = lane & 15, base = lane & ~15;
   const int64_t c_first = 4 * gwave + row, c_stride = 4 * nwaves;
   const int lo0 = c_first < a.N ? a.cam_ptr[c_first] : 0, hi0 = c_first < a.N ? a.cam_ptr[c_first + 1] : 0;
-  XcdSync xs = {0u, 0u, 0u};
-  if constexpr (XS) xs = xcd_register(a.bar);
+  GridBar gb = grid_bar(a.bar);
+  XcdSync xs = {};
+  if constexpr (XS) xs = xcd_register(gb);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     // iteration 0 runs Gram-Schmidt per pair; later iterations read the
@@ -468,7 +474,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
                                                 qj1);
     const double t = block_sum(v, lds);
     if (threadIdx.x == 0) a.loss_part[blockIdx.x] = t;
-    loop_sync<XS>(a.bar, xs);
+    loop_sync<XS>(gb, xs);
     if (a.loss_trace && gtid == 0) {
       double s = 0.0;
       const Arr<XS, double> lp(a.loss_part);
@@ -535,7 +541,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
         a.rot[c * 9 + l16] = rv;
       }
     }
-    loop_sync<XS>(a.bar, xs);
+    loop_sync<XS>(gb, xs);
   }
 }
 
@@ -619,11 +625,12 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
     const float p0 = a.params[c * 9 + kq];
     cam_store_rot(a.rot, c, p0, lane);
   }
-  XcdSync xs = {0u, 0u, 0u};
+  GridBar gb = grid_bar(a.bar);
+  XcdSync xs = {};
   if constexpr (XS)
-    xs = xcd_register(a.bar);
+    xs = xcd_register(gb);
   else
-    grid_barrier(a.bar);
+    grid_barrier(gb);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
@@ -688,7 +695,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
       const double t = block_sum(lsum, lds);
       if (threadIdx.x == 0) a.loss_part[rb * gridDim.x + blockIdx.x] = t;
     }
-    loop_sync<XS>(a.bar, xs);
+    loop_sync<XS>(gb, xs);
     if (a.loss_trace && gtid == 0) {
       double sum = 0.0;
       const Arr<XS, double> lp(a.loss_part);

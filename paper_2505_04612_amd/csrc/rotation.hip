@@ -174,6 +174,7 @@ __device__ inline void ra_store_rot(double* __restrict__ rot, int64_t c, float p
 }
 
 __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
+  GridBar gb = grid_bar(a.bar);
   __shared__ double lds[kSolveBlock / 64];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
   }
   RowList L0 = {0, 0, {-1, -1, -1, -1}};
   if (c_first < a.N) L0 = row_list(a.cam_ptr, a.cam_items, (int)c_first, l16);
-  grid_barrier(a.bar);
+  grid_barrier(gb);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     double v = 0.0;
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
       const double t = block_sum(v, lds);
       if (threadIdx.x == 0) a.part[blockIdx.x] = t;
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
     if (a.trace && gtid == 0) {
       double s = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) s += a.part[b];
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve(RaArgs a) {
       }
       ra_store_rot(a.rot, c, pq, base, l16, live);
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
   }
 }
 
@@ -283,6 +284,7 @@ struct RaCamArgs {
 };
 
 __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
+  GridBar gb = grid_bar(a.bar);
   __shared__ double lds[kSolveBlock / 64];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
   const int64_t NR = (int64_t)a.N * 9;
   // rotations of the initial parameters (buffer 0)
   for (int64_t c = gwave; c < a.N; c += nwaves) ra_store_rot(a.rot, c, a.params[6 * c + kq], 0, lane, true);
-  grid_barrier(a.bar);
+  grid_barrier(gb);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
       const double t = block_sum(lsum, lds);
       if (threadIdx.x == 0) a.part[rb * gridDim.x + blockIdx.x] = t;
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
     if (a.trace && gtid == 0) {
       double t = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) t += a.part[rb * gridDim.x + b];
@@ -399,11 +401,11 @@ struct LzArgs {
 
 // Sum over the grid of one double per thread, returned in every thread
 // (per-wavefront sums, then every workgroup adds them in the same order).
-__device__ inline double grid_allsum(double v, double* part, double* lds1, unsigned* bar, int64_t gwave, int64_t nwaves) {
+__device__ inline double grid_allsum(double v, double* part, double* lds1, GridBar& gb, int64_t gwave, int64_t nwaves) {
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
   if ((threadIdx.x & 63) == 0) part[gwave] = v;
-  grid_barrier(bar);
+  grid_barrier(gb);
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int64_t k = 0; k < nwaves; ++k) t += part[k];
@@ -552,6 +554,7 @@ constexpr int kLzMaxSteps = 4096;
 constexpr double kLzTol = 1e-11;
 
 __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
+  GridBar gb = grid_bar(a.bar);
   extern __shared__ double hs[];   // [m + 1] dots of the current step, then [1] broadcast
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -563,9 +566,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
   // q0 = start / |start|
   double acc = 0.0;
   for (int64_t i = gtid; i < n; i += gsize) acc += a.start[i] * a.start[i];
-  const double inv0 = 1.0 / sqrt(grid_allsum(acc, a.part, lds1, a.bar, gwave, nwaves));
+  const double inv0 = 1.0 / sqrt(grid_allsum(acc, a.part, lds1, gb, gwave, nwaves));
   for (int64_t i = gtid; i < n; i += gsize) a.V[i] = a.start[i] * inv0;
-  grid_barrier(a.bar);
+  grid_barrier(gb);
   int m = a.m;
   bool have_s = false;
   for (int k = 0; k < a.m; ++k) {
@@ -579,7 +582,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
         if (l16 < 3) a.w[3 * c + l16] = pick3d(y, l16);
       }
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
     // two passes of classical Gram-Schmidt against q_0 .. q_k
     double alpha_k = 0.0;
     bool stop = false;
@@ -600,7 +603,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
         for (int s = 32; s >= 1; s >>= 1) d += __shfl_xor(d, s);
         if (lane == 0) a.h[j] = d;
       }
-      grid_barrier(a.bar);
+      grid_barrier(gb);
       for (int j = threadIdx.x; j <= k; j += blockDim.x) hs[j] = a.h[j];
       __syncthreads();
       alpha_k += hs[k];
@@ -623,9 +626,9 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
       }
       __syncthreads();   // hs is rewritten by the next pass
       if (pass == 0) {
-        grid_barrier(a.bar);
+        grid_barrier(gb);
       } else {
-        const double b = sqrt(grid_allsum(nrm, a.part, lds1, a.bar, gwave, nwaves));
+        const double b = sqrt(grid_allsum(nrm, a.part, lds1, gb, gwave, nwaves));
         if (gtid == 0) {
           a.alpha[k] = alpha_k;
           a.beta[k] = b;
@@ -636,7 +639,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
         if (!(b > 1e-12 * fmax(1.0, fabs(alpha_k))) || k + 1 == a.m) {
           stop = true;
         } else if ((k + 1) % kLzCheck == 0) {
-          grid_barrier(a.bar);   // alpha, beta of this step visible
+          grid_barrier(gb);   // alpha, beta of this step visible
           if (gtid == 0) {
             const double theta = tridiag_smallest(a.alpha, a.beta, k + 1, a.s, a.s + a.m);
             double tn = 0.0;
@@ -644,7 +647,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
             a.info[0] = theta;
             a.h[a.m] = (fabs(b * a.s[k]) <= kLzTol * fmax(tn, 1e-300)) ? 1.0 : 0.0;
           }
-          grid_barrier(a.bar);
+          grid_barrier(gb);
           stop = a.h[a.m] != 0.0;
           have_s = stop;
         }
@@ -658,14 +661,14 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_lanczos(LzArgs a) {
       }
     }
     if (stop) break;
-    grid_barrier(a.bar);
+    grid_barrier(gb);
   }
-  grid_barrier(a.bar);
+  grid_barrier(gb);
   if (gtid == 0) {
     if (!have_s) a.info[0] = tridiag_smallest(a.alpha, a.beta, m, a.s, a.s + a.m);
     a.info[1] = (double)m;
   }
-  grid_barrier(a.bar);
+  grid_barrier(gb);
   for (int64_t i = gtid; i < n; i += gsize) {
     double x = 0.0;
     for (int j = 0; j < m; ++j) x += a.s[j] * a.V[(int64_t)j * n + i];

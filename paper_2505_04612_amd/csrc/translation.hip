@@ -281,6 +281,7 @@ __device__ inline void ta_camera_group(const TaArgs& a, const RowList& L, int64_
 }
 
 __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
+  GridBar gb = grid_bar(a.bar);
   __shared__ double lds[kSolveBlock / 64];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
       ta_pair_runs(a.centres, a.N, a.runs, a.P, n, a.cams[2 * n], a.cams[2 * n + 1], d, a.invP, a.rec);
     }
     if (a.trace) ta_loss_partials(a.rec, a.P, a.runs, a.part, a.part_stride, gtid, gsize, lds);
-    grid_barrier(a.bar);
+    grid_barrier(gb);
     if (a.trace && gtid == 0) {
       for (int r = 0; r < a.runs; ++r) {
         double s = 0.0;
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve(TaArgs a) {
         if (r0 < a.runs) ta_camera_group<1>(a, L, c, l16, r0, lr, bc1, bc2);
       }
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
   }
 }
 
@@ -436,6 +437,7 @@ __device__ inline void ta_cam_group(const TaCamArgs& a, const float* __restrict_
 }
 
 __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
+  GridBar gb = grid_bar(a.bar);
   __shared__ double wloss[kSolveBlock / 64][kTaMaxRuns];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
         a.part[rb * RS + threadIdx.x * a.part_stride + blockIdx.x] = t;
       }
     }
-    grid_barrier(a.bar);
+    grid_barrier(gb);
     if (a.trace && gtid == 0) {
       for (int r = 0; r < a.runs; ++r) {
         double t = 0.0;
