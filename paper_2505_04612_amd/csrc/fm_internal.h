@@ -746,6 +746,39 @@ __device__ inline void grid_barrier(GridBar& gb) {
   __syncthreads();
 }
 
+// Store at agent scope (relaxed atomic): written through to memory, so it is
+// visible on every XCD once complete, with no L2 write-back.
+template <typename T>
+__device__ inline void store_wt(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// grid_barrier for loops that write everything other workgroups read after
+// the barrier with store_wt: the release is only each thread's wait for its
+// own stores to complete, without the write-back of the XCD's L2 (which
+// would sit on the path of the last workgroup to arrive); the acquire still
+// invalidates the L2, so that plain loads after the barrier see the other
+// workgroups' stores.  Data a workgroup alone reads back (its own Adam
+// moments) may still be written with plain stores.
+__device__ inline void grid_barrier_wt(GridBar& gb) {
+  unsigned* count = gb.bar;
+  unsigned* gen = gb.bar + 32;
+  unsigned f = 0u;
+  if (threadIdx.x == 0) f = bar_load(gb.bar + 64);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  __syncthreads();
+  if (threadIdx.x == 0 && f == 0u) {
+    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gb.next)
+      __hip_atomic_store(gen, gb.gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      bar_reach(gb.bar, gen, gb.gnext);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  gb.next += gridDim.x;
+  gb.gnext += 1u;
+  __syncthreads();
+}
+
 // XCD of the running workgroup (hardware register XCC_ID, bits 3:0), and
 // after xcd_register the number of the launch's workgroups on it, the number
 // of XCDs that hold any, and the opening values of the next grid_sync: the

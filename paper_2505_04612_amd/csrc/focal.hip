@@ -183,7 +183,9 @@ struct FoSolveArgs {
   int64_t lr_step0, lr_total, adam_step0;
 };
 
-// Rotation of the parameters p0 held by lanes 0..5, stored by lanes 0..8.
+// Rotation of the parameters p0 held by lanes 0..5, stored by lanes 0..8
+// (written through to memory if WTS).
+template <bool WTS>
 __device__ inline void fo_store_rot(double* __restrict__ rot, int64_t c, float p0, int lane) {
   double a1[3], a2[3], R[3][3];
 #pragma unroll
@@ -196,7 +198,10 @@ __device__ inline void fo_store_rot(double* __restrict__ rot, int64_t c, float p
     double rv = R[0][0];
 #pragma unroll
     for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
-    rot[c * 9 + lane] = rv;
+    if constexpr (WTS)
+      store_wt(&rot[c * 9 + lane], rv);
+    else
+      rot[c * 9 + lane] = rv;
   }
 }
 
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
   const int kq = lane < 9 ? lane : 8;
   const WT* W36 = reinterpret_cast<const WT*>(a.W36);
   const int64_t NR = (int64_t)a.N * 9;
-  for (int64_t c = gwave; c < a.N; c += nwaves) fo_store_rot(a.rot, c, a.params[c * 9 + kq], lane);
+  for (int64_t c = gwave; c < a.N; c += nwaves) fo_store_rot<false>(a.rot, c, a.params[c * 9 + kq], lane);
   grid_barrier(gb);
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
@@ -275,23 +280,25 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
       gs_adjoint(acc, a1, a2, g);
       const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
       const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+      // parameters, scales, rotations and loss partials are read by other
+      // workgroups after the barrier: written through to memory
       if (lane < 9) {
-        pw[c * 9 + lane] = pq;
+        store_wt(&pw[c * 9 + lane], pq);
         a.m[c * 9 + lane] = mq;
         a.v[c * 9 + lane] = vq;
       }
       if (lane == 9) {
-        fw[c] = adam_update(f0, (float)fsum, mf, vf, a.lr_phi * frac, a.b1, a.b2, a.eps, bc1, bc2);
+        store_wt(&fw[c], adam_update(f0, (float)fsum, mf, vf, a.lr_phi * frac, a.b1, a.b2, a.eps, bc1, bc2));
         a.m_phi[c] = mf;
         a.v_phi[c] = vf;
       }
-      fo_store_rot(rw, c, pq, lane);
+      fo_store_rot<true>(rw, c, pq, lane);
     }
     if (a.trace) {
       const double t = block_sum(lsum, lds);
-      if (threadIdx.x == 0) a.part[rb * gridDim.x + blockIdx.x] = t;
+      if (threadIdx.x == 0) store_wt(&a.part[rb * gridDim.x + blockIdx.x], t);
     }
-    grid_barrier(gb);
+    grid_barrier_wt(gb);
     if (a.trace && gtid == 0) {
       double t = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) t += a.part[rb * gridDim.x + b];

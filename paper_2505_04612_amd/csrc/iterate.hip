@@ -577,7 +577,8 @@ struct CamSolveArgs {
 };
 
 // Rotation of the parameters p0 held by lanes 0..5 of the wavefront, stored
-// by lanes 0..8 at rot[c].
+// by lanes 0..8 at rot[c] (written through to memory if WTS).
+template <bool WTS>
 __device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float p0, int lane) {
   double a1[3], a2[3], R[3][3];
 #pragma unroll
@@ -590,7 +591,10 @@ __device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float 
     double rv = R[0][0];
 #pragma unroll
     for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
-    rot[c * 9 + lane] = rv;
+    if constexpr (WTS)
+      store_wt(&rot[c * 9 + lane], rv);
+    else
+      rot[c * 9 + lane] = rv;
   }
 }
 
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
   // rotations of the initial parameters (buffer 0)
   for (int64_t c = gwave; c < a.N; c += nwaves) {
     const float p0 = a.params[c * 9 + kq];
-    cam_store_rot(a.rot, c, p0, lane);
+    cam_store_rot<false>(a.rot, c, p0, lane);
   }
   GridBar gb = grid_bar(a.bar);
   XcdSync xs = {};
@@ -684,18 +688,32 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
       gs_adjoint(acc, f, a2, g);
       const double lr = (lane < 6 ? a.lr_rot : a.lr_t) * frac;
       const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+      // what other workgroups read (parameters, rotations, loss partials)
+      // is written through to memory on the flat barrier's path; the Adam
+      // moments stay with this wavefront
       if (lane < 9) {
-        pw[c * 9 + lane] = pq;
+        if constexpr (XS)
+          pw[c * 9 + lane] = pq;
+        else
+          store_wt(&pw[c * 9 + lane], pq);
         a.m[c * 9 + lane] = mq;
         a.v[c * 9 + lane] = vq;
       }
-      cam_store_rot(rw, c, pq, lane);
+      cam_store_rot<!XS>(rw, c, pq, lane);
     }
     if (a.loss_trace) {
       const double t = block_sum(lsum, lds);
-      if (threadIdx.x == 0) a.loss_part[rb * gridDim.x + blockIdx.x] = t;
+      if (threadIdx.x == 0) {
+        if constexpr (XS)
+          a.loss_part[rb * gridDim.x + blockIdx.x] = t;
+        else
+          store_wt(&a.loss_part[rb * gridDim.x + blockIdx.x], t);
+      }
     }
-    loop_sync<XS>(gb, xs);
+    if constexpr (XS)
+      grid_sync(a.bar, xs);
+    else
+      grid_barrier_wt(gb);
     if (a.loss_trace && gtid == 0) {
       double sum = 0.0;
       const Arr<XS, double> lp(a.loss_part);

@@ -155,7 +155,8 @@ struct RaArgs {
 };
 
 // Rotation of camera c from the parameters p0 held by lanes 0..5 of its row,
-// stored by lanes 0..8.
+// stored by lanes 0..8 (written through to memory if WTS).
+template <bool WTS = false>
 __device__ inline void ra_store_rot(double* __restrict__ rot, int64_t c, float p0, int base, int l16, bool live) {
   double a1[3], a2[3], R[3][3];
 #pragma unroll
@@ -169,7 +170,10 @@ __device__ inline void ra_store_rot(double* __restrict__ rot, int64_t c, float p
     double rv = R[0][0];
 #pragma unroll
     for (int j = 1; j < 9; ++j) rv = (l16 == j) ? R[j / 3][j % 3] : rv;
-    rot[c * 9 + l16] = rv;
+    if constexpr (WTS)
+      store_wt(&rot[c * 9 + l16], rv);
+    else
+      rot[c * 9 + l16] = rv;
   }
 }
 
@@ -337,18 +341,20 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
       }
       gs_adjoint(acc, a1, a2, g);
       const float pq = adam_update(p0, (float)pick9(g, kq), mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
+      // parameters, rotations and loss partials are read by other
+      // workgroups after the barrier: written through to memory
       if (lane < 6) {
-        pw[6 * c + lane] = pq;
+        store_wt(&pw[6 * c + lane], pq);
         a.m[6 * c + lane] = mq;
         a.v[6 * c + lane] = vq;
       }
-      ra_store_rot(rw, c, pq, 0, lane, true);
+      ra_store_rot<true>(rw, c, pq, 0, lane, true);
     }
     if (a.trace) {
       const double t = block_sum(lsum, lds);
-      if (threadIdx.x == 0) a.part[rb * gridDim.x + blockIdx.x] = t;
+      if (threadIdx.x == 0) store_wt(&a.part[rb * gridDim.x + blockIdx.x], t);
     }
-    grid_barrier(gb);
+    grid_barrier_wt(gb);
     if (a.trace && gtid == 0) {
       double t = 0.0;
       for (int b = 0; b < (int)gridDim.x; ++b) t += a.part[rb * gridDim.x + b];

@@ -421,7 +421,7 @@ __device__ inline void ta_cam_group(const TaCamArgs& a, const float* __restrict_
   for (int j = 1; j < 3 * G; ++j) gl = (l3 == j) ? acc[j] : gl;
   const float pq = adam_update(p0, (float)gl, mq, vq, lr, a.b1, a.b2, a.eps, bc1, bc2);
   if (lane < 3 * G) {
-    pw[own] = pq;
+    store_wt(&pw[own], pq);   // read by other workgroups after the barrier
     a.m[own] = mq;
     a.v[own] = vq;
   }
@@ -471,10 +471,11 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
       if ((int)threadIdx.x < a.runs) {
         double t = 0.0;
         for (int w = 0; w < kSolveBlock / 64; ++w) t += wloss[w][threadIdx.x];
-        a.part[rb * RS + threadIdx.x * a.part_stride + blockIdx.x] = t;
+        store_wt(&a.part[rb * RS + threadIdx.x * a.part_stride + blockIdx.x], t);
       }
     }
-    grid_barrier(gb);
+    // everything other workgroups read after it was written with store_wt
+    grid_barrier_wt(gb);
     if (a.trace && gtid == 0) {
       for (int r = 0; r < a.runs; ++r) {
         double t = 0.0;
