@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256, 4) void k_mlp_forward(int64_t M, const float* 
 // Backward of sum_m dout[m] * sigmoid(z3[m]) from the stored activations.
 // Each wavefront accumulates its gradient contributions in registers and
 // writes them to its own slot of `part` [waves, kG_N]; k_mlp_reduce adds the
-// slots in slot order.
+// slots in a fixed order.
 __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __restrict__ feats, MlpPtrs w,
                                                       const _Float16* __restrict__ act,
                                                       const float* __restrict__ dout, float* __restrict__ part) {
@@ -266,11 +266,35 @@ struct MlpGradPtrs {
   float *W1, *b1, *W2, *b2, *W3, *b3;
 };
 
-__global__ void k_mlp_reduce(const float* __restrict__ part, int64_t slots, MlpGradPtrs g) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kG_N) return;
+// Sum of the gradient slots, entry by entry: each workgroup takes 64
+// entries (one per lane, coalesced over the slots' rows); its kRedWaves
+// wavefronts take consecutive ranges of the slots, eight running sums per
+// lane so that eight loads are in flight, and the wavefronts' sums are added
+// in wavefront order: a fixed order for any slot count.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void k_mlp_reduce(const float* __restrict__ part, int64_t slots,
+                                                              MlpGradPtrs g) {
+  __shared__ float red[kRedWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int64_t per = (slots + kRedWaves - 1) / kRedWaves;
+  const int64_t k0 = wave * per, k1 = min(slots, k0 + per);
+  float p[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (e < kG_N) {
+    int64_t k = k0;
+    for (; k + 8 <= k1; k += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] += part[(k + u) * kG_N + e];
+    }
+    for (; k < k1; ++k) p[0] += part[k * kG_N + e];
+  }
+  red[wave][lane] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+  __syncthreads();
+  if (wave != 0 || e >= kG_N) return;
   float s = 0.0f;
-  for (int64_t k = 0; k < slots; ++k) s += part[k * kG_N + e];
+#pragma unroll
+  for (int w = 0; w < kRedWaves; ++w) s += red[w][lane];
   if (e < kG_b2) g.W2[e] = s;
   else if (e < kG_W3) g.b2[e - kG_b2] = s;
   else if (e < kG_b3) g.W3[e - kG_W3] = s;
@@ -407,7 +431,7 @@ extern "C" fm_status fm_mlp_backward(fm_ctx* ctx, int64_t M, const float* feats,
     FM_CHECK_LAUNCH(ctx);
   }
   MlpGradPtrs gp{g->W1, g->b1, g->W2, g->b2, g->W3, g->b3};
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(kG_N, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, part,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kG_N + 63) / 64), dim3(64 * kRedWaves), 0, (hipStream_t)stream, part,
                      M > 0 ? slots : (int64_t)0, gp);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
@@ -503,7 +527,7 @@ extern "C" fm_status fm_mlp_backward_noalloc(fm_ctx* ctx, int64_t M, const float
     FM_CHECK_LAUNCH(ctx);
   }
   MlpGradPtrs gp{g->W1, g->b1, g->W2, g->b2, g->W3, g->b3};
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(kG_N, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, part,
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kG_N + 63) / 64), dim3(64 * kRedWaves), 0, (hipStream_t)stream, part,
                      M > 0 ? slots : (int64_t)0, gp);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
