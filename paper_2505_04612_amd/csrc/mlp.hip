@@ -137,6 +137,10 @@ __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __
                                                       const float* __restrict__ dout, float* __restrict__ part) {
   __shared__ MlpLds s;
   __shared__ _Float16 T[4][16][kHid + 4];   // per-wave transpose of dh2
+  // per-wave copy of the tile's activations (16 matches x 128, rows padded
+  // so that the four row groups a read instruction touches use different
+  // banks): read from global memory in 16-byte pieces, then per unit
+  __shared__ _Float16 Ast[4][16][2 * kHid + 8];
   load_lds(w, s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
@@ -159,6 +163,22 @@ __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __
   for (int64_t base = (int64_t)blockIdx.x * 4; base < ntiles; base += (int64_t)gridDim.x * 4) {
     const int64_t tile = base + wave;
     const bool tv = tile < ntiles;
+    // the tile's 16 x 128 activations (4 KB, 256 pieces of 16 bytes; rows
+    // past M are zeros)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int idx = 64 * t + lane, row = idx >> 4, piece = idx & 15;
+      const int64_t m = tile * 16 + row;
+      h8 v;
+      if (tv && m < M) {
+        v = *reinterpret_cast<const h8*>(act + m * 128 + 8 * piece);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (_Float16)0.0f;
+      }
+      *reinterpret_cast<h8*>(&Ast[wave][row][8 * piece]) = v;
+    }
+    __syncthreads();
     // this lane's result-layout rows 4q + j
     float h2[4][4], h1[4][4], d3[4], x[4][3];
 #pragma unroll
@@ -168,8 +188,8 @@ __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __
       const int64_t rc = ok ? row : 0;
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-        h2[j][nt] = ok ? (float)act[rc * 128 + 64 + 16 * nt + r] : 0.0f;
-        h1[j][nt] = ok ? (float)act[rc * 128 + 16 * nt + r] : 0.0f;
+        h2[j][nt] = (float)Ast[wave][4 * q + j][64 + 16 * nt + r];
+        h1[j][nt] = (float)Ast[wave][4 * q + j][16 * nt + r];
       }
       float z = 0.0f;
 #pragma unroll
