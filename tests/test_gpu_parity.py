@@ -295,6 +295,46 @@ def test_fused_solve_matches_oracle_steps(fm, ctx):
     assert rot.max() < 1e-3 and tra.max() < 1e-2
 
 
+def test_random_centre_start_follows_oracle_steps(fm, ctx):
+    """The tiny recipe's configured start, N(0, I) camera centres
+    (init_trans="random"): from there the endpoint of a whole solve depends
+    chaotically on rounding, so what is compared is the start itself.  50
+    fused iterations on the unit-weight Gram (what the first IRLS round
+    runs) equal 50 oracle Adam steps, trace and poses; and a whole solve
+    from that start stays finite and lowers the loss."""
+    from paper_2505_04612_amd import solver
+    sc = scene("tiny", init_trans="random")
+    assert np.abs(sc.t_init).max() > 0.5      # centres far from the truth, not perturbed
+    s = _scene_on_gpu(fm, ctx, sc, torch.float64)
+    W64, _ = fm.build_pair_grams(s)
+    th = _theta(sc)
+    p = torch.from_numpy(th.copy()).to(ctx.device)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    K = 50
+    trace = torch.empty(K, dtype=torch.float64, device=ctx.device)
+    inv_Z = 1.0 / sc.num_matches
+    fm.epipolar_solve(s, W64, p, m, v, K, 3e-3, 1e-2, 1e-3, 0, K, 0, inv_Z=inv_Z, loss_trace=trace)
+    W = expand36(W64.cpu().numpy())
+    sched = ea.Schedule(iters=K, round_len=K, lr_rot=f32(3e-3), lr_t=f32(1e-2), lr_final_frac=f32(1e-3),
+                        beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-12))
+    tr = th.astype(np.float64)
+    mr, vr = np.zeros_like(tr), np.zeros_like(tr)
+    losses = []
+    for k in range(K):
+        L, g = ea.loss_grad(tr, sc.pairs, W, inv_Z)
+        losses.append(L)
+        tr, mr, vr = ea.adam_step(tr, g, mr, vr, k + 1, ea.lr_at(sched, k), sched.beta1, sched.beta2, sched.eps)
+    assert s.barrier_failures() == 0
+    assert np.allclose(trace.cpu().numpy(), losses, rtol=1e-5)
+    rot, tra = ea.relative_pose_errors(p.cpu().numpy().astype(np.float64), tr, sc.pairs)
+    assert rot.max() < 1e-3 and tra.max() < 1e-2, (rot.max(), tra.max())
+    p2, tr2, _ = solver.solve(s, torch.from_numpy(th).to(ctx.device), solver.Schedule(iters=500, round_len=100))
+    assert torch.isfinite(p2).all()
+    tr2 = tr2.cpu().numpy()
+    assert np.isfinite(tr2).all() and tr2[-1] < tr2[0], (tr2[0], tr2[-1])
+
+
 @pytest.mark.parametrize("name", ["tiny", "medium"])
 def test_fused_solve_grid_invariance(fm, ctx, name):
     """The fused loop's camera sums run in a fixed order, so the parameters
