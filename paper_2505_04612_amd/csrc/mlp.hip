@@ -32,6 +32,8 @@ struct MlpPtrs {
 __device__ inline f4 mfma16(h4 a, h4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
 __device__ inline f4 mfma32(h8 a, h8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
 
+constexpr float kLog2e = 1.4426950408889634f;
+
 struct MlpLds {
   float W1[kHid * 3], b1[kHid], b2[kHid], W3[kHid], mean[3], rstd[3], b3;
 };
@@ -120,11 +122,14 @@ __global__ __launch_bounds__(256, 4) void k_mlp_forward(int64_t M, const float* 
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) part[j] += __shfl_xor(part[j], o);
+    // the sigmoid once per lane, without divergence: lane r < 4 of each
+    // quarter takes row 4q + r (hardware 2^x and reciprocal, ~1 ulp each)
+    float zr = part[0];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t row = tile * 16 + 4 * q + j;
-      if (r == j && row < M) out[row] = out_scale / (1.0f + expf(-(part[j] + s.b3)));
-    }
+    for (int j = 1; j < 4; ++j) zr = r == j ? part[j] : zr;
+    const int64_t orow = tile * 16 + 4 * q + r;
+    const float e = __builtin_amdgcn_exp2f(-(zr + s.b3) * kLog2e);
+    if (r < 4 && orow < M) out[orow] = out_scale * __builtin_amdgcn_rcpf(1.0f + e);
   }
 }
 
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(256) void k_mlp_backward(int64_t M, const float* __
       for (int nt = 0; nt < 4; ++nt) z = fmaf(s.W3[16 * nt + r], h2[j][nt], z);
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) z += __shfl_xor(z, o);
-      const float sg = 1.0f / (1.0f + expf(-(z + s.b3)));
+      const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-(z + s.b3) * kLog2e));
       d3[j] = ok ? dout[rc] * sg * (1.0f - sg) : 0.0f;
       if (ok) load_x(feats, rc, s, x[j]);
       else x[j][0] = x[j][1] = x[j][2] = 0.0f;
