@@ -598,6 +598,35 @@ __device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float 
   }
 }
 
+// Gram-Schmidt of the parameters p0 held by lanes 0..5 of the wavefront (a2
+// receives the second column's parameters).
+__device__ inline Gs cam_gs(float p0, double a2[3]) {
+  double a1[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    a1[j] = (double)__shfl(p0, j);
+    a2[j] = (double)__shfl(p0, 3 + j);
+  }
+  return gs_forward(a1, a2);
+}
+
+// Rotation of an already formed Gram-Schmidt, stored by lanes 0..8 at
+// rot[c] (written through to memory if WTS).
+template <bool WTS>
+__device__ inline void cam_store_gs(double* __restrict__ rot, int64_t c, const Gs& f, int lane) {
+  double R[3][3];
+  gs_matrix(f, R);
+  if (lane < 9) {
+    double rv = R[0][0];
+#pragma unroll
+    for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
+    if constexpr (WTS)
+      store_wt(&rot[c * 9 + lane], rv);
+    else
+      rot[c * 9 + lane] = rv;
+  }
+}
+
 template <typename WT, bool XS>
 __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
   __shared__ double lds[kCamBlock / 64];
@@ -629,6 +658,20 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
     const float p0 = a.params[c * 9 + kq];
     cam_store_rot<false>(a.rot, c, p0, lane);
   }
+  // the wavefront's first camera stays in registers for the launch: its
+  // parameters, Adam moments and their Gram-Schmidt, carried from one
+  // iteration's update to the next instead of reloaded (after the barrier's
+  // invalidation) and recomputed; its moments are stored once at the end
+  const bool own = gwave < a.N;
+  float p_own = 0.0f, m_own = 0.0f, v_own = 0.0f;
+  double a2_own[3] = {0.0, 1.0, 0.0};
+  Gs f_own{};
+  if (own) {
+    p_own = a.params[gwave * 9 + kq];
+    m_own = a.m[gwave * 9 + kq];
+    v_own = a.v[gwave * 9 + kq];
+    f_own = cam_gs(p_own, a2_own);
+  }
   GridBar gb = grid_bar(a.bar);
   XcdSync xs = {};
   if constexpr (XS)
@@ -651,18 +694,27 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
     for (int64_t c = gwave; c < a.N; c += nwaves) {
       const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
       // the camera's own parameters and moments (lanes 9..63 read entry 8;
-      // m and v are read and written by this wavefront alone)
-      const float p0 = Arr<XS, float>(pr)[c * 9 + kq];
-      float mq = a.m[c * 9 + kq], vq = a.v[c * 9 + kq];
-      // Gram-Schmidt of the camera's own parameters, needed by the adjoint
-      // below, ahead of the pair evaluations (it overlaps their loads)
-      double a1[3], a2[3], g[9];
+      // m and v are read and written by this wavefront alone) and their
+      // Gram-Schmidt, needed by the adjoint below: from registers for the
+      // first camera, else loaded and formed ahead of the pair evaluations
+      // (so that it overlaps their loads)
+      const bool first_cam = c == gwave;
+      float p0, mq, vq;
+      double a2[3], g[9];
+      Gs f;
+      if (first_cam) {
+        p0 = p_own;
+        mq = m_own;
+        vq = v_own;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        a1[j] = (double)__shfl(p0, j);
-        a2[j] = (double)__shfl(p0, 3 + j);
+        for (int j = 0; j < 3; ++j) a2[j] = a2_own[j];
+        f = f_own;
+      } else {
+        p0 = Arr<XS, float>(pr)[c * 9 + kq];
+        mq = a.m[c * 9 + kq];
+        vq = a.v[c * 9 + kq];
+        f = cam_gs(p0, a2);
       }
-      const Gs f = gs_forward(a1, a2);
       // this camera's side of each of its pairs: body-frame rotation
       // gradient (om for camera j, -om for camera i) and dL/dt
       double acc6[6], acc[12];
@@ -696,10 +748,20 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
           pw[c * 9 + lane] = pq;
         else
           store_wt(&pw[c * 9 + lane], pq);
-        a.m[c * 9 + lane] = mq;
-        a.v[c * 9 + lane] = vq;
+        if (!first_cam) {
+          a.m[c * 9 + lane] = mq;
+          a.v[c * 9 + lane] = vq;
+        }
       }
-      cam_store_rot<!XS>(rw, c, pq, lane);
+      if (first_cam) {
+        p_own = pq;
+        m_own = mq;
+        v_own = vq;
+        f_own = cam_gs(pq, a2_own);
+        cam_store_gs<!XS>(rw, c, f_own, lane);
+      } else {
+        cam_store_rot<!XS>(rw, c, pq, lane);
+      }
     }
     if (a.loss_trace) {
       const double t = block_sum(lsum, lds);
@@ -720,6 +782,11 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
       for (int b = 0; b < (int)gridDim.x; ++b) sum += lp[rb * gridDim.x + b];
       a.loss_trace[k] = sum * iz;
     }
+  }
+  // the first camera's moments, kept in registers during the launch
+  if (own && lane < 9) {
+    a.m[gwave * 9 + lane] = m_own;
+    a.v[gwave * 9 + lane] = v_own;
   }
   // after an odd number of iterations the latest parameters are in buffer 1
   if (a.K & 1) {
