@@ -713,39 +713,6 @@ struct GridBar {
 
 __device__ inline GridBar grid_bar(unsigned* bar) { return GridBar{bar, gridDim.x, 1u}; }
 
-// Grid barrier of the persistent loops that share data through plain loads
-// and stores.  Thread 0 of each workgroup makes the workgroup's writes
-// visible (agent-scope release: writes back the dirty lines of its XCD's L2)
-// and counts itself in; the workgroup whose increment brings the count to
-// the barrier's opening value stores the new generation, which the others
-// wait for (polling a word that no arrival increments); each then acquires
-// (invalidates its XCD's L2 and its CU's L1).  Counts and generations are
-// never reset within a launch, so a workgroup knows both opening values
-// without reading anything first, and opening the barrier takes one store.
-// That store needs no fence of its own: every workgroup's writes reached
-// memory before its increment, and the store is issued only after the last
-// increment has returned.  All atomics are relaxed and agent-scoped.  The
-// failure flag is read before the workgroup gathers, so that its latency
-// overlaps the wait for the other wavefronts.
-__device__ inline void grid_barrier(GridBar& gb) {
-  unsigned* count = gb.bar;
-  unsigned* gen = gb.bar + 32;
-  unsigned f = 0u;
-  if (threadIdx.x == 0) f = bar_load(gb.bar + 64);
-  __syncthreads();
-  if (threadIdx.x == 0 && f == 0u) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gb.next)
-      __hip_atomic_store(gen, gb.gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      bar_reach(gb.bar, gen, gb.gnext);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  gb.next += gridDim.x;
-  gb.gnext += 1u;
-  __syncthreads();
-}
-
 // Store at agent scope (relaxed atomic): written through to memory, so it is
 // visible on every XCD once complete, with no L2 write-back.
 template <typename T>
@@ -753,21 +720,37 @@ __device__ inline void store_wt(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// grid_barrier for loops that write everything other workgroups read after
-// the barrier with store_wt: the release is only each thread's wait for its
-// own stores to complete, without the write-back of the XCD's L2 (which
-// would sit on the path of the last workgroup to arrive); the acquire still
-// invalidates the L2, so that plain loads after the barrier see the other
-// workgroups' stores.  Data a workgroup alone reads back (its own Adam
+// Flat grid barrier of the persistent loops.  Thread 0 of each workgroup
+// makes the workgroup's writes visible and counts itself in; the workgroup
+// whose increment brings the count to the barrier's opening value stores
+// the new generation, which the others wait for (polling a word that no
+// arrival increments); each then acquires (invalidates its XCD's L2 and its
+// CU's L1).  Counts and generations are never reset within a launch, so a
+// workgroup knows both opening values without reading anything first, and
+// opening the barrier takes one store.  That store needs no fence of its
+// own: every workgroup's writes reached memory before its increment, and
+// the store is issued only after the last increment has returned.  All
+// atomics are relaxed and agent-scoped; the fences carry the ordering.  The
+// failure flag is read before the workgroup gathers, so that its latency
+// overlaps the wait for the other wavefronts.
+//
+// Making the writes visible: with WT false (data shared through plain
+// stores) an agent-scope release, which writes back the dirty lines of the
+// XCD's L2; with WT true (everything other workgroups read after the
+// barrier was written with store_wt) only each thread's wait for its own
+// stores to complete, so no L2 write-back sits on the path of the last
+// workgroup to arrive.  Data a workgroup alone reads back (its own Adam
 // moments) may still be written with plain stores.
-__device__ inline void grid_barrier_wt(GridBar& gb) {
+template <bool WT>
+__device__ inline void grid_barrier_t(GridBar& gb) {
   unsigned* count = gb.bar;
   unsigned* gen = gb.bar + 32;
   unsigned f = 0u;
   if (threadIdx.x == 0) f = bar_load(gb.bar + 64);
-  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  if constexpr (WT) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
   if (threadIdx.x == 0 && f == 0u) {
+    if constexpr (!WT) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == gb.next)
       __hip_atomic_store(gen, gb.gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
@@ -778,6 +761,9 @@ __device__ inline void grid_barrier_wt(GridBar& gb) {
   gb.gnext += 1u;
   __syncthreads();
 }
+
+__device__ inline void grid_barrier(GridBar& gb) { grid_barrier_t<false>(gb); }
+__device__ inline void grid_barrier_wt(GridBar& gb) { grid_barrier_t<true>(gb); }
 
 // XCD of the running workgroup (hardware register XCC_ID, bits 3:0), and
 // after xcd_register the number of the launch's workgroups on it, the number

@@ -576,28 +576,6 @@ struct CamSolveArgs {
   int64_t lr_step0, lr_total, adam_step0;
 };
 
-// Rotation of the parameters p0 held by lanes 0..5 of the wavefront, stored
-// by lanes 0..8 at rot[c] (written through to memory if WTS).
-template <bool WTS>
-__device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float p0, int lane) {
-  double a1[3], a2[3], R[3][3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    a1[j] = (double)__shfl(p0, j);
-    a2[j] = (double)__shfl(p0, 3 + j);
-  }
-  gs_matrix(gs_forward(a1, a2), R);
-  if (lane < 9) {
-    double rv = R[0][0];
-#pragma unroll
-    for (int j = 1; j < 9; ++j) rv = (lane == j) ? R[j / 3][j % 3] : rv;
-    if constexpr (WTS)
-      store_wt(&rot[c * 9 + lane], rv);
-    else
-      rot[c * 9 + lane] = rv;
-  }
-}
-
 // Gram-Schmidt of the parameters p0 held by lanes 0..5 of the wavefront (a2
 // receives the second column's parameters).
 __device__ inline Gs cam_gs(float p0, double a2[3]) {
@@ -625,6 +603,14 @@ __device__ inline void cam_store_gs(double* __restrict__ rot, int64_t c, const G
     else
       rot[c * 9 + lane] = rv;
   }
+}
+
+// Rotation of the parameters p0 held by lanes 0..5 of the wavefront, stored
+// by lanes 0..8 at rot[c] (written through to memory if WTS).
+template <bool WTS>
+__device__ inline void cam_store_rot(double* __restrict__ rot, int64_t c, float p0, int lane) {
+  double a2[3];
+  cam_store_gs<WTS>(rot, c, cam_gs(p0, a2), lane);
 }
 
 template <typename WT, bool XS>
