@@ -219,6 +219,17 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
   const int64_t NR = (int64_t)a.N * 9;
   for (int64_t c = gwave; c < a.N; c += nwaves) fo_store_rot<false>(a.rot, c, a.params[c * 9 + kq], lane);
   grid_barrier(gb);
+  // static data of the first 64 incidence entries of this wavefront's first
+  // camera (one per lane: the entry and both cameras), read once
+  int item0 = 0, ci0 = 0, cj0 = 0;
+  if (gwave < a.N) {
+    const int lo = a.cam_ptr[gwave], hi = a.cam_ptr[gwave + 1];
+    if (lo + lane < hi) {
+      item0 = a.cam_items[lo + lane];
+      ci0 = a.cams[2 * (item0 >> 1)];
+      cj0 = a.cams[2 * (item0 >> 1) + 1];
+    }
+  }
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
@@ -244,10 +255,13 @@ __global__ __launch_bounds__(kSolveBlock) void k_fo_solve(FoSolveArgs a) {
 #pragma unroll
       for (int j = 0; j < 12; ++j) acc[j] = 0.0;
       for (int q = lo + lane; q < hi; q += 64) {
-        const int item = a.cam_items[q];
+        // the lane's first entry of the wavefront's first camera from
+        // registers (read once per launch), the others from memory
+        const bool cached = c == gwave && q == lo + lane;
+        const int item = cached ? item0 : a.cam_items[q];
         const int64_t n = item >> 1;
         const int side = item & 1;
-        const int ci = a.cams[2 * n], cj = a.cams[2 * n + 1];
+        const int ci = cached ? ci0 : a.cams[2 * n], cj = cached ? cj0 : a.cams[2 * n + 1];
         double Ri[3][3], Rj[3][3], ti[3], tj[3];
 #pragma unroll
         for (int e = 0; e < 9; ++e) {

@@ -287,6 +287,24 @@ struct RaCamArgs {
   int64_t lr_step0, lr_total, adam_step0;
 };
 
+// Static data of one incidence entry: the entry (pair << 1 | side), both
+// cameras and the pair's relative rotation.
+struct RaEntry {
+  int item, ci, cj;
+  float q[9];
+};
+
+__device__ inline RaEntry ra_entry(const RaCamArgs& a, int q) {
+  RaEntry e;
+  e.item = a.cam_items[q];
+  const int64_t n = e.item >> 1;
+  e.ci = a.cams[2 * n];
+  e.cj = a.cams[2 * n + 1];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) e.q[k] = a.Rrel[9 * n + k];
+  return e;
+}
+
 __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
   GridBar gb = grid_bar(a.bar);
   __shared__ double lds[kSolveBlock / 64];
@@ -299,6 +317,13 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
   // rotations of the initial parameters (buffer 0)
   for (int64_t c = gwave; c < a.N; c += nwaves) ra_store_rot(a.rot, c, a.params[6 * c + kq], 0, lane, true);
   grid_barrier(gb);
+  // static data of the first 64 incidence entries of this wavefront's first
+  // camera (one per lane), read once for the launch
+  RaEntry e0{};
+  if (gwave < a.N) {
+    const int lo = a.cam_ptr[gwave], hi = a.cam_ptr[gwave + 1];
+    if (lo + lane < hi) e0 = ra_entry(a, lo + lane);
+  }
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
@@ -320,14 +345,19 @@ __global__ __launch_bounds__(kSolveBlock) void k_ra_solve_cam(RaCamArgs a) {
 #pragma unroll
       for (int j = 0; j < 12; ++j) acc[j] = 0.0;
       for (int q = lo + lane; q < hi; q += 64) {
-        const int item = a.cam_items[q];
-        const int64_t n = item >> 1;
-        const int side = item & 1;
+        // the lane's first entry of the wavefront's first camera from
+        // registers (read once per launch), the others from memory
+        RaEntry e;
+        if (c == gwave && q == lo + lane)
+          e = e0;
+        else
+          e = ra_entry(a, q);
+        const int side = e.item & 1;
         double Ri[3][3], Rj[3][3];
-        load_rot(rr, a.cams[2 * n], Ri);
-        load_rot(rr, a.cams[2 * n + 1], Rj);
+        load_rot(rr, e.ci, Ri);
+        load_rot(rr, e.cj, Rj);
         float rec[24];
-        const double d = ra_pair(Ri, Rj, a.Rrel + 9 * n, a.invP, rec);
+        const double d = ra_pair(Ri, Rj, e.q, a.invP, rec);
         if (side == 0) lsum += d;   // each pair's term once, from its first camera
 #pragma unroll
         for (int j = 0; j < 12; ++j) acc[j] += (double)(side ? rec[12 + j] : rec[j]);

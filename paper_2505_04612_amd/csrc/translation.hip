@@ -369,14 +369,34 @@ struct TaCamArgs {
   int64_t lr_step0, lr_total, adam_step0;
 };
 
+// Static data of one incidence entry: the entry (pair << 1 | side), both
+// cameras and the pair's direction.
+struct TaEntry {
+  int item, ci, cj;
+  float d[3];
+};
+
+__device__ inline TaEntry ta_entry(const TaCamArgs& a, int q) {
+  TaEntry e;
+  e.item = a.cam_items[q];
+  const int64_t n = e.item >> 1;
+  e.ci = a.cams[2 * n];
+  e.cj = a.cams[2 * n + 1];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) e.d[k] = a.dirs[3 * n + k];
+  return e;
+}
+
 // One camera for runs r0 .. r0 + G - 1 (G <= 4, so the 3G sums fit the
-// 12-value wave reduction).  `wl` (the wavefront's loss row in LDS, or NULL)
+// 12-value wave reduction).  With `cached`, the lane's first entry of the
+// camera is `e0` (read once per launch), so that pass's centre loads depend
+// on registers only.  `wl` (the wavefront's loss row in LDS, or NULL)
 // gathers the L1 terms of the pairs whose first camera this is, so each
 // pair's term is counted once.
 template <int G>
 __device__ inline void ta_cam_group(const TaCamArgs& a, const float* __restrict__ pr, float* __restrict__ pw,
                                     int64_t c, int lo, int hi, int lane, int r0, double lr, double bc1, double bc2,
-                                    double* wl) {
+                                    double* wl, bool cached, const TaEntry& e0) {
   const int64_t run_stride = (int64_t)a.N * 3;
   // this lane's own coordinate (lanes past 3G repeat the last one)
   const int l3 = lane < 3 * G ? lane : 3 * G - 1;
@@ -389,11 +409,15 @@ __device__ inline void ta_cam_group(const TaCamArgs& a, const float* __restrict_
 #pragma unroll
   for (int g = 0; g < G; ++g) ls[g] = 0.0;
   for (int q = lo + lane; q < hi; q += 64) {
-    const int item = a.cam_items[q];
-    const int64_t n = item >> 1;
-    const int ci = a.cams[2 * n], cj = a.cams[2 * n + 1];
+    TaEntry e;
+    if (cached && q == lo + lane)
+      e = e0;
+    else
+      e = ta_entry(a, q);
+    const int item = e.item, ci = e.ci, cj = e.cj;
     double d[3];
-    load_dir(a.dirs, n, d);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = (double)e.d[k];
     float oi[G][3], oj[G][3];
 #pragma unroll
     for (int g = 0; g < G; ++g)
@@ -445,6 +469,13 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
   const int64_t gwave = gtid >> 6, nwaves = gsize >> 6;
   const int64_t RS = (int64_t)a.runs * a.part_stride;
   double* wl = a.trace ? wloss[wv] : nullptr;
+  // static data of the first 64 incidence entries of this wavefront's first
+  // camera (one per lane), read once for the launch
+  TaEntry e0{0, 0, 0, {0.0f, 0.0f, 0.0f}};
+  if (gwave < a.N) {
+    const int lo = a.cam_ptr[gwave], hi = a.cam_ptr[gwave + 1];
+    if (lo + lane < hi) e0 = ta_entry(a, lo + lane);
+  }
   StepSched sch(a.log_frac, a.lr_step0, a.lr_total, a.adam_step0, a.b1, a.b2);
   for (int k = 0; k < a.K; ++k) {
     const int rb = k & 1;
@@ -459,12 +490,12 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
     for (int64_t c = gwave; c < a.N; c += nwaves) {
       const int lo = a.cam_ptr[c], hi = a.cam_ptr[c + 1];
       int r0 = 0;
-      for (; r0 + 4 <= a.runs; r0 += 4) ta_cam_group<4>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl);
+      for (; r0 + 4 <= a.runs; r0 += 4) ta_cam_group<4>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl, c == gwave, e0);
       if (r0 + 2 <= a.runs) {
-        ta_cam_group<2>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl);
+        ta_cam_group<2>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl, c == gwave, e0);
         r0 += 2;
       }
-      if (r0 < a.runs) ta_cam_group<1>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl);
+      if (r0 < a.runs) ta_cam_group<1>(a, pr, pw, c, lo, hi, lane, r0, lr, bc1, bc2, wl, c == gwave, e0);
     }
     if (a.trace) {
       __syncthreads();
