@@ -38,6 +38,23 @@ constexpr int kSolveBlock = 512;
 // per iteration: 512 threads 8.2, 256 7.1, 128 7.6 (more workgroups make
 // each grid barrier dearer).
 constexpr int kCamBlock = 256;
+
+// Workgroup size and count of a camera-by-camera loop compiled for up to
+// kSolveBlock threads (one wavefront per camera): kCamBlock-thread
+// workgroups while they fit one to a CU (the wavefronts then spread over
+// twice as many CUs: one per SIMD instead of two), else kSolveBlock-thread
+// workgroups up to `coop` co-resident (cameras strided beyond them).
+struct CamGrid {
+  int threads;
+  int64_t blocks;
+};
+inline CamGrid cam_grid(int64_t N, int64_t coop, int num_cu) {
+  const int64_t small = (N * 64 + kCamBlock - 1) / kCamBlock;
+  if (small <= num_cu) return CamGrid{kCamBlock, small > 0 ? small : 1};
+  int64_t b = (N * 64 + kSolveBlock - 1) / kSolveBlock;
+  if (b > coop) b = coop;
+  return CamGrid{kSolveBlock, b};
+}
 // Integer counters the IRLS pass spreads its kept-match counts over (one
 // 128-byte line each, so concurrent atomics rarely meet on one address).
 constexpr int kKeptSlots = 256;

@@ -396,8 +396,8 @@ extern "C" fm_status fm_epipolar_focal_solve(fm_ctx* ctx, fm_scene* s, const voi
   }
   // one wavefront per camera up to the co-resident limit (cameras strided
   // beyond it); two sets of loss partials
-  int64_t want = grid_for((int64_t)s->N * 64, kSolveBlock);
-  if (want > s->fo_coop_blocks) want = s->fo_coop_blocks;
+  const CamGrid cg = cam_grid(s->N, s->fo_coop_blocks, ctx->num_cu);
+  int64_t want = cg.blocks;
   if (2 * want > s->loss_part_cap) want = s->loss_part_cap / 2;
   if (want < 1) return fm_fail(ctx, FM_ECOOP, "fm_epipolar_focal_solve: no room for the loss partials");
   FoSolveArgs a;
@@ -413,9 +413,9 @@ extern "C" fm_status fm_epipolar_focal_solve(fm_ctx* ctx, fm_scene* s, const voi
   FM_HIP_TRY(ctx, fm_bar_reset(s->bar, st));
   fm_timed timer(ctx, FM_K_FO_SOLVE, st);
   hipError_t e = wdt == FM_F64 ? hipLaunchCooperativeKernel((const void*)k_fo_solve<double>, dim3((unsigned)want),
-                                                           dim3(kSolveBlock), args, 0, st)
+                                                           dim3(cg.threads), args, 0, st)
                                : hipLaunchCooperativeKernel((const void*)k_fo_solve<float>, dim3((unsigned)want),
-                                                           dim3(kSolveBlock), args, 0, st);
+                                                           dim3(cg.threads), args, 0, st);
   if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
   return FM_OK;
 }

@@ -836,8 +836,8 @@ extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rr
   // automatic grid: the camera loop, one wavefront per camera up to the
   // co-resident limit (faster at every size measured, up to the 5,000-camera
   // street graph with 185k pairs: 26.3 against 36.1 us per iteration)
-  int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
-  if (want_cam > s->ra_coop_blocks) want_cam = s->ra_coop_blocks;
+  const CamGrid cg = cam_grid(s->N, s->ra_coop_blocks, ctx->num_cu);
+  const int64_t want_cam = cg.blocks;
   if (cfg->blocks <= 0 && 2 * want_cam <= s->loss_part_cap) {
     RaCamArgs ca;
     ca.params = params; ca.alt = s->params_alt; ca.m = m; ca.v = v;
@@ -849,7 +849,7 @@ extern "C" fm_status fm_rotation_solve(fm_ctx* ctx, fm_scene* s, const float* Rr
     void* cargs[] = {&ca};
     fm_timed timer(ctx, FM_K_RA_SOLVE, st);
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_ra_solve_cam, dim3((unsigned)want_cam),
-                                              dim3(kSolveBlock), cargs, 0, st);
+                                              dim3(cg.threads), cargs, 0, st);
     if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
     return FM_OK;
   }

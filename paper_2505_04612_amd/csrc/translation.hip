@@ -501,7 +501,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_ta_solve_cam(TaCamArgs a) {
       __syncthreads();
       if ((int)threadIdx.x < a.runs) {
         double t = 0.0;
-        for (int w = 0; w < kSolveBlock / 64; ++w) t += wloss[w][threadIdx.x];
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wloss[w][threadIdx.x];
         store_wt(&a.part[rb * RS + threadIdx.x * a.part_stride + blockIdx.x], t);
       }
     }
@@ -782,8 +782,8 @@ extern "C" fm_status fm_translation_solve(fm_ctx* ctx, fm_scene* s, const float*
     // pair term, this one is cheap enough to evaluate twice at any size
     // measured: on the 5,000-camera street graph (185k pairs) 24.0 against
     // 27.3 us per iteration for 4 runs
-    int64_t want_cam = grid_for((int64_t)s->N * 64, kSolveBlock);
-    if (want_cam > s->ta_coop_blocks) want_cam = s->ta_coop_blocks;
+    const CamGrid cg = cam_grid(s->N, s->ta_coop_blocks, ctx->num_cu);
+    int64_t want_cam = cg.blocks;
     if (want_cam > s->ta_part_cap) want_cam = s->ta_part_cap;
     TaCamArgs ca;
     ca.centres = centres; ca.alt = s->ta_alt; ca.m = m; ca.v = v;
@@ -795,7 +795,7 @@ extern "C" fm_status fm_translation_solve(fm_ctx* ctx, fm_scene* s, const float*
     void* cargs[] = {&ca};
     fm_timed timer(ctx, FM_K_TA_SOLVE, st);
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_ta_solve_cam, dim3((unsigned)want_cam),
-                                              dim3(kSolveBlock), cargs, 0, st);
+                                              dim3(cg.threads), cargs, 0, st);
     if (e != hipSuccess) return fm_fail(ctx, FM_ECOOP, "cooperative launch failed: %s", hipGetErrorString(e));
     return FM_OK;
   }
