@@ -32,11 +32,13 @@ constexpr int kBlock = 256;
 // Threads per workgroup of the persistent solve (eight wavefronts: fewer,
 // larger workgroups make its grid barriers cheaper).
 constexpr int kSolveBlock = 512;
-// Threads per workgroup of the epipolar camera loop: four wavefronts, so
-// that the loop's wavefronts (one per camera, two per SIMD at its register
-// use) spread over twice as many CUs as with eight.  Medium helix scene, µs
-// per iteration: 512 threads 8.2, 256 7.1, 128 7.6 (more workgroups make
-// each grid barrier dearer).
+// Threads per workgroup of the camera loops (the epipolar one always, the
+// translation, rotation and focal ones while a workgroup per CU suffices):
+// four wavefronts, so that the loops' wavefronts (one per camera) spread
+// over twice as many CUs as with eight.  Medium helix scene, µs per
+// iteration of the epipolar loop: 512 threads 8.2, 256 7.1, 128 7.6 (more
+// workgroups make each grid barrier dearer); translation (4 runs) 5.20 ->
+// 4.63, rotation 6.08 -> 5.05, focal 9.39 -> 7.34 going from 512 to 256.
 constexpr int kCamBlock = 256;
 
 // Workgroup size and count of a camera-by-camera loop compiled for up to
