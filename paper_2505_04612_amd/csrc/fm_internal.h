@@ -222,57 +222,12 @@ __device__ inline void gs_matrix(const Gs& g, double R[3][3]) {
   }
 }
 
-// Reads of arrays that other workgroups write while a persistent launch
-// runs, between two grid_sync calls (SH = true): buffer loads with the sc0
-// cache policy, which bypass the CU's L1 (grid_sync does not invalidate the
-// L1s) and are served by the XCD's L2, which grid_sync writes back and
-// invalidates once per XCD.  Byte offsets are 32-bit: arrays below 2 GiB.
-// SH = false: plain loads.
-constexpr int kBufWord3 = 0x00020000;   // buffer resource word 3 for raw loads on gfx9
-constexpr int kSc0 = 1;                 // cache-policy bits of the buffer-load builtins: sc0
-
-template <bool SH, typename T>
-struct Arr;
-
-template <typename T>
-struct Arr<false, T> {
-  const T* p;
-  __device__ explicit Arr(const T* q) : p(q) {}
-  __device__ T operator[](int64_t i) const { return p[i]; }
-  __device__ float4 f4(int64_t i) const { return reinterpret_cast<const float4*>(p + i)[0]; }
-  __device__ float2 f2(int64_t i) const { return reinterpret_cast<const float2*>(p + i)[0]; }
-};
-
-template <typename T>
-struct Arr<true, T> {
-  __amdgpu_buffer_rsrc_t r;
-  __device__ explicit Arr(const T* q)
-      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q), 0, 0x7fffffff, kBufWord3)) {}
-  __device__ T operator[](int64_t i) const {
-    const int off = (int)(i * (int64_t)sizeof(T));
-    if constexpr (sizeof(T) == 4)
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kSc0));
-    else
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kSc0));
-  }
-  // 16 bytes from element i on (16-byte aligned)
-  __device__ float4 f4(int64_t i) const {
-    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)(i * (int64_t)sizeof(T)), 0, kSc0));
-  }
-  // 8 bytes from element i on (8-byte aligned)
-  __device__ float2 f2(int64_t i) const {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(i * (int64_t)sizeof(T)), 0, kSc0));
-  }
-};
-
-template <bool SH = false>
 __device__ inline void load_pose(const float* params, int c, double a1[3], double a2[3], double t[3]) {
-  const Arr<SH, float> p(params);
   const int64_t b = (int64_t)c * 9;
   for (int k = 0; k < 3; ++k) {
-    a1[k] = (double)p[b + k];
-    a2[k] = (double)p[b + 3 + k];
-    t[k] = (double)p[b + 6 + k];
+    a1[k] = (double)params[b + k];
+    a2[k] = (double)params[b + 3 + k];
+    t[k] = (double)params[b + 6 + k];
   }
 }
 
@@ -447,12 +402,10 @@ __device__ inline void rs_stage_d(const double (&in)[S], double (&out)[(S + 1) /
   }
 }
 
-// Adds one side (12 floats) of a pair record to acc (SH: see Arr).
-template <bool SH = false>
+// Adds one side (12 floats) of a pair record to acc.
 __device__ inline void add_record(const float* __restrict__ contrib, int item, double acc[12]) {
-  const Arr<SH, float> c(contrib);
-  const int64_t b = (int64_t)(item >> 1) * 24 + (item & 1) * 12;
-  const float4 r0 = c.f4(b), r1 = c.f4(b + 4), r2 = c.f4(b + 8);
+  const float4* c = reinterpret_cast<const float4*>(contrib + (int64_t)(item >> 1) * 24 + (item & 1) * 12);
+  const float4 r0 = c[0], r1 = c[1], r2 = c[2];
   acc[0] += r0.x; acc[1] += r0.y; acc[2] += r0.z; acc[3] += r0.w;
   acc[4] += r1.x; acc[5] += r1.y; acc[6] += r1.z; acc[7] += r1.w;
   acc[8] += r2.x; acc[9] += r2.y; acc[10] += r2.z; acc[11] += r2.w;
@@ -533,15 +486,14 @@ __device__ inline void row_sum12(double acc[12], int lane) {
 }
 
 // Summed records of one camera in every lane of its row.
-template <bool SH = false>
 __device__ inline void row_camera_sums(const RowList& L, const int32_t* __restrict__ cam_items,
                                        const float* __restrict__ contrib, int lane, double acc[12]) {
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
-    if (L.it[j] >= 0) add_record<SH>(contrib, L.it[j], acc);
-  for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record<SH>(contrib, cam_items[q], acc);
+    if (L.it[j] >= 0) add_record(contrib, L.it[j], acc);
+  for (int q = L.lo + 64 + (lane & 15); q < L.hi; q += 16) add_record(contrib, cam_items[q], acc);
   row_sum12(acc, lane);
 }
 
@@ -820,15 +772,19 @@ __device__ inline XcdSync xcd_register(GridBar& gb) {
 }
 
 // Grid barrier for loops whose data shared between workgroups is written
-// with plain stores and read through Arr<true, T> (sc0 loads: L1 bypassed,
-// served by the XCD's L2).  Cache maintenance runs once per XCD instead of
-// once per workgroup: each thread waits for its own stores to reach the L2;
-// the workgroups of an XCD count in on the XCD's counter; the last of them
+// with plain stores.  The L2 write-back runs once per XCD instead of once
+// per workgroup: each thread waits for its own stores to reach the L2; the
+// workgroups of an XCD count in on the XCD's counter; the last of them
 // writes the XCD's L2 back (agent-scope release), counts the XCD in on the
 // top-level counter and waits for every XCD to have arrived, invalidates the
 // XCD's L2 (agent-scope acquire; complete before it moves on) and moves the
-// XCD's generation word, which the XCD's other workgroups wait for.  As in
-// grid_barrier, counts and generations only grow within a launch.
+// XCD's generation word, which the XCD's other workgroups wait for.  Each of
+// those then acquires too: that invalidates its CU's L1, which may still hold
+// lines it read before the barrier (loads of group scope, sc0, are served
+// from the L1 as plain ones are, and an L1 invalidation of group scope does
+// nothing in a workgroup that is not split across CUs; only the agent-scope
+// invalidation clears it).  As in grid_barrier, counts and generations only
+// grow within a launch.
 __device__ inline void grid_sync(unsigned* __restrict__ bar, XcdSync& xs) {
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   unsigned f = 0u;
@@ -847,6 +803,7 @@ __device__ inline void grid_sync(unsigned* __restrict__ bar, XcdSync& xs) {
       __hip_atomic_store(xg, xs.gnext, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       bar_reach(bar, xg, xs.gnext);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
   xs.lnext += xs.nx;

@@ -26,36 +26,32 @@ __device__ inline double load_w(const WT* p, int k) {
 // Loss term of pair n and what its adjoint needs: E_n at the current poses
 // (`rot`, optional, holds each camera's rotation from Gram-Schmidt of the
 // current parameters, so pairs need not repeat it) and g = W_n e_n, in
-// float64.  SH: parameters and rotations are read through Arr<true, T> (the
-// persistent loops, where other workgroups wrote them since the last
-// grid_sync); the Gram is constant.
+// float64.
 struct PairEval {
   double Ri[3][3], Rj[3][3], Rij[3][3], th[3], ti[3], g[3][3];
   double ns, loss;
 };
 
-template <typename WT, bool SH>
+template <typename WT>
 __device__ inline PairEval pair_eval(const float* __restrict__ params, const double* __restrict__ rot, int ci, int cj,
                                      const WT* __restrict__ W36, int64_t n) {
   PairEval e;
   double a1[3], a2[3], tj[3], E[3][3];
   if (rot) {
-    const Arr<SH, float> P(params);
-    const Arr<SH, double> R(rot);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      e.ti[k] = (double)P[(int64_t)ci * 9 + 6 + k];
-      tj[k] = (double)P[(int64_t)cj * 9 + 6 + k];
+      e.ti[k] = (double)params[(int64_t)ci * 9 + 6 + k];
+      tj[k] = (double)params[(int64_t)cj * 9 + 6 + k];
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      e.Ri[k / 3][k % 3] = R[(int64_t)ci * 9 + k];
-      e.Rj[k / 3][k % 3] = R[(int64_t)cj * 9 + k];
+      e.Ri[k / 3][k % 3] = rot[(int64_t)ci * 9 + k];
+      e.Rj[k / 3][k % 3] = rot[(int64_t)cj * 9 + k];
     }
   } else {
-    load_pose<SH>(params, ci, a1, a2, e.ti);
+    load_pose(params, ci, a1, a2, e.ti);
     gs_matrix(gs_forward(a1, a2), e.Ri);
-    load_pose<SH>(params, cj, a1, a2, tj);
+    load_pose(params, cj, a1, a2, tj);
     gs_matrix(gs_forward(a1, a2), e.Rj);
   }
   e.ns = pair_essential(e.Ri, e.ti, e.Rj, tj, e.Rij, e.th, E);
@@ -89,11 +85,11 @@ __device__ inline PairEval pair_eval(const float* __restrict__ params, const dou
 
 // Loss term and adjoint record of pair n.  rec = [dL/dR_i (3x3 row-major),
 // dL/dt_i, dL/dR_j, dL/dt_j] as float32.
-template <typename WT, bool SH = false>
+template <typename WT>
 __device__ inline double pair_loss_adjoint(const float* __restrict__ params, const double* __restrict__ rot, int ci,
                                            int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
                                            float* __restrict__ rec) {
-  const PairEval e = pair_eval<WT, SH>(params, rot, ci, cj, W36, n);
+  const PairEval e = pair_eval<WT>(params, rot, ci, cj, W36, n);
   if (!(e.ns > 0.0)) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) rec[k] = 0.0f;
@@ -112,11 +108,11 @@ __device__ inline double pair_loss_adjoint(const float* __restrict__ params, con
 // Loss term of pair n and its adjoint in the fused loops' compact form
 // (essential_adjoint_omega): om, dL/dt_i, dL/dt_j (all 0 for a degenerate
 // pair).
-template <typename WT, bool SH>
+template <typename WT>
 __device__ inline double pair_loss_omega(const float* __restrict__ params, const double* __restrict__ rot, int ci,
                                          int cj, const WT* __restrict__ W36, int64_t n, double two_inv_Z,
                                          double om[3], double dti[3], double dtj[3]) {
-  const PairEval e = pair_eval<WT, SH>(params, rot, ci, cj, W36, n);
+  const PairEval e = pair_eval<WT>(params, rot, ci, cj, W36, n);
   if (!(e.ns > 0.0)) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) om[k] = dti[k] = dtj[k] = 0.0;
@@ -134,8 +130,8 @@ __device__ inline double pair_loss_omega(const float* __restrict__ params, const
 // Pair phase over pairs [first, P) with stride `stride`; writes the records
 // and returns this thread's loss sum (float64, in pair order).  The cameras
 // of the first two pairs come in registers (ci0, cj0 and ci1, cj1), read
-// once per solve.  SH: the poses are read through Arr<true, T>.
-template <typename WT, bool SH = false>
+// once per solve.
+template <typename WT>
 __device__ inline double pair_phase(const float* params, const double* rot, const int32_t* cams, const WT* W36,
                                     int64_t P, double two_inv_Z, float* contrib, int64_t first, int64_t stride,
                                     int ci0, int cj0, int ci1 = 0, int cj1 = 0) {
@@ -144,7 +140,7 @@ __device__ inline double pair_phase(const float* params, const double* rot, cons
     float rec[24];
     const bool held0 = n == first, held1 = n == first + stride;
     const int ci = held0 ? ci0 : (held1 ? ci1 : cams[2 * n]), cj = held0 ? cj0 : (held1 ? cj1 : cams[2 * n + 1]);
-    sum += pair_loss_adjoint<WT, SH>(params, rot, ci, cj, W36, n, two_inv_Z, rec);
+    sum += pair_loss_adjoint<WT>(params, rot, ci, cj, W36, n, two_inv_Z, rec);
     float4* dst = reinterpret_cast<float4*>(contrib + n * 24);
 #pragma unroll
     for (int k = 0; k < 6; ++k) dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
@@ -158,7 +154,7 @@ __device__ inline double pair_phase(const float* params, const double* rot, cons
 // at contrib + 6 q, so a camera's records are one contiguous run.  Pair phase
 // as above, each side written to its slot (qi0, qj0 and qi1, qj1: slots of
 // the first two pairs, held in registers).
-template <typename WT, bool SH>
+template <typename WT>
 __device__ inline double pair_phase_slots(const float* params, const double* rot, const int32_t* cams,
                                           const int32_t* pair_slot, const WT* W36, int64_t P, double two_inv_Z,
                                           float* contrib, int64_t first, int64_t stride, int ci0, int cj0, int ci1,
@@ -170,7 +166,7 @@ __device__ inline double pair_phase_slots(const float* params, const double* rot
     const int qi = held0 ? qi0 : (held1 ? qi1 : pair_slot[2 * n]);
     const int qj = held0 ? qj0 : (held1 ? qj1 : pair_slot[2 * n + 1]);
     double om[3], dti[3], dtj[3];
-    sum += pair_loss_omega<WT, SH>(params, rot, ci, cj, W36, n, two_inv_Z, om, dti, dtj);
+    sum += pair_loss_omega<WT>(params, rot, ci, cj, W36, n, two_inv_Z, om, dti, dtj);
     float2* di = reinterpret_cast<float2*>(contrib + (int64_t)qi * 6);
     float2* dj = reinterpret_cast<float2*>(contrib + (int64_t)qj * 6);
     di[0] = make_float2((float)-om[0], (float)-om[1]);
@@ -400,10 +396,10 @@ constexpr int kRowItems = 6;
 // lo + l16 + 16 j; the first NE of them are all loaded before any is added
 // (so their loads are in flight together), then added in slot order, then
 // the rest.  acc = (om, dL/dt) of the camera.
-template <bool SH, int NE>
+template <int NE>
 __device__ inline void row_camera_sums_slots(int lo, int hi, const float* __restrict__ contrib, int lane,
                                              double (&acc)[6]) {
-  const Arr<SH, float> c(contrib);
+  const float2* c = reinterpret_cast<const float2*>(contrib);
   const int l16 = lane & 15;
   float2 r[NE][3];
 #pragma unroll
@@ -411,9 +407,9 @@ __device__ inline void row_camera_sums_slots(int lo, int hi, const float* __rest
     r[j][0] = r[j][1] = r[j][2] = make_float2(0.0f, 0.0f);
     const int q = lo + l16 + 16 * j;
     if (q < hi) {
-      r[j][0] = c.f2((int64_t)q * 6);
-      r[j][1] = c.f2((int64_t)q * 6 + 2);
-      r[j][2] = c.f2((int64_t)q * 6 + 4);
+      r[j][0] = c[(int64_t)q * 3];
+      r[j][1] = c[(int64_t)q * 3 + 1];
+      r[j][2] = c[(int64_t)q * 3 + 2];
     }
   }
 #pragma unroll
@@ -424,15 +420,15 @@ __device__ inline void row_camera_sums_slots(int lo, int hi, const float* __rest
     acc[3] += r[j][1].y; acc[4] += r[j][2].x; acc[5] += r[j][2].y;
   }
   for (int q = lo + 16 * NE + l16; q < hi; q += 16) {
-    const float2 a0 = c.f2((int64_t)q * 6), a1 = c.f2((int64_t)q * 6 + 2), a2 = c.f2((int64_t)q * 6 + 4);
+    const float2 a0 = c[(int64_t)q * 3], a1 = c[(int64_t)q * 3 + 1], a2 = c[(int64_t)q * 3 + 2];
     acc[0] += a0.x; acc[1] += a0.y; acc[2] += a1.x;
     acc[3] += a1.y; acc[4] += a2.x; acc[5] += a2.y;
   }
   row_sum6(acc, lane);
 }
 
-// Grid barrier of the fused loops: per-XCD (grid_sync, with the shared
-// arrays read through Arr<true, T>) or flat (grid_barrier, plain reads).
+// Grid barrier of the fused loops: per-XCD (grid_sync) or flat
+// (grid_barrier).
 template <bool XS>
 __device__ inline void loop_sync(GridBar& gb, XcdSync& xs) {
   if constexpr (XS)
@@ -469,7 +465,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
   for (int k = 0; k < a.K; ++k) {
     // iteration 0 runs Gram-Schmidt per pair; later iterations read the
     // rotations the camera phase stored with the updated parameters
-    const double v = pair_phase_slots<WT, XS>(a.params, k > 0 ? a.rot : nullptr, a.cams, a.pair_slot, W36, a.P,
+    const double v = pair_phase_slots<WT>(a.params, k > 0 ? a.rot : nullptr, a.cams, a.pair_slot, W36, a.P,
                                                 2.0 * iz, a.contrib, gtid, gsize, ci0, cj0, ci1, cj1, qi0, qj0, qi1,
                                                 qj1);
     const double t = block_sum(v, lds);
@@ -477,8 +473,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
     loop_sync<XS>(gb, xs);
     if (a.loss_trace && gtid == 0) {
       double s = 0.0;
-      const Arr<XS, double> lp(a.loss_part);
-      for (int b = 0; b < (int)gridDim.x; ++b) s += lp[b];
+      for (int b = 0; b < (int)gridDim.x; ++b) s += a.loss_part[b];
       a.loss_trace[k] = s * iz;
     }
     const double frac = sch.frac;
@@ -494,7 +489,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
       float p0 = 0.0f, mq = 0.0f, vq = 0.0f;
       // (m, v: only this lane reads and writes them during the launch)
       if (live && l16 < 9) {
-        p0 = Arr<XS, float>(a.params)[c * 9 + l16];
+        p0 = a.params[c * 9 + l16];
         mq = a.m[c * 9 + l16];
         vq = a.v[c * 9 + l16];
       }
@@ -513,7 +508,7 @@ __global__ __launch_bounds__(kSolveBlock) void k_solve(SolveArgs a) {
       }
       if (!live) a1[0] = a2[1] = 1.0;
       const Gs f = gs_forward(a1, a2);
-      row_camera_sums_slots<XS, kRowItems>(lo, hi, a.contrib, lane, acc6);
+      row_camera_sums_slots<kRowItems>(lo, hi, a.contrib, lane, acc6);
       omega_grad(f, acc6, acc6 + 3, acc);
       gs_adjoint(acc, f, a2, g);
       // lanes 0..8 of the row update one parameter each
@@ -696,7 +691,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
         for (int j = 0; j < 3; ++j) a2[j] = a2_own[j];
         f = f_own;
       } else {
-        p0 = Arr<XS, float>(pr)[c * 9 + kq];
+        p0 = pr[c * 9 + kq];
         mq = a.m[c * 9 + kq];
         vq = a.v[c * 9 + kq];
         f = cam_gs(p0, a2);
@@ -713,7 +708,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
         const int side = first ? side0 : item & 1;
         const int ci = first ? ci0 : a.cams[2 * n], cj = first ? cj0 : a.cams[2 * n + 1];
         double om[3], dti[3], dtj[3];
-        const double l = pair_loss_omega<WT, XS>(pr, rr, ci, cj, W36, n, 2.0 * iz, om, dti, dtj);
+        const double l = pair_loss_omega<WT>(pr, rr, ci, cj, W36, n, 2.0 * iz, om, dti, dtj);
         if (side == 0) lsum += l;   // each pair's loss once, from its first camera
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -764,8 +759,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
       grid_barrier_wt(gb);
     if (a.loss_trace && gtid == 0) {
       double sum = 0.0;
-      const Arr<XS, double> lp(a.loss_part);
-      for (int b = 0; b < (int)gridDim.x; ++b) sum += lp[rb * gridDim.x + b];
+      for (int b = 0; b < (int)gridDim.x; ++b) sum += a.loss_part[rb * gridDim.x + b];
       a.loss_trace[k] = sum * iz;
     }
   }
@@ -777,7 +771,7 @@ __global__ __launch_bounds__(kCamBlock) void k_solve_cam(CamSolveArgs a) {
   // after an odd number of iterations the latest parameters are in buffer 1
   if (a.K & 1) {
     for (int64_t c = gwave; c < a.N; c += nwaves)
-      if (lane < 9) a.params[c * 9 + lane] = Arr<XS, float>(a.params_alt)[c * 9 + lane];
+      if (lane < 9) a.params[c * 9 + lane] = a.params_alt[c * 9 + lane];
   }
 }
 
