@@ -341,9 +341,9 @@ def test_fused_solve_grid_invariance(fm, ctx, name):
     after K iterations are bit-identical for any number of workgroups (1 to
     beyond the automatic choice): every grid barrier must publish every
     workgroup's records and poses before the next phase reads them.  Grids
-    of 128 workgroups and more synchronise per XCD (one L2 write-back and
-    invalidation per XCD, shared arrays read past the L1), smaller ones with
-    the flat barrier, so the comparison also pins one against the other."""
+    of 128 workgroups and more synchronise per XCD (one L2 write-back per
+    XCD, an acquire in every workgroup), smaller ones with the flat
+    barrier, so the comparison also pins one against the other."""
     sc = scene(name)
     s = _scene_on_gpu(fm, ctx, sc, torch.float64 if name == "tiny" else torch.float32)
     W64, _ = fm.build_pair_grams(s)
@@ -359,6 +359,49 @@ def test_fused_solve_grid_invariance(fm, ctx, name):
     assert s.barrier_failures() == 0
     for blocks, p, m, v in results[1:]:
         assert torch.equal(p, results[0][1]) and torch.equal(m, results[0][2]) and torch.equal(v, results[0][3]), blocks
+
+
+def test_camera_loop_per_xcd_barrier_follows_oracle_steps(fm, ctx):
+    """The camera loop on the differential-precision scene: 1,000 cameras
+    make 250 workgroups of four wavefronts, so its grid barrier is the
+    per-XCD one, and every wavefront re-reads its neighbours' poses each
+    iteration.  Two runs of K fused iterations are bit-identical, and they
+    equal K oracle Adam steps on the same Gram (loss trace and poses, the
+    bar of the tiny scene's step test).  A workgroup reading a neighbour's
+    pose from lines left in its CU's L1 before the barrier would break
+    both: the released workgroups must each make an agent-scope acquire."""
+    sc = scene("diffprec")
+    assert sc.num_cams == 1000 and sc.pairs.shape[0] < 131072    # camera loop, 250 workgroups
+    s = _scene_on_gpu(fm, ctx, sc, torch.bfloat16)
+    W64, _ = fm.build_pair_grams(s)
+    th = _theta(sc)
+    K = 20
+    inv_Z = 1.0 / sc.num_matches
+    runs = []
+    for _ in range(2):
+        p = torch.from_numpy(th.copy()).to(ctx.device)
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        trace = torch.empty(K, dtype=torch.float64, device=ctx.device)
+        fm.epipolar_solve(s, W64, p, m, v, K, 3e-3, 1e-2, 1e-3, 0, K, 0, inv_Z=inv_Z, loss_trace=trace)
+        runs.append((p, m, v, trace))
+    assert s.barrier_failures() == 0
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert torch.equal(a, b)
+    W = expand36(W64.cpu().numpy())
+    sched = ea.Schedule(iters=K, round_len=K, lr_rot=f32(3e-3), lr_t=f32(1e-2), lr_final_frac=f32(1e-3),
+                        beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-12))
+    tr = th.astype(np.float64)
+    mr, vr = np.zeros_like(tr), np.zeros_like(tr)
+    losses = []
+    for k in range(K):
+        L, g = ea.loss_grad(tr, sc.pairs, W, inv_Z)
+        losses.append(L)
+        tr, mr, vr = ea.adam_step(tr, g, mr, vr, k + 1, ea.lr_at(sched, k), sched.beta1, sched.beta2, sched.eps)
+    assert np.allclose(runs[0][3].cpu().numpy(), losses, rtol=1e-5)
+    rot, tra = ea.relative_pose_errors(runs[0][0].cpu().numpy().astype(np.float64), tr, sc.pairs)
+    print(f"diffprec camera loop vs oracle steps: rot max {rot.max():.3e} deg, t max {tra.max():.3e} deg", flush=True)
+    assert rot.max() < 1e-3 and tra.max() < 1e-2, (rot.max(), tra.max())
 
 
 @pytest.mark.parametrize("name,wdt", [("tiny", "f64"), ("medium", "f64"), ("medium", "f32")])
