@@ -450,7 +450,8 @@ def bench_mlp(ctx, M: int, reps: int = 20) -> dict:
     t_bwd = timed(lambda: api.mlp_backward(ctx, w, feats, act, dout, g))
     fl = 2.0 * 64 * 64
     return {
-        "kernels": "k_mlp_forward (64x64 layer on v_mfma_f32_16x16x32_f16), k_mlp_backward (dh1 on "
+        "kernels": "k_mlp_forward (64x64 layer on v_mfma_f32_16x16x32_f16, 64->1 layer on v_mfma_f32_16x16x16_f16), "
+                   "k_mlp_backward (dh1 on "
                    "v_mfma_f32_16x16x32_f16, dW2 on v_mfma_f32_16x16x16_f16) + k_mlp_reduce",
         "matches": M,
         "forward_us": t_fwd * 1e6, "forward_matches_per_s": M / t_fwd,

@@ -10,7 +10,9 @@
 //     forward's 64x64 layer, the backward's dh1 = dh2 W2): two per 16x16
 //     output tile;
 //   v_mfma_f32_16x16x16_f16: A[r][4q + j], B[4q + j][r]; used for the
-//     backward's dW2, whose contraction runs over a 16-match tile.
+//     backward's dW2, whose contraction runs over a 16-match tile, and for
+//     the forward's 64 -> 1 layer, whose operand B is the transposed 64x64
+//     layer's result as it stands (units along 4q + j, matches along r).
 // A tile is 16 matches; lanes r = 0..15 of each quarter q address one match
 // (operand A) or one output unit (result).
 #include <mutex>
@@ -60,10 +62,17 @@ __device__ inline void load_x(const float* feats, int64_t m, const MlpLds& s, fl
 
 // Blocks of 4 wavefronts walk the 16-match tiles in block-uniform steps (so
 // block barriers are safe); tile = step * 4 * gridDim + 4 * block + wave.
+// KEEP: also store each match's 128 FP16 activations to act (what the
+// backward reads back); the plain forward is instantiated without that code.
+template <bool KEEP>
 __global__ __launch_bounds__(256, 4) void k_mlp_forward(int64_t M, const float* __restrict__ feats, MlpPtrs w,
                                                      float out_scale, float* __restrict__ out,
                                                      _Float16* __restrict__ act) {
   __shared__ MlpLds s;
+  // per-wavefront staging of the kept activations: rows padded by 16 bytes,
+  // so that the 16 rows a store instruction touches start in different banks
+  constexpr int kTstRow = 2 * kHid + 8;
+  __shared__ __attribute__((aligned(16))) _Float16 Tst[4][16][kTstRow];
   load_lds(w, s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
@@ -75,6 +84,18 @@ __global__ __launch_bounds__(256, 4) void k_mlp_forward(int64_t M, const float* 
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
       for (int j = 0; j < 8; ++j) B[kk][nt][j] = (_Float16)w.W2[(16 * nt + r) * kHid + 32 * kk + 8 * q + j];
+  // output-layer operand A3[n][k] for units k of n-tile nt: row 0 holds W3
+  // (as float16 high and low parts, so the products keep float32
+  // precision), rows 1..15 are zero; lane (q, r) holds A3[r][4q + j]
+  h4 W3h[4], W3l[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float w3 = r == 0 ? w.W3[16 * nt + 4 * q + j] : 0.0f;
+      W3h[nt][j] = (_Float16)w3;
+      W3l[nt][j] = (_Float16)(w3 - (float)W3h[nt][j]);
+    }
   const int64_t ntiles = (M + 15) / 16;
   for (int64_t base = (int64_t)blockIdx.x * 4; base < ntiles; base += (int64_t)gridDim.x * 4) {
     const int64_t tile = base + wave;
@@ -92,44 +113,46 @@ __global__ __launch_bounds__(256, 4) void k_mlp_forward(int64_t M, const float* 
         const float z = fmaf(s.W1[3 * k], x[0], fmaf(s.W1[3 * k + 1], x[1], fmaf(s.W1[3 * k + 2], x[2], s.b1[k])));
         A[kk][j] = (_Float16)fmaxf(z, 0.0f);
       }
-    if (act && ok) {
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-        *reinterpret_cast<h8*>(act + m * 128 + 32 * kk + 8 * q) = A[kk];
-    }
-    f4 C[4];
+    // layer 2 transposed (W2 as operand A, the tile's layer-1 activations as
+    // operand B): C[nt][j] = z2 of unit 16 nt + 4q + j, match 16 tile + r,
+    // which after bias, ReLU and rounding to float16 is operand B of the
+    // output layer's 16x16x16 MFMA as it stands (units along 4q + j)
+    f4 Z = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    h4 h[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      C[nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      f4 C = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) C[nt] = mfma32(A[kk], B[kk][nt], C[nt]);
+      for (int kk = 0; kk < 2; ++kk) C = mfma32(B[kk][nt], A[kk], C);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[nt][j] = (_Float16)fmaxf(C[j] + s.b2[16 * nt + 4 * q + j], 0.0f);
+      Z = mfma16(W3h[nt], h[nt], Z);
+      Z = mfma16(W3l[nt], h[nt], Z);
     }
-    // C[nt][j] = z2 of match 16 tile + 4q + j, unit 16 nt + r
-    float part[4];
+    // the tile's activations (16 rows of 128 halves: one contiguous 4 KB
+    // block of act) through this wavefront's LDS rows, then written with
+    // consecutive 16-byte stores; LDS operations of a wavefront complete in
+    // order, the fences keep the compiler from reordering them
+    if constexpr (KEEP) {
+      _Float16* T = &Tst[wave][0][0];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t row = tile * 16 + 4 * q + j;
-      float acc = 0.0f;
+      for (int kk = 0; kk < 2; ++kk) *reinterpret_cast<h8*>(T + r * kTstRow + 32 * kk + 8 * q) = A[kk];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        const _Float16 h = (_Float16)fmaxf(C[nt][j] + s.b2[16 * nt + r], 0.0f);
-        if (act && row < M) act[row * 128 + 64 + 16 * nt + r] = h;
-        acc = fmaf(s.W3[16 * nt + r], (float)h, acc);
+      for (int nt = 0; nt < 4; ++nt) *reinterpret_cast<h4*>(T + r * kTstRow + 64 + 16 * nt + 4 * q) = h[nt];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = lane + 64 * i, row = c >> 4, col = 8 * (c & 15);
+        const int64_t mr = tile * 16 + row;
+        if (mr < M) *reinterpret_cast<h8*>(act + mr * 128 + col) = *reinterpret_cast<const h8*>(T + row * kTstRow + col);
       }
-      part[j] = acc;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) part[j] += __shfl_xor(part[j], o);
-    // the sigmoid once per lane, without divergence: lane r < 4 of each
-    // quarter takes row 4q + r (hardware 2^x and reciprocal, ~1 ulp each)
-    float zr = part[0];
-#pragma unroll
-    for (int j = 1; j < 4; ++j) zr = r == j ? part[j] : zr;
-    const int64_t orow = tile * 16 + 4 * q + r;
-    const float e = __builtin_amdgcn_exp2f(-(zr + s.b3) * kLog2e);
-    if (r < 4 && orow < M) out[orow] = out_scale * __builtin_amdgcn_rcpf(1.0f + e);
+    // Z[j] = row 4q + j of A3 H2^T: row 0 (lanes q = 0, register 0) is z3 of
+    // match 16 tile + r; the sigmoid on the hardware 2^x and reciprocal
+    // (~1 ulp each)
+    const float e = __builtin_amdgcn_exp2f(-(Z[0] + s.b3) * kLog2e);
+    if (q == 0 && ok) out[m] = out_scale * __builtin_amdgcn_rcpf(1.0f + e);
   }
 }
 
@@ -420,8 +443,12 @@ extern "C" fm_status fm_mlp_forward(fm_ctx* ctx, int64_t M, const float* feats, 
   // four workgroups of four wavefronts per CU: the forward kernel's register
   // use allows four wavefronts per SIMD, and its per-tile chain (feature load,
   // layer 1 from LDS, MFMA, epilogue) needs them to hide its latency
-  hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_blocks(ctx, M, 4)), dim3(256), 0, (hipStream_t)stream, M, feats, p,
-                     out_scale, out, (_Float16*)act);
+  if (act)
+    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(mlp_blocks(ctx, M, 4)), dim3(256), 0, (hipStream_t)stream, M, feats,
+                       p, out_scale, out, (_Float16*)act);
+  else
+    hipLaunchKernelGGL(k_mlp_forward<false>, dim3(mlp_blocks(ctx, M, 4)), dim3(256), 0, (hipStream_t)stream, M, feats,
+                       p, out_scale, out, (_Float16*)nullptr);
   FM_CHECK_LAUNCH(ctx);
   return FM_OK;
 }
