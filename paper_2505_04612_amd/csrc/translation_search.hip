@@ -109,7 +109,25 @@ __global__ __launch_bounds__(kTsBlock) void k_ts_search(const double* __restrict
     }
     __syncthreads();
     if (live) {
-      for (int c = slice; c < len; c += S) {
+      // four of this lane's candidates per step: their forms are independent
+      // chains, evaluated as one expression each (the same rounding as one
+      // at a time) and compared in candidate order (the same ties)
+      int c = slice;
+      for (; c + 3 * S < len; c += 4 * S) {
+        double q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* m = tile + 6 * (c + u * S);
+          q[u] = A6[0] * m[0] + A6[1] * m[1] + A6[2] * m[2] + A6[3] * m[3] + A6[4] * m[4] + A6[5] * m[5];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q[u] < best_v) {
+            best_v = q[u];
+            best_i = base + c + u * S;
+          }
+      }
+      for (; c < len; c += S) {
         const double* m = tile + 6 * c;
         const double q = A6[0] * m[0] + A6[1] * m[1] + A6[2] * m[2] + A6[3] * m[3] + A6[4] * m[4] + A6[5] * m[5];
         if (q < best_v) {
